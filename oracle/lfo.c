@@ -1,0 +1,456 @@
+/*
+ * lfo.c -- CPU oracle for Looking Forward track following (arXiv 2402.14670).
+ *
+ * TEST INFRASTRUCTURE ONLY (see lfo.h).  Plain single-threaded C: linear
+ * scans instead of binary searches, every triplet kept and fully sorted
+ * instead of a bounded selection, and the steps run in the paper's order.
+ * Every float expression below is binary32 and is evaluated exactly as
+ * written (C left-to-right association, no contraction).
+ *
+ * Readings of the paper where it is silent or garbled are marked [R..] and
+ * match the numbered list of readings kept with the design notes.
+ */
+#include "lfo.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static const int X_LAYERS[6] = {0, 3, 4, 7, 8, 11};
+static const int UV_LAYERS[6] = {1, 2, 5, 6, 9, 10};
+/* Triplet seeding layer sets: first x layer of T1/T2/T3, or last x layer
+ * (Triplet Seeding subsection). */
+static const int SEED_SETS[2][3] = {{0, 4, 8}, {3, 7, 11}};
+
+static int is_uv(int l) { int k = l & 3; return k == 1 || k == 2; }
+
+void lfo_default_params(lfo_params *p) {
+    memset(p, 0, sizeof(*p));
+    /* Table of parameters and tolerances, "Forward" column. */
+    p->T_triplet = 8.0f;
+    p->T_x = 2.0f;
+    p->T_uv_scale = 50.0f;       /* T_uv = 50 (tx + ty) */
+    p->T_uv_floor = 2.0f;        /* [R17] */
+    p->T_ty = 0.02f;
+    p->T_y = 800.0f;
+    p->T_Q = 0.5f;
+    p->n_hits_window = 32;
+    p->n_triplets = 12;
+    /* Search windows: x_tol = 150 mm + 2000 GeV/p; x_asym = 100 mm; u/v +-800 mm. */
+    p->xtol_const = 150.0f;
+    p->xtol_pscale = 2000.0f;
+    p->xasym = 100.0f;
+    p->uv_halfwidth = 800.0f;
+    /* Sagitta-like correction of the triplet middle hit. */
+    p->K_first = 1.00177513f;
+    p->K_last = 1.00142634f;
+    /* Magnet x-opening tolerance, 8..40 mm as a function of p and tx [R10]. */
+    p->magtol_const = 8.0f;
+    p->magtol_pscale = 24.0f;
+    p->magtol_txscale = 20.0f;
+    p->magtol_min = 8.0f;
+    p->magtol_max = 40.0f;
+    p->p_charge_cut = 5.0f;
+    /* C(n_hits) table. */
+    p->C_nhits[0] = 5.0f;
+    p->C_nhits[1] = 1.0f;
+    p->C_nhits[2] = 0.8f;
+    p->C_nhits[3] = 0.5f;
+}
+
+/* ---------------------------------------------------------------- */
+typedef struct {
+    const float *x, *z, *dxdy;     /* event-local hit arrays */
+    uint32_t begin[2 * LFO_NL];    /* event-local bucket bounds */
+    uint32_t end[2 * LFO_NL];
+} event_view;
+
+typedef struct { float chi2; int set, h0, h1, h2; } triplet;
+
+static int triplet_cmp(const void *pa, const void *pb) {
+    const triplet *a = (const triplet *)pa, *b = (const triplet *)pb;
+    /* [R13] ascending (chi2, set, h0, h2) */
+    if (a->chi2 < b->chi2) return -1;
+    if (a->chi2 > b->chi2) return 1;
+    if (a->set != b->set) return a->set < b->set ? -1 : 1;
+    if (a->h0 != b->h0) return a->h0 < b->h0 ? -1 : 1;
+    if (a->h2 != b->h2) return a->h2 < b->h2 ? -1 : 1;
+    return 0;
+}
+
+/* Closest hit to x_expected inside [first, last): linear scan, strict '<'
+ * so the lowest index wins a tie [R12].  Returns -1 if none is finite. */
+static int closest_x(const event_view *ev, int first, int last, float x_expected, float *dist) {
+    int best = -1;
+    float bd = INFINITY;
+    for (int i = first; i < last; ++i) {
+        float d = fabsf(ev->x[i] - x_expected);
+        if (d < bd) { bd = d; best = i; }
+    }
+    *dist = bd;
+    return best;
+}
+
+/* Same for a stereo layer: the hit's x at y=0 is moved to the predicted y
+ * with the hit's own stereo slope before comparing [R16]. */
+static int closest_uv(const event_view *ev, int first, int last, float x_pred, float y_pred,
+                      float *dist) {
+    int best = -1;
+    float bd = INFINITY;
+    for (int i = first; i < last; ++i) {
+        float d = fabsf(ev->x[i] + ev->dxdy[i] * y_pred - x_pred);
+        if (d < bd) { bd = d; best = i; }
+    }
+    *dist = bd;
+    return best;
+}
+
+/* x(z) model of the Propagation section, cubic term dRatio:
+ *   g(u) = u^2 (1 + dRatio u),  x(u) = a + b u + c g(u),  u = z - z_ref. */
+static float g_of(float u, float dRatio) { return u * u * (1.0f + dRatio * u); }
+
+static void track_one(const lfo_geometry *G, const lfo_params *P, const event_view *ev,
+                      float x_in, float y_in, float tx_in, float ty_in, float qop,
+                      uint8_t *found, uint8_t *n_out, int32_t *hit_out, float *par_out,
+                      int32_t *dbg_win, float *dbg_wx, int64_t *dbg_counts, int32_t *dbg_trip,
+                      float *dbg_trip_chi2, float *dbg_candQ, int32_t *dbg_cand_hits) {
+    const int NT = P->n_triplets;
+    *found = 0;
+    *n_out = 0;
+    for (int l = 0; l < LFO_NL; ++l) hit_out[l] = -1;
+    for (int k = 0; k < 7; ++k) par_out[k] = 0.0f;
+
+    /* ---- Kinematics [R2][R3]: the y-slope picks the detector half. ---- */
+    float p = 1.0f / fabsf(qop);
+    int q = qop > 0.0f ? 1 : -1;
+    int zone = ty_in >= 0.0f ? 1 : 0;
+
+    /* ---- pt-kick extrapolation to every layer [R1]: straight to the
+     *      bending plane, kick dtx = kick*q/p, then the post-magnet model. ---- */
+    float x_mag = x_in + tx_in * (G->z_mag - G->z_in);
+    float dtx = G->kick * qop;
+    float T = tx_in + dtx;
+    float kd = G->kappa * dtx;
+    float x_ext[LFO_NL], y_ext[LFO_NL];
+    for (int l = 0; l < LFO_NL; ++l) {
+        float dz = G->z[l] - G->z_mag;
+        float dzT = G->z[l] - G->z_T;
+        x_ext[l] = x_mag + T * dz + kd * dzT * dzT;
+        y_ext[l] = y_in + ty_in * (G->z[l] - G->z_in);
+    }
+
+    /* ---- Step 1: search windows (x_min/x_max; u/v straight line +-800 mm;
+     *      at most n_hits_window hits, symmetric around the centre). ---- */
+    float xtol = P->xtol_const + P->xtol_pscale / p;          /* [R4] */
+    float asymL = 0.0f, asymR = 0.0f;                          /* [R5] */
+    if (q * G->polarity > 0) asymR = P->xasym; else asymL = P->xasym;
+    int wfirst[LFO_NL], wlast[LFO_NL];
+    for (int l = 0; l < LFO_NL; ++l) {
+        float xc, xmin, xmax;
+        if (is_uv(l)) {                                         /* [R6] */
+            xc = x_ext[l] - G->dxdy[l] * y_ext[l];
+            xmin = xc - P->uv_halfwidth;
+            xmax = xc + P->uv_halfwidth;
+        } else {
+            xc = x_ext[l];
+            xmin = xc - xtol - asymL;
+            xmax = xc + xtol + asymR;
+        }
+        int b = 2 * l + zone;
+        int begin = (int)ev->begin[b], end = (int)ev->end[b];
+        /* [R7] closed interval by counting over the sorted bucket */
+        int lo = begin, hi = begin, c = begin;
+        for (int i = begin; i < end; ++i) {
+            if (ev->x[i] < xmin) ++lo;
+            if (ev->x[i] <= xmax) ++hi;
+            if (ev->x[i] < xc) ++c;
+        }
+        if (hi < lo) hi = lo;
+        if (c < lo) c = lo;
+        if (c > hi) c = hi;
+        int N = P->n_hits_window;
+        if (hi - lo > N) {                                     /* [R8] */
+            int first = c - N / 2;
+            if (first < lo) first = lo;
+            if (first > hi - N) first = hi - N;
+            wfirst[l] = first;
+            wlast[l] = first + N;
+        } else {
+            wfirst[l] = lo;
+            wlast[l] = hi;
+        }
+        if (dbg_win) { dbg_win[2 * l] = wfirst[l]; dbg_win[2 * l + 1] = wlast[l]; }
+        if (dbg_wx) { dbg_wx[3 * l] = xmin; dbg_wx[3 * l + 1] = xc; dbg_wx[3 * l + 2] = xmax; }
+    }
+
+    /* ---- Step 2: triplet seeding. ---- */
+    int64_t n_pairs = 0, n_doublets = 0;
+    size_t cap = 64, ntrip = 0;
+    triplet *trips = (triplet *)malloc(cap * sizeof(triplet));
+    if (!trips) return;
+    for (int s = 0; s < 2; ++s) {
+        int l0 = SEED_SETS[s][0], l1 = SEED_SETS[s][1], l2 = SEED_SETS[s][2];
+        float K = s == 0 ? P->K_first : P->K_last;
+        for (int i0 = wfirst[l0]; i0 < wlast[l0]; ++i0) {
+            for (int i2 = wfirst[l2]; i2 < wlast[l2]; ++i2) {
+                ++n_pairs;
+                float x0 = ev->x[i0], z0 = ev->z[i0];
+                float x2 = ev->x[i2], z2 = ev->z[i2];
+                float txd = (x2 - x0) / (z2 - z0);
+                /* doublet filter 1: below p_charge_cut the bending from the
+                 * upstream track to the doublet must follow the charge [R9] */
+                if (p < P->p_charge_cut && !((txd - tx_in) * qop > 0.0f)) continue;
+                /* doublet filter 2: x opening at the bending plane [R10] */
+                float xm = x0 + txd * (G->z_mag - z0);
+                float tol = P->magtol_const + P->magtol_pscale / p + P->magtol_txscale * fabsf(txd);
+                if (tol < P->magtol_min) tol = P->magtol_min;
+                if (tol > P->magtol_max) tol = P->magtol_max;
+                if (!(fabsf(xm - x_mag) < tol)) continue;
+                ++n_doublets;
+                /* middle hit: straight line corrected by K [R11] */
+                float x1e = G->z[l1] * txd + (x0 - txd * z0) * K;
+                float d;
+                int i1 = closest_x(ev, wfirst[l1], wlast[l1], x1e, &d);
+                if (i1 < 0 || !(d * d < P->T_triplet)) continue;
+                if (ntrip == cap) {
+                    cap *= 2;
+                    triplet *nt = (triplet *)realloc(trips, cap * sizeof(triplet));
+                    if (!nt) { free(trips); return; }
+                    trips = nt;
+                }
+                triplet t = {d * d, s, i0, i1, i2};
+                trips[ntrip++] = t;
+            }
+        }
+    }
+    qsort(trips, ntrip, sizeof(triplet), triplet_cmp);        /* [R13] */
+    int nkeep = (int)ntrip < NT ? (int)ntrip : NT;
+    for (int r = 0; r < NT; ++r) {
+        if (dbg_trip) {
+            int32_t *o = dbg_trip + 4 * r;
+            if (r < nkeep) { o[0] = trips[r].set; o[1] = trips[r].h0; o[2] = trips[r].h1; o[3] = trips[r].h2; }
+            else { o[0] = o[1] = o[2] = o[3] = -1; }
+        }
+        if (dbg_trip_chi2) dbg_trip_chi2[r] = r < nkeep ? trips[r].chi2 : NAN;
+    }
+    if (dbg_candQ) for (int r = 0; r < NT; ++r) dbg_candQ[r] = NAN;
+    if (dbg_cand_hits) for (int r = 0; r < NT * LFO_NL; ++r) dbg_cand_hits[r] = -1;
+
+    /* ---- Steps 3-4: extension, fit and quality for each kept triplet. ---- */
+    float T_uv = P->T_uv_scale * (fabsf(tx_in) + fabsf(ty_in));   /* [R17] */
+    if (T_uv < P->T_uv_floor) T_uv = P->T_uv_floor;
+    int best_rank = -1, best_n = 0;
+    float best_Q = 0.0f;
+    int best_hits[LFO_NL];
+    float best_par[5];
+    int n_valid = 0;
+    for (int r = 0; r < nkeep; ++r) {
+        const triplet *t = &trips[r];
+        int l0 = SEED_SETS[t->set][0], l1 = SEED_SETS[t->set][1], l2 = SEED_SETS[t->set][2];
+        int hits[LFO_NL];
+        for (int l = 0; l < LFO_NL; ++l) hits[l] = -1;
+        hits[l0] = t->h0; hits[l1] = t->h1; hits[l2] = t->h2;
+
+        /* parabola (cubic when dRatio != 0) through the three hits [R14]:
+         * x - c g(u) is linear in u, so equal secant slopes give c. */
+        float u0 = ev->z[t->h0] - G->z_ref, u1 = ev->z[t->h1] - G->z_ref, u2 = ev->z[t->h2] - G->z_ref;
+        float X0 = ev->x[t->h0], X1 = ev->x[t->h1], X2 = ev->x[t->h2];
+        float g0 = g_of(u0, G->dRatio), g1 = g_of(u1, G->dRatio), g2 = g_of(u2, G->dRatio);
+        float s01 = (X1 - X0) / (u1 - u0);
+        float s12 = (X2 - X1) / (u2 - u1);
+        float G01 = (g1 - g0) / (u1 - u0);
+        float G12 = (g2 - g1) / (u2 - u1);
+        float c = (s12 - s01) / (G12 - G01);
+        float b = s01 - c * G01;
+        float a = X0 - b * u0 - c * g0;
+
+        /* extension to the three missing x layers (no refit) [R15] */
+        for (int k = 0; k < 6; ++k) {
+            int l = X_LAYERS[k];
+            if (hits[l] >= 0) continue;
+            float u = G->z[l] - G->z_ref;
+            float xe = a + b * u + c * g_of(u, G->dRatio);
+            float d;
+            int i = closest_x(ev, wfirst[l], wlast[l], xe, &d);
+            if (i >= 0 && d * d < P->T_x) hits[l] = i;
+        }
+        /* extension to the u/v layers, slope-dependent tolerance [R16][R17] */
+        for (int k = 0; k < 6; ++k) {
+            int l = UV_LAYERS[k];
+            float u = G->z[l] - G->z_ref;
+            float xp = a + b * u + c * g_of(u, G->dRatio);
+            float d;
+            int i = closest_uv(ev, wfirst[l], wlast[l], xp, y_ext[l], &d);
+            if (i >= 0 && d * d < T_uv) hits[l] = i;
+        }
+        if (dbg_cand_hits) memcpy(dbg_cand_hits + r * LFO_NL, hits, sizeof(hits));
+        /* candidate rule: >= 9 hits and a u/v hit in each station [R18] */
+        int n = 0, n_uv = 0, st_ok = 1;
+        for (int l = 0; l < LFO_NL; ++l) if (hits[l] >= 0) { ++n; if (is_uv(l)) ++n_uv; }
+        for (int st = 0; st < 3; ++st)
+            if (hits[4 * st + 1] < 0 && hits[4 * st + 2] < 0) st_ok = 0;
+        if (n < 9 || !st_ok) continue;
+
+        /* ---- x least-squares fit over all hits [R19]: corrections (da, db, dc)
+         * to the triplet model, basis {1, s, s^2 (1 + dRatio u)}, s = u/1024. ---- */
+        float su[LFO_NL], sh[LFO_NL], rho[LFO_NL];
+        float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, S11 = 0.0f, S12 = 0.0f, S22 = 0.0f;
+        float R0 = 0.0f, R1 = 0.0f, R2 = 0.0f;
+        for (int l = 0; l < LFO_NL; ++l) {
+            int i = hits[l];
+            if (i < 0) continue;
+            float u = ev->z[i] - G->z_ref;
+            float xm;
+            if (is_uv(l)) {
+                float yv = y_in + ty_in * (ev->z[i] - G->z_in);
+                xm = ev->x[i] + ev->dxdy[i] * yv;
+            } else {
+                xm = ev->x[i];
+            }
+            float s = u * 0.0009765625f;
+            float h = s * s * (1.0f + G->dRatio * u);
+            float r = xm - (a + b * u + c * g_of(u, G->dRatio));
+            su[l] = s; sh[l] = h; rho[l] = r;
+            S0 = S0 + 1.0f;
+            S1 = S1 + s;
+            S2 = S2 + h;
+            S11 = S11 + s * s;
+            S12 = S12 + s * h;
+            S22 = S22 + h * h;
+            R0 = R0 + r;
+            R1 = R1 + s * r;
+            R2 = R2 + h * r;
+        }
+        /* normal equations M (da db dc)^T = (R0 R1 R2)^T solved by Cramer's rule */
+        float m00 = S11 * S22 - S12 * S12;
+        float m01 = S1 * S22 - S12 * S2;
+        float m02 = S1 * S12 - S11 * S2;
+        float det = S0 * m00 - S1 * m01 + S2 * m02;
+        if (!(fabsf(det) > 0.0f)) continue;
+        float da = (R0 * m00 - S1 * (R1 * S22 - S12 * R2) + S2 * (R1 * S12 - S11 * R2)) / det;
+        float db = (S0 * (R1 * S22 - S12 * R2) - R0 * m01 + S2 * (S1 * R2 - R1 * S2)) / det;
+        float dc = (S0 * (S11 * R2 - R1 * S12) - S1 * (S1 * R2 - R1 * S2) + R0 * m02) / det;
+
+        /* residuals to the fitted model; Q_x [R21] */
+        float res[LFO_NL];
+        float Qx = 0.0f;
+        for (int l = 0; l < LFO_NL; ++l) {
+            if (hits[l] < 0) continue;
+            res[l] = rho[l] - (da + db * su[l] + dc * sh[l]);
+            Qx = Qx + res[l] * res[l] / (is_uv(l) ? T_uv : P->T_x);
+        }
+
+        /* ---- y least-squares line over the u/v hits [R20]: each hit's y is
+         * where its fibre meets the fitted x, y = y_ext - res/dxdy, so the
+         * offsets from the input line are eta = -res/dxdy. ---- */
+        float Y_S0 = 0.0f, Y_S1 = 0.0f, Y_S11 = 0.0f, Y0 = 0.0f, Y1 = 0.0f;
+        float eta[LFO_NL];
+        for (int l = 0; l < LFO_NL; ++l) {
+            int i = hits[l];
+            if (i < 0 || !is_uv(l)) continue;
+            eta[l] = -res[l] / ev->dxdy[i];
+            Y_S0 = Y_S0 + 1.0f;
+            Y_S1 = Y_S1 + su[l];
+            Y_S11 = Y_S11 + su[l] * su[l];
+            Y0 = Y0 + eta[l];
+            Y1 = Y1 + su[l] * eta[l];
+        }
+        float D = Y_S0 * Y_S11 - Y_S1 * Y_S1;
+        if (!(fabsf(D) > 0.0f)) continue;
+        float dy0 = (Y0 * Y_S11 - Y_S1 * Y1) / D;
+        float dty = (Y_S0 * Y1 - Y_S1 * Y0) / D;
+        float dslope = dty * 0.0009765625f;
+        if (!(fabsf(dslope) < P->T_ty)) continue;              /* [R22] */
+        float Qy = 0.0f;
+        for (int l = 0; l < LFO_NL; ++l) {
+            if (hits[l] < 0 || !is_uv(l)) continue;
+            float ry = eta[l] - (dy0 + dty * su[l]);
+            Qy = Qy + ry * ry / P->T_y;
+        }
+        /* ---- quality factor [R21] ---- */
+        float Q = (Qx / (float)(n - 3) + Qy / (float)(n_uv - 2)) * P->C_nhits[n - 9];
+        if (dbg_candQ) dbg_candQ[r] = Q;
+        if (!(Q < P->T_Q)) continue;
+        ++n_valid;
+        /* best candidate: lowest Q, then lowest rank [R23] */
+        if (best_rank < 0 || Q < best_Q) {
+            best_rank = r;
+            best_Q = Q;
+            memcpy(best_hits, hits, sizeof(hits));
+            best_par[0] = a + da;
+            best_par[1] = b + db * 0.0009765625f;
+            best_par[2] = c + dc * 0.00000095367431640625f;
+            best_par[3] = (y_in + ty_in * (G->z_ref - G->z_in)) + dy0;
+            best_par[4] = ty_in + dslope;
+            best_n = n;
+        }
+    }
+    free(trips);
+    if (dbg_counts) {
+        dbg_counts[0] = n_pairs;
+        dbg_counts[1] = n_doublets;
+        dbg_counts[2] = (int64_t)ntrip;
+        dbg_counts[3] = n_valid;
+    }
+    if (best_rank < 0) return;
+
+    /* ---- momentum from the slope change at z_T [R24] ---- */
+    float bb = best_par[1], cc = best_par[2];
+    float uT = G->z_T - G->z_ref;
+    float txT = bb + 2.0f * cc * uT + 3.0f * cc * G->dRatio * uT * uT;
+    float qop_out = (txT - tx_in) / G->kick;
+
+    *found = 1;
+    *n_out = (uint8_t)best_n;
+    for (int l = 0; l < LFO_NL; ++l) hit_out[l] = best_hits[l];
+    par_out[0] = best_par[0];
+    par_out[1] = best_par[1];
+    par_out[2] = best_par[2];
+    par_out[3] = best_par[3];
+    par_out[4] = best_par[4];
+    par_out[5] = qop_out;
+    par_out[6] = best_Q;
+}
+
+int lfo_find_tracks(const lfo_geometry *g, const lfo_params *P, uint32_t n_events,
+                    const uint32_t *hit_off, const float *hit_x, const float *hit_z,
+                    const float *hit_dxdy, const uint32_t *trk_off, const float *trk_x,
+                    const float *trk_y, const float *trk_tx, const float *trk_ty,
+                    const float *trk_qop, uint32_t ev_begin, uint32_t ev_end,
+                    lfo_out *out, lfo_debug *dbg) {
+    if (!g || !P || !hit_off || !trk_off || !out || ev_end > n_events || ev_begin > ev_end)
+        return -1;
+    if (P->n_triplets < 1 || P->n_triplets > LFO_MAX_TRIPLETS || P->n_hits_window < 1) return -1;
+    const int NT = P->n_triplets;
+    for (uint32_t e = ev_begin; e < ev_end; ++e) {
+        uint32_t base = hit_off[24 * e];
+        event_view ev;
+        ev.x = hit_x + base;
+        ev.z = hit_z + base;
+        ev.dxdy = hit_dxdy + base;
+        for (int b = 0; b < 24; ++b) {
+            ev.begin[b] = hit_off[24 * e + b] - base;
+            ev.end[b] = hit_off[24 * e + b + 1] - base;
+        }
+        for (uint32_t t = trk_off[e]; t < trk_off[e + 1]; ++t) {
+            float par[7];
+            track_one(g, P, &ev, trk_x[t], trk_y[t], trk_tx[t], trk_ty[t], trk_qop[t],
+                      &out->found[t], &out->n_hits[t], &out->hit_idx[(size_t)t * LFO_NL], par,
+                      dbg && dbg->win ? dbg->win + (size_t)t * 24 : NULL,
+                      dbg && dbg->wx ? dbg->wx + (size_t)t * 36 : NULL,
+                      dbg && dbg->counts ? dbg->counts + (size_t)t * 4 : NULL,
+                      dbg && dbg->trip ? dbg->trip + (size_t)t * NT * 4 : NULL,
+                      dbg && dbg->trip_chi2 ? dbg->trip_chi2 + (size_t)t * NT : NULL,
+                      dbg && dbg->cand_Q ? dbg->cand_Q + (size_t)t * NT : NULL,
+                      dbg && dbg->cand_hits ? dbg->cand_hits + (size_t)t * NT * LFO_NL : NULL);
+            out->a[t] = par[0];
+            out->b[t] = par[1];
+            out->c[t] = par[2];
+            out->y0[t] = par[3];
+            out->ty[t] = par[4];
+            out->qop[t] = par[5];
+            out->Q[t] = par[6];
+        }
+    }
+    return 0;
+}

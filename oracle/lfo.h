@@ -1,0 +1,85 @@
+/*
+ * lfo.h -- CPU oracle for Looking Forward track following (arXiv 2402.14670).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, single-threaded
+ * reference that the GPU library is checked against.  Only the tests, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product path never does.  It shares no code, header or constant with the
+ * GPU library: its structures below are its own.
+ *
+ * Arithmetic is IEEE binary32, round to nearest even, built with
+ * -ffp-contract=off and without fast-math, evaluated in the order written in
+ * lfo.c (the paper keeps hits in fp32; its Performance section).
+ *
+ * Entry point: lfo_find_tracks() runs the four steps of the paper's
+ * "Algorithm logic" section (search windows, triplet seeding, extension,
+ * quality filter) followed by the momentum / state computation, for every
+ * input track of every event, and writes one result slot per input track.
+ */
+#ifndef LFO_H
+#define LFO_H
+#include <stdint.h>
+
+#define LFO_NL 12
+#define LFO_MAX_TRIPLETS 64
+
+/* Detector and field description (all mm, GeV). */
+typedef struct {
+    float z[LFO_NL];      /* layer planes; x layers 0,3,4,7,8,11, u/v layers 1,2,5,6,9,10 */
+    float dxdy[LFO_NL];   /* stereo tangent of each layer (0 for x layers) */
+    float z_in;           /* z of the upstream track states */
+    float z_mag;          /* bending plane of the pt-kick (z_bending) */
+    float z_ref;          /* reference plane of the x(z) track model (8520 mm) */
+    float z_T;            /* plane where the post-magnet slope is read for q/p */
+    float kick;           /* slope kick per unit q/p: dtx = kick * q/p */
+    float kappa;          /* residual curvature after the magnet, per unit dtx */
+    float dRatio;         /* cubic term of the x(z) model */
+    int32_t polarity;     /* +1: q > 0 bends towards +x (window asymmetry on +x) */
+} lfo_geometry;
+
+/* Tunable parameters (Table of tolerances, Forward column; C(n_hits) table). */
+typedef struct {
+    float T_triplet, T_x, T_uv_scale, T_uv_floor, T_ty, T_y, T_Q;
+    float xtol_const, xtol_pscale, xasym, uv_halfwidth;
+    float K_first, K_last;
+    float magtol_const, magtol_pscale, magtol_txscale, magtol_min, magtol_max;
+    float p_charge_cut;
+    float C_nhits[4];     /* C(9), C(10), C(11), C(12) */
+    int32_t n_hits_window;
+    int32_t n_triplets;   /* <= LFO_MAX_TRIPLETS */
+} lfo_params;
+
+/* One result slot per input track.  hit_idx is event-local (index into the
+ * event's hits in bucket-major order), -1 where the layer has no hit. */
+typedef struct {
+    uint8_t *found, *n_hits;
+    int32_t *hit_idx;                       /* [n_tracks * 12] */
+    float *a, *b, *c, *y0, *ty, *qop, *Q;   /* x(z_ref), dx/dz(z_ref), curvature, y(z_ref), dy/dz */
+} lfo_out;
+
+/* Optional intermediate dumps (any pointer may be NULL). */
+typedef struct {
+    int32_t *win;          /* [n_tracks * 24]: event-local [first, last) per layer */
+    float *wx;             /* [n_tracks * 36]: x_min, centre, x_max per layer */
+    int64_t *counts;       /* [n_tracks * 4]: doublet pairs, filtered doublets, triplets, valid candidates */
+    int32_t *trip;         /* [n_tracks * n_triplets * 4]: set, h0, h1, h2 (rank order; -1 padded) */
+    float *trip_chi2;      /* [n_tracks * n_triplets] */
+    float *cand_Q;         /* [n_tracks * n_triplets]: Q of each candidate, NaN if rejected earlier */
+    int32_t *cand_hits;    /* [n_tracks * n_triplets * 12]: hits after extension, -1 = none */
+} lfo_debug;
+
+void lfo_default_params(lfo_params *p);
+
+/* Runs events [ev_begin, ev_end) of the batch.  Arrays are the whole batch:
+ * hit_off[24*n_events+1] (bucket = 24*event + 2*layer + zone), hits sorted
+ * by non-decreasing x inside each bucket; trk_off[n_events+1].  Output and
+ * debug arrays are indexed by the global track index.  Returns 0, or -1 on
+ * an argument error. */
+int lfo_find_tracks(const lfo_geometry *g, const lfo_params *P, uint32_t n_events,
+                    const uint32_t *hit_off, const float *hit_x, const float *hit_z,
+                    const float *hit_dxdy, const uint32_t *trk_off, const float *trk_x,
+                    const float *trk_y, const float *trk_tx, const float *trk_ty,
+                    const float *trk_qop, uint32_t ev_begin, uint32_t ev_end,
+                    lfo_out *out, lfo_debug *dbg);
+
+#endif

@@ -1,0 +1,669 @@
+"""Pins for the CPU oracle: checks against what the paper and the mathematics
+fix, independent of the oracle's own code.
+
+Each ``pin_*`` function takes an oracle library handle (``None`` = the built
+oracle) and raises AssertionError when the oracle disagrees.  The same pins
+are run against copies of the oracle with planted mistakes, each of which
+must fail at least one pin.
+"""
+from __future__ import annotations
+
+import functools
+import math
+import os
+
+import numpy as np
+
+import lfgen
+import oracle
+import truth
+
+NL = 12
+X_LAYERS = (0, 3, 4, 7, 8, 11)
+UV_LAYERS = (1, 2, 5, 6, 9, 10)
+SEED_SETS = ((0, 4, 8), (3, 7, 11))
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_constants.txt")
+W = lfgen.world()
+f32 = np.float32
+
+
+def golden_constants() -> dict:
+    out = {}
+    with open(GOLDEN) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            head = line.split("|")[0].split()
+            out[head[0]] = float(head[1])
+    return out
+
+
+# ------------------------------------------------------------------ events
+@functools.lru_cache(maxsize=None)
+def ev_noise_free(seed: int = 11, p_min: float = 1.5, p_max: float = 50.0, n: int = 40):
+    """Single-event geometry, no smearing, no noise, every layer efficient."""
+    return lfgen.generate("single", seed=seed, sigma_x=0.0, qop_sigma=0.0, hit_eff=1.0, n_noise=0,
+                          p_min=p_min, p_max=p_max, n_particles=n)
+
+
+@functools.lru_cache(maxsize=None)
+def ev_single():
+    return lfgen.generate("single")
+
+
+@functools.lru_cache(maxsize=None)
+def ev_nominal(n: int = 2):
+    return lfgen.generate("nominal", n_events=n)
+
+
+@functools.lru_cache(maxsize=None)
+def ev_stress():
+    return lfgen.generate("stress", n_events=1)
+
+
+@functools.lru_cache(maxsize=None)
+def ev_tiny():
+    return lfgen.generate("single", seed=7, n_events=6, n_particles=8, n_noise=20, p_min=1.5,
+                          p_max=20.0)
+
+
+def truth_hit(ev, t: int, layer: int) -> int:
+    """Event-local index of the hit the track's particle left in ``layer`` (-1 if none)."""
+    e = int(ev.track_event()[t])
+    pid = int(ev.trk_pid[t])
+    base = int(ev.hit_off[24 * e])
+    for zone in (0, 1):
+        b = 24 * e + 2 * layer + zone
+        h = np.arange(int(ev.hit_off[b]), int(ev.hit_off[b + 1]))
+        h = h[ev.hit_pid[h] == pid]
+        if len(h):
+            return int(h[0]) - base
+    return -1
+
+
+def particle(ev, t: int):
+    e = int(ev.track_event()[t])
+    g = int(ev.par_off[e]) + int(ev.trk_pid[t])
+    return float(ev.par_p[g]), float(ev.par_q[g]), float(ev.par_tx[g]), float(ev.par_ty[g])
+
+
+# ------------------------------------------------------------------ pins
+def pin_constants(lib=None):
+    """Default parameters equal the values the paper prints."""
+    gold = golden_constants()
+    p = oracle.make_params(None, lib)
+    for k, v in gold.items():
+        if k.startswith("C_"):
+            got = p.C_nhits[int(k[2:]) - 9]
+        elif k == "z_ref":
+            got = oracle.Z_REF
+        else:
+            got = getattr(p, k)
+        assert got == f32(v), f"{k}: oracle default {got} != paper {v}"
+
+
+def pin_extrapolation_noise_free(lib=None):
+    """Window centres equal the exact hit positions of noise-free tracks with
+    exact q/p (x layers: x; u/v layers: x - dxdy*y), and the truth hit sits
+    inside every window."""
+    ev = ev_noise_free()
+    o = oracle.run(ev, W, debug=True, lib=lib)
+    worst = 0.0
+    n = 0
+    for t in range(ev.n_tracks):
+        for l in range(NL):
+            h = truth_hit(ev, t, l)
+            if h < 0:
+                continue
+            base = int(ev.hit_off[24 * int(ev.track_event()[t])])
+            worst = max(worst, abs(float(o["wx"][t, l, 1]) - float(ev.hit_x[base + h])))
+            assert o["win"][t, l, 0] <= h < o["win"][t, l, 1], f"truth hit outside window t={t} l={l}"
+            n += 1
+    assert n > 300
+    assert worst <= 1e-3, f"window centre off the exact hit by {worst} mm"
+
+
+def pin_window_bounds(lib=None):
+    """x-layer width 2*(150 + 2000/p) + 100 with the asymmetry on the bending
+    side; u/v layers +-800 mm around the centre."""
+    ev = ev_single()
+    o = oracle.run(ev, W, debug=True, lib=lib)
+    for t in range(ev.n_tracks):
+        qop = float(ev.trk_qop[t])
+        xtol = 150.0 + 2000.0 * abs(qop)
+        for l in range(NL):
+            xmin, xc, xmax = (float(v) for v in o["wx"][t, l])
+            tol = 2e-3 + 1e-6 * abs(xc)
+            if l in X_LAYERS:
+                right = xtol + (100.0 if qop > 0 else 0.0)
+                left = xtol + (100.0 if qop < 0 else 0.0)
+                assert abs((xmax - xc) - right) < tol, (t, l, xmax - xc, right)
+                assert abs((xc - xmin) - left) < tol, (t, l, xc - xmin, left)
+            else:
+                assert abs((xmax - xc) - 800.0) < tol and abs((xc - xmin) - 800.0) < tol
+
+
+def _brute_window(xs, xmin, xc, xmax, N):
+    """R7/R8 by brute force over the sorted bucket (bucket-relative indices)."""
+    inside = [i for i in range(len(xs)) if xmin <= xs[i] <= xmax]
+    if not inside:
+        lo = sum(1 for v in xs if v < xmin)
+        return lo, lo
+    lo, hi = inside[0], inside[-1] + 1
+    if hi - lo <= N:
+        return lo, hi
+    c = sum(1 for v in xs if v < xc)
+    c = min(max(c, lo), hi)
+    first = min(max(c - N // 2, lo), hi - N)
+    return first, first + N
+
+
+def pin_window_search(lib=None):
+    """Windows (incl. the symmetric cap at n_hits_window) equal a brute-force
+    scan of the bucket, on a dense event where most windows are capped."""
+    for ev in (ev_stress(), ev_nominal(1)):
+        o = oracle.run(ev, W, debug=True, lib=lib)
+        n_capped = 0
+        for t in range(ev.n_tracks):
+            zone = 1 if ev.trk_ty[t] >= 0 else 0
+            for l in range(NL):
+                b = 2 * l + zone
+                h0, h1 = int(ev.hit_off[b]), int(ev.hit_off[b + 1])
+                xs = ev.hit_x[h0:h1]
+                xmin, xc, xmax = o["wx"][t, l]
+                f, e = _brute_window(xs, xmin, xc, xmax, 32)
+                got = (int(o["win"][t, l, 0]) - h0, int(o["win"][t, l, 1]) - h0)
+                assert got == (f, e), (t, l, got, (f, e))
+                n_capped += (e - f) == 32
+        assert n_capped > 0
+
+
+def pin_window_edges_closed(lib=None):
+    """Hits exactly on x_min and x_max are inside the window; the next float
+    outward is not (closed interval)."""
+    ev = ev_single()
+    o = oracle.run(ev, W, debug=True, lib=lib)
+    t, l = 0, 0
+    zone = 1 if ev.trk_ty[t] >= 0 else 0
+    xmin, _, xmax = (f32(v) for v in o["wx"][t, l])
+    b = 2 * l + zone
+    h0, h1 = int(ev.hit_off[b]), int(ev.hit_off[b + 1])
+    extra = np.array([np.nextafter(xmin, f32(-np.inf)), xmin, xmax, np.nextafter(xmax, f32(np.inf))],
+                     np.float32)
+    xs = np.sort(np.concatenate([ev.hit_x[h0:h1], extra]), kind="stable")
+    # rebuild the event with the four extra hits in bucket b
+    hx = np.concatenate([ev.hit_x[:h0], xs, ev.hit_x[h1:]])
+    hz = np.concatenate([ev.hit_z[:h0], np.full(len(xs), ev.hit_z[h0] if h1 > h0 else W["z"][l], np.float32),
+                         ev.hit_z[h1:]])
+    hd = np.concatenate([ev.hit_dxdy[:h0], np.full(len(xs), W["dxdy"][l], np.float32), ev.hit_dxdy[h1:]])
+    off = ev.hit_off.astype(np.int64).copy()
+    off[b + 1:] += 4
+    ev2 = lfgen.Events(**{**ev.__dict__, "hit_x": hx.astype(np.float32), "hit_z": hz.astype(np.float32),
+                          "hit_dxdy": hd.astype(np.float32), "hit_off": off.astype(np.uint32),
+                          "hit_pid": np.zeros(len(hx), np.int32)})
+    o2 = oracle.run(ev2, W, debug=True, lib=lib)
+    f, e = int(o2["win"][t, l, 0]) - h0, int(o2["win"][t, l, 1]) - h0
+    win = xs[f:e]
+    assert (win == xmin).any() and (win == xmax).any(), "edge hits must be inside"
+    assert not (win < xmin).any() and not (win > xmax).any(), "hits beyond the edges must be outside"
+
+
+def closed_form_triplet_residual() -> tuple[float, float]:
+    """Middle-hit residual per unit dtx for each seed set, derived in float64
+    from the toy field and the paper's K factors (independent of the oracle):
+    x1_true - [z1*t + (x0 - t*z0)*K] for the line t through (z0,x0),(z2,x2)."""
+    z = W["z"]
+    out = []
+    for (l0, l1, l2), K in zip(SEED_SETS, (1.00177513, 1.00142634)):
+        # residual is linear in dtx and independent of tx: evaluate at dtx = 1, tx = 0
+        x = [(z[i] - W["z_mag"]) + W["kappa"] * (z[i] - W["z_T"]) ** 2 for i in (l0, l1, l2)]
+        t = (x[2] - x[0]) / (z[l2] - z[l0])
+        x1e = z[l1] * t + (x[0] - t * z[l0]) * K
+        out.append(x[1] - x1e)
+    return out[0], out[1]
+
+
+def pin_triplet_closed_form(lib=None):
+    """chi2 of every true triplet of a noise-free track equals the closed-form
+    sagitta residual (C_s * dtx)^2 within 1e-3 mm."""
+    ev = ev_noise_free()
+    o = oracle.run(ev, W, debug=True, lib=lib, params={"n_triplets": 64})
+    cf = closed_form_triplet_residual()
+    checked = 0
+    for t in range(ev.n_tracks):
+        p, q, tx, ty = particle(ev, t)
+        dtx = 1.2 * q / p
+        for s, layers in enumerate(SEED_SETS):
+            hs = [truth_hit(ev, t, l) for l in layers]
+            if min(hs) < 0:
+                continue
+            rows = np.nonzero((o["trip"][t, :, 0] == s) & (o["trip"][t, :, 1] == hs[0]) &
+                              (o["trip"][t, :, 3] == hs[2]))[0]
+            expect = abs(cf[s] * dtx)
+            if expect ** 2 >= 8.0:
+                assert len(rows) == 0 or o["trip"][t, rows[0], 2] != hs[1]
+                continue
+            assert len(rows) == 1, f"true doublet missing t={t} set={s}"
+            got = math.sqrt(float(o["trip_chi2"][t, rows[0]]))
+            if o["trip"][t, rows[0], 2] == hs[1]:
+                assert abs(got - expect) < 1e-3, (t, s, got, expect)
+                checked += 1
+            else:
+                assert got <= expect + 1e-3, "a farther middle hit was preferred"
+    assert checked > 40
+
+
+def pin_magnet_threshold(lib=None):
+    """With the magnet tolerance pinned to 6 mm, a true doublet passes exactly
+    when its closed-form offset at z_mag (8.0876*dtx for the first set,
+    -20.594*dtx for the last; straight line through the two hits) is below 6 mm."""
+    ev = ev_noise_free()
+    z = W["z"]
+    offs = []
+    for (l0, _, l2) in SEED_SETS:
+        x0 = (z[l0] - W["z_mag"]) + W["kappa"] * (z[l0] - W["z_T"]) ** 2
+        x2 = (z[l2] - W["z_mag"]) + W["kappa"] * (z[l2] - W["z_T"]) ** 2
+        t = (x2 - x0) / (z[l2] - z[l0])
+        offs.append(x0 + t * (W["z_mag"] - z[l0]))
+    ev = ev_noise_free(seed=12, p_max=10.0, n=80)
+    o = oracle.run(ev, W, debug=True, lib=lib,
+                   params={"n_triplets": 64, "magtol_min": 6.0, "magtol_max": 6.0, "p_charge_cut": 0.0})
+    n_in = n_out = 0
+    for t in range(ev.n_tracks):
+        p, q, tx, ty = particle(ev, t)
+        dtx = 1.2 * q / p
+        for s, layers in enumerate(SEED_SETS):
+            hs = [truth_hit(ev, t, l) for l in layers]
+            if min(hs) < 0:
+                continue
+            off = abs(offs[s] * dtx)
+            if abs(off - 6.0) < 0.05:
+                continue
+            present = ((o["trip"][t, :, 0] == s) & (o["trip"][t, :, 1] == hs[0]) &
+                       (o["trip"][t, :, 3] == hs[2])).any()
+            assert present == (off < 6.0), (t, s, off, present)
+            n_in += present
+            n_out += not present
+    assert n_in > 10 and n_out > 5
+
+
+def pin_charge_filter(lib=None):
+    """Below 5 GeV the doublet must bend the way the upstream charge says:
+    flipping the sign of q/p removes every true low-momentum triplet."""
+    ev = ev_noise_free(seed=12, p_max=10.0, n=80)
+    flipped = lfgen.Events(**{**ev.__dict__, "trk_qop": (-ev.trk_qop).astype(np.float32)})
+    o = oracle.run(ev, W, debug=True, lib=lib, params={"n_triplets": 64})
+    of = oracle.run(flipped, W, debug=True, lib=lib, params={"n_triplets": 64})
+    n_low = 0
+    for t in range(ev.n_tracks):
+        p, q, tx, ty = particle(ev, t)
+        if p >= 4.9:
+            continue
+        for s, layers in enumerate(SEED_SETS):
+            hs = [truth_hit(ev, t, l) for l in layers]
+            if min(hs) < 0:
+                continue
+            key = lambda oo: ((oo["trip"][t, :, 0] == s) & (oo["trip"][t, :, 1] == hs[0]) &
+                              (oo["trip"][t, :, 3] == hs[2])).any()
+            assert key(o), f"true low-p triplet missing t={t}"
+            assert not key(of), f"wrong-charge doublet accepted t={t}"
+            n_low += 1
+    assert n_low > 10
+
+
+def _bruteforce_triplets(ev, t, P, NT):
+    """Exhaustive O(n0*n2*n1) triplet enumeration over whole buckets, float32,
+    every triplet kept, fully sorted by (chi2, set, h0, h2)."""
+    e = int(ev.track_event()[t])
+    base = int(ev.hit_off[24 * e])
+    X, Z = ev.hit_x, ev.hit_z
+    qop = f32(ev.trk_qop[t])
+    x_in, tx_in, ty_in = f32(ev.trk_x[t]), f32(ev.trk_tx[t]), f32(ev.trk_ty[t])
+    p = f32(1.0) / abs(qop)
+    zone = 1 if ty_in >= 0 else 0
+    x_mag = x_in + tx_in * (f32(W["z_mag"]) - f32(W["z_in"]))
+    out = []
+    for s, (l0, l1, l2) in enumerate(SEED_SETS):
+        K = f32(P["K_first"] if s == 0 else P["K_last"])
+        b = [24 * e + 2 * l + zone for l in (l0, l1, l2)]
+        r0 = range(int(ev.hit_off[b[0]]), int(ev.hit_off[b[0] + 1]))
+        r1 = range(int(ev.hit_off[b[1]]), int(ev.hit_off[b[1] + 1]))
+        r2 = range(int(ev.hit_off[b[2]]), int(ev.hit_off[b[2] + 1]))
+        for i0 in r0:
+            for i2 in r2:
+                x0, z0, x2, z2 = X[i0], Z[i0], X[i2], Z[i2]
+                txd = (x2 - x0) / (z2 - z0)
+                if p < f32(P["p_charge_cut"]) and not ((txd - tx_in) * qop > 0):
+                    continue
+                xm = x0 + txd * (f32(W["z_mag"]) - z0)
+                tol = f32(P["magtol_const"]) + f32(P["magtol_pscale"]) / p + f32(P["magtol_txscale"]) * abs(txd)
+                tol = min(max(tol, f32(P["magtol_min"])), f32(P["magtol_max"]))
+                if not abs(xm - x_mag) < tol:
+                    continue
+                x1e = f32(W["z"][l1]) * txd + (x0 - txd * z0) * K
+                d = [abs(X[i1] - x1e) for i1 in r1]
+                if not d:
+                    continue
+                k = int(np.argmin(d))          # first minimum = lowest index
+                if d[k] * d[k] < f32(P["T_triplet"]):
+                    out.append((float(d[k] * d[k]), s, i0 - base, r1[k] - base, i2 - base))
+    out.sort(key=lambda r: (r[0], r[1], r[2], r[4]))
+    return out[:NT], len(out)
+
+
+def pin_bruteforce_triplets(lib=None):
+    """With windows spanning whole buckets, the windowed search keeps exactly
+    the top-n triplets of an exhaustive enumeration (tiny events)."""
+    ev = ev_tiny()
+    NT = 2
+    big = {"xtol_const": 1e7, "uv_halfwidth": 1e7, "n_hits_window": 100000, "n_triplets": NT,
+           "T_triplet": 40.0}
+    P = oracle.default_params()
+    P.update(big)
+    o = oracle.run(ev, W, params=big, debug=True, lib=lib)
+    n_cut = 0
+    for t in range(ev.n_tracks):
+        ref, n_all = _bruteforce_triplets(ev, t, P, NT)
+        got = [(float(o["trip_chi2"][t, r]), *map(int, o["trip"][t, r])) for r in range(NT)
+               if o["trip"][t, r, 0] >= 0]
+        assert len(got) == len(ref), (t, got, ref)
+        for g, r in zip(got, ref):
+            assert g[1:] == r[1:] and f32(g[0]) == f32(r[0]), (t, g, r)
+        assert int(o["counts"][t, 2]) == n_all
+        n_cut += n_all > NT
+    assert n_cut > 0
+
+
+def _fit_truth(p, q, tx, ty):
+    dtx = W["kick"] * q / p
+    T = tx + dtx
+    zr = oracle.Z_REF
+    a = tx * W["z_mag"] + T * (zr - W["z_mag"]) + W["kappa"] * dtx * (zr - W["z_T"]) ** 2
+    b = T + 2 * W["kappa"] * dtx * (zr - W["z_T"])
+    c = W["kappa"] * dtx
+    return a, b, c, ty * zr, ty
+
+
+def pin_fit_noise_free(lib=None):
+    """Noise-free tracks: (a, b, c) = (x, dx/dz, curvature) at z_ref, (y0, ty)
+    = (ty*z_ref, ty), Q ~ 0, q/p_out = q/p_true, all 12 true hits."""
+    ev = ev_noise_free()
+    o = oracle.run(ev, W, lib=lib)
+    n = 0
+    for t in np.nonzero(o["found"])[0]:
+        p, q, tx, ty = particle(ev, t)
+        a, b, c, y0, tyt = _fit_truth(p, q, tx, ty)
+        assert abs(o["a"][t] - a) < 2e-3
+        assert abs(o["b"][t] - b) < 1e-6
+        assert abs(o["c"][t] - c) < 1e-3 * abs(c) + 1e-12
+        assert abs(o["y0"][t] - y0) < 2e-3
+        assert abs(o["ty"][t] - tyt) < 1e-5
+        assert abs(o["qop"][t] * p / q - 1.0) < 1e-5
+        assert o["Q"][t] < 1e-6
+        for l in range(NL):
+            assert o["hit_idx"][t, l] == truth_hit(ev, t, l)
+        n += 1
+    assert n >= 35
+
+
+def lstsq_fit(ev, t, hits, P, T_uv):
+    """float64 least squares over a track's hits: returns predicted x per hit,
+    fitted y per u/v hit, (a,b,c,y0,ty) and Q."""
+    e = int(ev.track_event()[t])
+    base = int(ev.hit_off[24 * e])
+    zr = oracle.Z_REF
+    y_in, ty_in = float(ev.trk_y[t]), float(ev.trk_ty[t])
+    rows, xs, isuv, idx = [], [], [], []
+    for l in range(NL):
+        h = int(hits[l])
+        if h < 0:
+            continue
+        g = base + h
+        z = float(ev.hit_z[g])
+        u = z - zr
+        x = float(ev.hit_x[g])
+        if l in UV_LAYERS:
+            x += float(ev.hit_dxdy[g]) * (y_in + ty_in * (z - W["z_in"]))
+        rows.append([1.0, u, u * u * (1.0 + W.get("dRatio", 0.0) * u)])
+        xs.append(x)
+        isuv.append(l in UV_LAYERS)
+        idx.append(g)
+    A = np.array(rows)
+    sol, *_ = np.linalg.lstsq(A, np.array(xs), rcond=None)
+    xf = A @ sol
+    r = np.array(xs) - xf
+    isuv = np.array(isuv)
+    Qx = float(np.sum(r[~isuv] ** 2) / P["T_x"] + np.sum(r[isuv] ** 2) / T_uv)
+    # y of each u/v hit where its fibre meets the fitted x
+    gi = np.array(idx)[isuv]
+    ys = (xf[isuv] - ev.hit_x[gi].astype(np.float64)) / ev.hit_dxdy[gi].astype(np.float64)
+    B = np.stack([np.ones(isuv.sum()), A[isuv, 1]], 1)
+    ysol, *_ = np.linalg.lstsq(B, ys, rcond=None)
+    ry = ys - B @ ysol
+    Qy = float(np.sum(ry ** 2) / P["T_y"])
+    n, nuv = len(xs), int(isuv.sum())
+    Q = (Qx / (n - 3) + Qy / (nuv - 2)) * P["C_nhits"][n - 9]
+    return xf, A, sol, ysol, Q
+
+
+def pin_fit_lstsq(lib=None):
+    """With smeared hits the oracle's float32 fits agree with float64 least
+    squares over the same hits: x at every hit within 1e-3 mm, ty within 1e-5,
+    Q within 1e-2 relative (the stereo-corrected x of a u/v hit is rounded to
+    float32, about 1e-4 mm, on residuals of a few 0.01 mm)."""
+    ev = ev_nominal(1)
+    P = oracle.default_params()
+    o = oracle.run(ev, W, lib=lib)
+    n = 0
+    for t in np.nonzero(o["found"])[0][:150]:
+        T_uv = max(2.0, 50.0 * (abs(float(ev.trk_tx[t])) + abs(float(ev.trk_ty[t]))))
+        xf, A, sol, ysol, Q = lstsq_fit(ev, t, o["hit_idx"][t], P, T_uv)
+        mine = np.array([float(o["a"][t]), float(o["b"][t]), float(o["c"][t])])
+        assert np.max(np.abs(A @ mine - xf)) < 1e-3, (t, A @ mine - xf)
+        y0 = float(o["y0"][t])
+        assert abs(float(o["ty"][t]) - ysol[1]) < 1e-5, (t, o["ty"][t], ysol[1])
+        assert abs(y0 - ysol[0]) < 5e-3, (t, y0, ysol[0])
+        assert abs(float(o["Q"][t]) - Q) <= 1e-2 * Q + 1e-7, (t, o["Q"][t], Q)
+        n += 1
+    assert n > 100
+
+
+def pin_y_fit_recovers_slope(lib=None):
+    """The y fit measures ty from the stereo hits: with the input slope off by
+    +3e-4, the fitted ty returns to the true slope."""
+    ev = ev_noise_free(p_min=5.0)
+    d = np.float32(3e-4)
+    bent = lfgen.Events(**{**ev.__dict__, "trk_ty": (ev.trk_ty + d).astype(np.float32),
+                           "trk_y": (ev.trk_y + d * np.float32(W["z_in"])).astype(np.float32)})
+    o = oracle.run(bent, W, lib=lib)
+    n = 0
+    for t in np.nonzero(o["found"])[0]:
+        p, q, tx, ty = particle(ev, t)
+        assert abs(float(o["ty"][t]) - ty) < 2e-5, (t, o["ty"][t], ty)
+        assert abs(float(o["y0"][t]) - ty * oracle.Z_REF) < 0.1
+        n += 1
+    assert n >= 30
+
+
+def pin_physics_single(lib=None):
+    """Single-event workload (p > 5 GeV): efficiency >= 90% and q/p resolution
+    below 1% (the paper's headline physics claims), ghost rate <= 10%."""
+    ev = ev_single()
+    o = oracle.run(ev, W, lib=lib)
+    ph = truth.physics(ev, o, p_min=5.0)
+    assert ph["efficiency"] >= 0.9, ph
+    assert ph["qop_resolution"] < 0.01, ph
+    assert ph["ghost_rate"] <= 0.1, ph
+
+
+def check_invariants(ev, o, NT=12):
+    tev = ev.track_event()
+    for t in np.nonzero(o["found"])[0]:
+        hits = o["hit_idx"][t]
+        n = int((hits >= 0).sum())
+        assert n == int(o["n_hits"][t]) and 9 <= n <= 12
+        for st in range(3):
+            assert hits[4 * st + 1] >= 0 or hits[4 * st + 2] >= 0
+        zone = 1 if ev.trk_ty[t] >= 0 else 0
+        base = int(ev.hit_off[24 * tev[t]])
+        for l in range(NL):
+            h = int(hits[l])
+            if h < 0:
+                continue
+            b = 24 * tev[t] + 2 * l + zone
+            assert ev.hit_off[b] <= base + h < ev.hit_off[b + 1], "hit outside its layer/zone bucket"
+            if "win" in o:
+                assert o["win"][t, l, 0] <= h < o["win"][t, l, 1], "hit outside its window"
+        assert o["Q"][t] < 0.5
+        assert abs(float(o["ty"][t]) - float(ev.trk_ty[t])) <= 0.02 + 1e-6
+    if "trip" in o:
+        assert (o["trip"].shape[1] == NT)
+        for t in range(ev.n_tracks):
+            ch = o["trip_chi2"][t]
+            ch = ch[~np.isnan(ch)]
+            assert np.all(ch < 8.0) and np.all(np.diff(ch) >= 0)
+            assert len(ch) == min(NT, int(o["counts"][t, 2]))
+
+
+def pin_invariants(lib=None):
+    """Structural invariants of every output, on nominal and stress events."""
+    for ev in (ev_nominal(1), ev_stress()):
+        o = oracle.run(ev, W, debug=True, lib=lib)
+        assert o["found"].sum() > 0
+        check_invariants(ev, o)
+
+
+def pin_batch_independence(lib=None):
+    """Each event's result is the same alone, in a batch, and in another order."""
+    ev = ev_nominal(2)
+    o = oracle.run(ev, W, lib=lib)
+    rev = lfgen.select_events(ev, [1, 0])
+    orv = oracle.run(rev, W, lib=lib)
+    n0 = int(ev.trk_off[1])
+    n1 = ev.n_tracks - n0
+    for k in ("found", "hit_idx", "a", "b", "c", "y0", "ty", "qop", "Q"):
+        assert np.array_equal(o[k][:n0], orv[k][n1:]), k
+        assert np.array_equal(o[k][n0:], orv[k][:n1]), k
+
+
+def make_event(bucket_hits: dict, tracks: list) -> "lfgen.Events":
+    """A one-event batch from hand-placed hits: {(layer, zone): [x, ...]} and
+    tracks [(x, y, tx, ty, qop), ...] (hits get the layer's z and stereo)."""
+    xs, zs, ds, off = [], [], [], [0]
+    for b in range(24):
+        l, zone = divmod(b, 2)
+        v = sorted(bucket_hits.get((l, zone), []))
+        xs += v
+        zs += [W["z"][l]] * len(v)
+        ds += [W["dxdy"][l]] * len(v)
+        off.append(len(xs))
+    tr = np.array(tracks, np.float32).reshape(-1, 5)
+    z = np.zeros(0, np.float32)
+    return lfgen.Events(
+        n_events=1, hit_off=np.array(off, np.uint32), hit_x=np.array(xs, np.float32),
+        hit_z=np.array(zs, np.float32), hit_dxdy=np.array(ds, np.float32),
+        hit_pid=np.full(len(xs), -1, np.int32), trk_off=np.array([0, len(tr)], np.uint32),
+        trk_x=tr[:, 0].copy(), trk_y=tr[:, 1].copy(), trk_tx=tr[:, 2].copy(), trk_ty=tr[:, 3].copy(),
+        trk_qop=tr[:, 4].copy(), trk_pid=np.full(len(tr), -1, np.int32), par_off=np.zeros(2, np.uint32),
+        par_p=z, par_q=z, par_tx=z, par_ty=z, par_mask=np.zeros(0, np.uint16),
+        par_has_track=np.zeros(0, np.uint8))
+
+
+def pin_tie_breaks(lib=None):
+    """Equal chi2 is ordered by (set, h0, h2) and the closest-hit search keeps
+    the lowest index: a straight line at x = 100 with K = 1 gives chi2 = 0 for
+    every combination, with duplicated hits in layers 0, 4 and 8."""
+    hits = {(l, 1): [100.0] for l in X_LAYERS}
+    for l in (0, 4, 8):
+        hits[(l, 1)] = [100.0, 100.0]
+    ev = make_event(hits, [(100.0, 270.0, 0.0, 0.1, 1.0 / 50.0)])
+    o = oracle.run(ev, W, params={"K_first": 1.0, "K_last": 1.0, "n_triplets": 8}, debug=True, lib=lib)
+    off = [int(v) for v in ev.hit_off]
+    L = lambda l, k=0: off[2 * l + 1] + k
+    expect = [(0, L(0), L(4), L(8)), (0, L(0), L(4), L(8, 1)), (0, L(0, 1), L(4), L(8)),
+              (0, L(0, 1), L(4), L(8, 1)), (1, L(3), L(7), L(11))]
+    got = [tuple(int(v) for v in o["trip"][0, r]) for r in range(8) if o["trip"][0, r, 0] >= 0]
+    assert got == expect, (got, expect)
+    assert np.all(o["trip_chi2"][0, :5] == 0.0)
+
+
+def pin_extension_rule(lib=None):
+    """Each candidate adds, per missing layer, the closest window hit to the
+    triplet's parabola (float64, through the three seed hits) exactly when its
+    squared distance is below T_x (x layers) or T_uv (u/v layers, hit moved
+    along its fibre to the input track's y)."""
+    # nominal tracks, and shallow tracks (|tx| + |ty| < 0.04, where the 2 mm^2
+    # floor of T_uv applies) with coarse hit resolution
+    shallow = lfgen.generate("single", seed=13, tx_max=0.02, ty_max=0.02, sigma_x=0.5, p_min=5.0)
+    for ev in (ev_nominal(1), shallow):
+        n_add, n_rej = _extension_rule(ev, lib)
+        assert n_add > 100 and n_rej > 20, (n_add, n_rej)
+
+
+def _extension_rule(ev, lib):
+    o = oracle.run(ev, W, debug=True, lib=lib)
+    X, Z, D = (a.astype(np.float64) for a in (ev.hit_x, ev.hit_z, ev.hit_dxdy))
+    n_add = n_rej = 0
+    for t in range(min(ev.n_tracks, 120)):
+        T_uv = max(2.0, 50.0 * (abs(float(ev.trk_tx[t])) + abs(float(ev.trk_ty[t]))))
+        for r in range(o["trip"].shape[1]):
+            s, h0, h1, h2 = (int(v) for v in o["trip"][t, r])
+            if s < 0:
+                break
+            u = Z[[h0, h1, h2]] - oracle.Z_REF
+            coef = np.linalg.solve(np.stack([np.ones(3), u, u * u], 1), X[[h0, h1, h2]])
+            cand = o["cand_hits"][t, r]
+            for l in range(NL):
+                if l in SEED_SETS[s]:
+                    assert cand[l] == (h0, h1, h2)[SEED_SETS[s].index(l)]
+                    continue
+                ul = W["z"][l] - oracle.Z_REF
+                pred = coef[0] + coef[1] * ul + coef[2] * ul * ul
+                f, e = int(o["win"][t, l, 0]), int(o["win"][t, l, 1])
+                if l in X_LAYERS:
+                    d = np.abs(X[f:e] - pred)
+                    T = 2.0
+                else:
+                    y = float(ev.trk_y[t]) + float(ev.trk_ty[t]) * (W["z"][l] - W["z_in"])
+                    d = np.abs(X[f:e] + D[f:e] * y - pred)
+                    T = T_uv
+                dmin = float(d.min()) if e > f else np.inf
+                h = int(cand[l])
+                if h >= 0:
+                    assert f <= h < e
+                    assert d[h - f] <= dmin + 1e-4 and d[h - f] ** 2 < T + 1e-3, (t, r, l, d[h - f], T)
+                    n_add += 1
+                else:
+                    assert dmin ** 2 >= T - 1e-3, (t, r, l, dmin, T)
+                    n_rej += 1
+    return n_add, n_rej
+
+
+def pin_nine_hit_tracks(lib=None):
+    """A noise-free particle with exactly 9 hits (a complete seed set and a
+    u/v hit per station) is found with exactly those 9 hits."""
+    ev = lfgen.generate("single", seed=14, sigma_x=0.0, qop_sigma=0.0, hit_eff=0.75, n_noise=0,
+                        n_particles=80, p_min=5.0)
+    o = oracle.run(ev, W, lib=lib)
+    n = 0
+    for t in range(ev.n_tracks):
+        th = [truth_hit(ev, t, l) for l in range(NL)]
+        if sum(h >= 0 for h in th) != 9:
+            continue
+        if not all(th[4 * s + 1] >= 0 or th[4 * s + 2] >= 0 for s in range(3)):
+            continue
+        if not any(all(th[l] >= 0 for l in st) for st in SEED_SETS):
+            continue
+        assert o["found"][t], t
+        # another particle's hit may join within tolerance; the 9 own hits must be there
+        assert all(o["hit_idx"][t][l] == th[l] for l in range(NL) if th[l] >= 0), t
+        n += int(o["n_hits"][t]) == 9
+    assert n >= 3, n
+
+
+ALL_PINS = [pin_constants, pin_extrapolation_noise_free, pin_window_bounds, pin_window_search,
+            pin_window_edges_closed, pin_triplet_closed_form, pin_magnet_threshold,
+            pin_charge_filter, pin_bruteforce_triplets, pin_fit_noise_free, pin_fit_lstsq,
+            pin_y_fit_recovers_slope, pin_physics_single, pin_invariants, pin_batch_independence,
+            pin_tie_breaks, pin_extension_rule, pin_nine_hit_tracks]
