@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Throughput of Looking Forward track following on one MI355X.
+
+Workload: the nominal batch -- 1,000 synthetic events, each with 350
+particles (p 2-100 GeV, pt > 0.3 GeV), 200 upstream input tracks (170 true,
+30 fake) and ~5.4k SciFi hits -- resident in HBM.  One step is one pass of
+the whole hot path (windows, triplet seeding, extension, fits, selection,
+momentum) over the batch.  ``value`` is events/s of the batched persistent
+launch; the per-event-launch (plain) and one-wave-per-track (grid) modes are
+reported beside it, with identical output.
+
+Roofline: the path is bound by plain VALU arithmetic (binary32 and integer,
+no FMA contraction, no packed math, no dense contraction), so the dominant
+kernel is reported against the non-packed VALU issue rate of the chip.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Peak VALU lane-operations per second without FMA or packed FP32:
+# 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+# Algorithmic VALU lane-operations per input track of the nominal workload:
+# ~1,160 (windows) + 17 x 1,288 doublet pairs + 81 x 22.0 filtered doublets
+# + 20 x 7.5 triplets + 1,273 x 6.9 kept candidates (model, extension scans)
+# + 514 x 2.45 accepted fits; work-unit means measured on this workload.
+OPS_PER_TRACK = 35.0e3
+# Algorithmic HBM bytes per event of the nominal workload: 12 B per hit in
+# (x, z, dxdy), 20 B per input track in, 78 B per track out, offsets.
+BYTES_PER_HIT_IN = 12
+BYTES_PER_TRACK_IN = 20
+BYTES_PER_TRACK_OUT = 78
+WORKLOAD = "nominal"
+KERNEL = "k_persistent"
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum CPU time of the oracle baseline sample (0 disables it)")
+    ap.add_argument("--events", type=int, default=1000)
+    return ap.parse_args()
+
+
+def algorithmic_bytes(ev) -> int:
+    return (BYTES_PER_HIT_IN * ev.n_hits + BYTES_PER_TRACK_IN * ev.n_tracks + BYTES_PER_TRACK_OUT * ev.n_tracks
+            + 4 * (24 * ev.n_events + 1) + 4 * (ev.n_events + 1))
+
+
+def time_mode(lf, ctx, bid, mode, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        lf.lf_find_tracks(ctx, bid, mode, stream.cuda_stream)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        lf.lf_find_tracks(ctx, bid, mode, stream.cuda_stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(end) / steps, wall
+
+
+def cpu_baseline(ev, world, min_seconds):
+    """The oracle, as it stands, on the host: repeated passes over a sample
+    of the same workload until min_seconds of CPU time have elapsed."""
+    import oracle
+    oracle.build(force=False)
+    n_sample = min(ev.n_events, 250)
+    import lfgen
+    sub = lfgen.select_events(ev, range(n_sample))
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.run(sub, world)
+        done += n_sample
+        el = time.perf_counter() - t0
+        if el >= min_seconds:
+            break
+    return dict(value=done / el, unit="events/s", cores=1, kind="oracle",
+                sample=f"first {n_sample} events of the nominal batch, {done} events processed "
+                       f"single-threaded in {el:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); events are "
+              f"independent, so N GPUs would each take their own batches -- see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import lfgen
+    from paper_2402_14670_amd import lf
+
+    torch.cuda.set_device(0)
+    # an explicit stream: the library launches on it and the timing events are recorded on it
+    stream = torch.cuda.Stream()
+    world = lfgen.world()
+    ev = lfgen.generate(WORKLOAD, n_events=args.events)
+    print(f"bench: {ev.n_events} events, {ev.n_tracks} tracks, {ev.n_hits} hits", file=sys.stderr, flush=True)
+
+    ctx = lf.lf_create(world)
+    bid = lf.lf_upload_events(ctx, ev, stream.cuda_stream)
+    res = {}
+    for mode, steps, warm in (("batched", args.steps, args.warmup), ("grid", args.steps, args.warmup),
+                              ("plain", args.plain_steps, 1)):
+        ms, wall = time_mode(lf, ctx, bid, mode, steps, warm, stream)
+        res[mode] = ms
+        print(f"bench: {mode:8s} {ms:8.3f} ms/step  {ev.n_events / ms * 1e3:12.0f} events/s", file=sys.stderr,
+              flush=True)
+    out = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
+    lf.lf_destroy(ctx)
+
+    ms = res["batched"]
+    value = ev.n_events / (ms * 1e-3)
+    ops = OPS_PER_TRACK * ev.n_tracks
+    achieved = ops / (ms * 1e-3) / 1e12
+    nbytes = algorithmic_bytes(ev)
+    line = {
+        "metric": "events/s on 1 MI355X (batched persistent launch)",
+        "value": round(value, 1),
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",
+                   "events": ev.n_events, "input_tracks": ev.n_tracks, "hits": ev.n_hits,
+                   "n_hits_window": 32, "n_triplets": 12},
+        "modes": {m: {"ms_per_step": round(v, 4), "events_per_s": round(ev.n_events / v * 1e3, 1),
+                      "input_tracks_per_s": round(ev.n_tracks / v * 1e3, 1)} for m, v in res.items()},
+        "batched_over_plain": round(res["plain"] / ms, 2),
+        "found_tracks": int(out["found"].sum()),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                     "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                     "kernel": KERNEL, "ops_per_launch": ops,
+                     "hbm": {"algorithmic_bytes": nbytes, "achieved_GBs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                             "peak_GBs": HBM_PEAK_GBS,
+                             "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}},
+        "latency_ms": None,
+    }
+    if args.cpu_seconds > 0:
+        line["cpu_baseline"] = cpu_baseline(ev, world, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * lf.h -- Looking Forward track following on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the GPU library.  The method is the forward tracking step of
+ * "Looking Forward: A High-Throughput Track Following Algorithm for Parallel
+ * Architectures" (arXiv 2402.14670): each upstream (VELO-UT) track state is
+ * extended into the twelve SciFi layers (three stations of x-u-v-x layers,
+ * Context section) by
+ *   1. search windows in every layer from a pt-kick extrapolation
+ *      ("Defining the search windows"),
+ *   2. triplet seeding on x layers ("Triplet Seeding"),
+ *   3. extension to the remaining x and stereo layers ("Extending triplets
+ *      to other layers", track-fit model equation of the "Propagation" section),
+ *   4. least-squares fits and the quality factor Q ("Quality Filter",
+ *      C(n_hits) table), keeping the best candidate per input track,
+ * followed by the momentum and state computation ("Calculation of momentum
+ * and track states").  Every step runs in hand-written HIP kernels.
+ *
+ * Conventions
+ *  - Every call returns LF_OK (0) or a negative LF_ERR_* code; no exception
+ *    crosses the ABI and the library never exits the process.  After an
+ *    error, lf_last_error(ctx) describes it.
+ *  - Units are mm and GeV/c.  Arithmetic is IEEE binary32 (round to nearest
+ *    even, no contraction into FMA, correctly rounded division), evaluated in
+ *    a fixed order, so results do not depend on batch composition, event
+ *    order or launch configuration.
+ *  - A context is not thread-safe: use one per thread or serialise calls.
+ *  - hip_stream arguments take a hipStream_t (for instance a PyTorch stream
+ *    handle) or NULL for the context's own stream.  All streams run at the
+ *    default priority.
+ */
+#ifndef LF_H
+#define LF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LF_NLAYERS 12
+
+/* Opaque context, owned by the library (lf_create / lf_destroy). */
+typedef struct lf_ctx lf_ctx;
+
+enum {
+    LF_OK = 0,
+    LF_ERR_INVALID = -1,   /* bad argument or malformed batch (NaN/inf, q/p == 0, unsorted bucket, bad offsets) */
+    LF_ERR_TOO_LARGE = -2, /* the batch does not fit the context's device-memory budget */
+    LF_ERR_NOMEM = -3,     /* host or device allocation failed */
+    LF_ERR_DEVICE = -4,    /* a HIP runtime call failed */
+    LF_ERR_STATE = -5      /* unknown batch id, or a call out of order */
+};
+
+/* Execution modes of lf_find_tracks. */
+enum {
+    LF_MODE_PLAIN = 0,     /* one kernel launch per event */
+    LF_MODE_BATCHED = 1,   /* one persistent launch over the whole batch, (event, track) work queue */
+    LF_MODE_GRID = 2       /* one launch, one wavefront per input track (no queue) */
+};
+
+/* Detector and field description.  Layers 0..11 are three stations of
+ * x-u-v-x planes: x layers 0,3,4,7,8,11 and stereo layers 1,2,5,6,9,10
+ * (Context section).  The field enters through the pt-kick at z_mag with
+ * slope kick dtx = kick * q/p ("Defining the search windows") and the
+ * x(z) model of the "Propagation" section with residual curvature kappa*dtx
+ * about z_T and cubic term dRatio. */
+typedef struct {
+    float z[LF_NLAYERS];     /* z of each layer plane */
+    float dxdy[LF_NLAYERS];  /* stereo tangent (0 for x layers, +-tan 5 deg for u/v) */
+    float z_in;              /* z of the upstream track states */
+    float z_mag;             /* bending plane z_bending */
+    float z_ref;             /* reference plane of the track model (8520 mm) */
+    float z_T;               /* plane where the post-magnet slope is read for q/p */
+    float kick;              /* dtx = kick * q/p */
+    float kappa;             /* residual curvature per unit dtx */
+    float dRatio;            /* cubic term of x(z) */
+    int32_t polarity;        /* +1: q > 0 bends towards +x; -1 the opposite */
+} lf_geometry;
+
+/* Tunable parameters.  Defaults (lf_default_params) are the "Forward"
+ * column of the paper's table of tolerances and its C(n_hits) table, plus
+ * the readings the paper leaves open (magnet tolerance form, T_uv floor). */
+typedef struct {
+    float T_triplet;       /* middle-hit chi2 tolerance (mm^2), 8 */
+    float T_x;             /* x-layer extension chi2 tolerance (mm^2), 2 */
+    float T_uv_scale;      /* T_uv = T_uv_scale * (|tx| + |ty|), 50 */
+    float T_uv_floor;      /* lower bound of T_uv (mm^2), 2 */
+    float T_ty;            /* |ty_fit - ty_in| tolerance, 0.02 */
+    float T_y;             /* y residual normalisation (mm^2), 800 */
+    float T_Q;             /* quality factor cut, 0.5 */
+    float xtol_const;      /* x_tol = xtol_const + xtol_pscale / p: 150 mm */
+    float xtol_pscale;     /* 2000 mm GeV */
+    float xasym;           /* window asymmetry on the bending side, 100 mm */
+    float uv_halfwidth;    /* stereo-layer window half width, 800 mm */
+    float K_first;         /* middle-hit correction, first-layer set, 1.00177513 */
+    float K_last;          /* middle-hit correction, last-layer set, 1.00142634 */
+    float magtol_const;    /* magnet opening tolerance = const + pscale/p + txscale*|tx|, */
+    float magtol_pscale;   /*   clamped to [magtol_min, magtol_max]: 8 + 24/p + 20|tx| in [8, 40] mm */
+    float magtol_txscale;
+    float magtol_min;
+    float magtol_max;
+    float p_charge_cut;    /* below this p (GeV) the doublet must bend with the charge, 5 */
+    float C_nhits[4];      /* C(9), C(10), C(11), C(12): 5.0, 1.0, 0.8, 0.5 */
+    int32_t n_hits_window; /* hits kept per window (1..64), 32 */
+    int32_t n_triplets;    /* triplets kept per input track (1..32), 12 */
+} lf_params;
+
+/* A batch of events in host memory, ragged structure-of-arrays.  Hits are
+ * bucket-major: bucket b = 24*event + 2*layer + zone (zone 1 = y > 0 half,
+ * zone 0 = y < 0 half); hits of bucket b are [hit_off[b], hit_off[b+1]) with
+ * hit_off[0] == 0, and x is non-decreasing inside each bucket.  hit_x is the
+ * x of the fibre at y = 0, hit_z its z, hit_dxdy its stereo tangent.  Track
+ * states (x, y, tx, ty, q/p) are at z = z_in; tracks of event e are
+ * [trk_off[e], trk_off[e+1]).  The library copies everything; the caller
+ * keeps ownership of these buffers. */
+typedef struct {
+    uint32_t n_events;
+    const uint32_t *hit_off;   /* [24*n_events + 1] */
+    const float *hit_x, *hit_z, *hit_dxdy;
+    const uint32_t *trk_off;   /* [n_events + 1] */
+    const float *trk_x, *trk_y, *trk_tx, *trk_ty, *trk_qop;
+} lf_batch;
+
+/* Caller-allocated host output, one slot per input track (global track
+ * order of the batch).  hit_idx[12*t + layer] is an event-local hit index
+ * (index among the event's hits in bucket-major order) or -1.  a, b, c are
+ * x, dx/dz and the curvature coefficient at z_ref; y0, ty the y line at
+ * z_ref; qop the refined q/p; Q the quality factor.  Not-found tracks have
+ * found = 0, n_hits = 0, hit_idx = -1 and zero parameters. */
+typedef struct {
+    uint8_t *found, *n_hits;
+    int32_t *hit_idx;
+    float *a, *b, *c, *y0, *ty, *qop, *Q;
+} lf_tracks_out;
+
+/* Launch configuration of the kernels (lf_set_exec).  Zero fields keep the
+ * current value. */
+typedef struct {
+    int32_t waves_per_block;   /* 1, 2 or 4 wavefronts per workgroup */
+    int32_t items_per_grab;    /* tracks a wavefront takes per queue claim (batched mode), 1..16 */
+    int32_t blocks_per_cu;     /* persistent grid = blocks_per_cu * compute units (batched mode) */
+} lf_exec;
+
+/* Fills *p with the default parameters. */
+void lf_default_params(lf_params *p);
+
+/* Creates a context on the current HIP device.  Geometry and parameters are
+ * copied.  device_budget_bytes bounds the device memory of all resident
+ * batches (0 = no bound).  Errors: LF_ERR_INVALID (NULL pointers, parameters
+ * out of range), LF_ERR_DEVICE, LF_ERR_NOMEM. */
+int lf_create(const lf_geometry *geom, const lf_params *params, size_t device_budget_bytes,
+              lf_ctx **out);
+
+/* Validates a host batch without touching the device: LF_OK, or
+ * LF_ERR_INVALID with the reason in lf_last_error(NULL).  lf_upload_events
+ * runs the same checks. */
+int lf_check_batch(const lf_batch *batch);
+
+/* Validates a host batch, copies it to device memory (on hip_stream) and
+ * returns its id.  Input and output buffers of the batch stay resident until
+ * lf_fetch_tracks or lf_release_batch.  Errors: LF_ERR_INVALID (malformed
+ * batch; nothing is copied), LF_ERR_TOO_LARGE (over budget), LF_ERR_NOMEM,
+ * LF_ERR_DEVICE. */
+int lf_upload_events(lf_ctx *ctx, const lf_batch *batch, void *hip_stream, uint64_t *batch_id);
+
+/* Enqueues the whole hot path for a resident batch on hip_stream and
+ * returns without waiting.  mode is LF_MODE_PLAIN, LF_MODE_BATCHED or
+ * LF_MODE_GRID; all modes write identical results.  May be called again on
+ * the same batch (results are rewritten).  Errors: LF_ERR_STATE (unknown
+ * batch), LF_ERR_INVALID (mode), LF_ERR_DEVICE. */
+int lf_find_tracks(lf_ctx *ctx, uint64_t batch_id, int mode, void *hip_stream);
+
+/* Copies the results of a batch into caller buffers holding at least
+ * cap_tracks >= number of input tracks slots, waits for completion and
+ * frees the batch.  Errors: LF_ERR_STATE, LF_ERR_INVALID (NULL buffer or
+ * cap_tracks too small; the batch stays resident), LF_ERR_DEVICE. */
+int lf_fetch_tracks(lf_ctx *ctx, uint64_t batch_id, lf_tracks_out *out, size_t cap_tracks,
+                    void *hip_stream);
+
+/* Frees a resident batch without fetching it.  Errors: LF_ERR_STATE. */
+int lf_release_batch(lf_ctx *ctx, uint64_t batch_id);
+
+/* Sets the launch configuration used by later lf_find_tracks calls.
+ * Errors: LF_ERR_INVALID (value out of range). */
+int lf_set_exec(lf_ctx *ctx, const lf_exec *exec);
+
+/* Sizes of a resident batch.  Any output pointer may be NULL.
+ * Errors: LF_ERR_STATE. */
+int lf_batch_info(lf_ctx *ctx, uint64_t batch_id, uint32_t *n_events, uint32_t *n_tracks,
+                  uint32_t *n_hits, size_t *device_bytes);
+
+/* Device bytes held by resident batches. */
+size_t lf_device_bytes_in_use(const lf_ctx *ctx);
+
+/* Destroys the context and frees every resident batch.  NULL is ignored. */
+void lf_destroy(lf_ctx *ctx);
+
+/* Message of the last error on ctx ("" if none); valid until the next call
+ * on ctx.  With ctx == NULL, the last lf_create failure of this thread. */
+const char *lf_last_error(const lf_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,409 @@
+// lf_api.cpp -- C ABI of the Looking Forward GPU library (declared in
+// include/lf.h): contexts, batch validation and residency, launches and
+// result retrieval.  The numerical work is all in lf_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lf.h"
+#include "lf_internal.h"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Batch {
+    void *dmem = nullptr;
+    size_t bytes = 0;
+    lfk::DevBatch dev{};
+    uint32_t n_events = 0, n_tracks = 0, n_hits = 0;
+    std::vector<uint32_t> trk_off;  // host copy, for per-event launches
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct lf_ctx {
+    lf_geometry geom{};
+    lf_params params{};
+    lfk::KParams *d_params = nullptr;  // device copy of geometry + parameters
+    size_t budget = 0;
+    size_t used = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    lfk::ExecCfg exec{2, 1, 0, 0};
+    std::map<uint64_t, Batch> batches;
+    uint64_t next_id = 1;
+    std::string err;
+};
+
+namespace {
+
+int fail(lf_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg; else g_create_error = msg;
+    return code;
+}
+
+int hip_fail(lf_ctx *c, hipError_t e, const char *what) {
+    return fail(c, LF_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+hipStream_t pick(lf_ctx *c, void *s) { return s ? reinterpret_cast<hipStream_t>(s) : c->stream; }
+
+bool finitef(float v) { return std::isfinite(v); }
+
+int check_params(const lf_geometry *g, const lf_params *p, std::string &why) {
+    for (int l = 0; l < LF_NLAYERS; ++l)
+        if (!finitef(g->z[l]) || !finitef(g->dxdy[l])) { why = "geometry: non-finite layer z or dxdy"; return 0; }
+    const float gs[] = {g->z_in, g->z_mag, g->z_ref, g->z_T, g->kick, g->kappa, g->dRatio};
+    for (float v : gs) if (!finitef(v)) { why = "geometry: non-finite value"; return 0; }
+    if (g->kick == 0.0f) { why = "geometry: kick must be non-zero"; return 0; }
+    if (g->polarity != 1 && g->polarity != -1) { why = "geometry: polarity must be +1 or -1"; return 0; }
+    if (p->n_hits_window < 1 || p->n_hits_window > lfk::MAX_WINDOW) { why = "params: n_hits_window must be 1..64"; return 0; }
+    if (p->n_triplets < 1 || p->n_triplets > lfk::MAX_TRIPLETS) { why = "params: n_triplets must be 1..32"; return 0; }
+    const float ps[] = {p->T_triplet, p->T_x, p->T_uv_scale, p->T_uv_floor, p->T_ty, p->T_y, p->T_Q,
+                        p->xtol_const, p->xtol_pscale, p->xasym, p->uv_halfwidth, p->K_first, p->K_last,
+                        p->magtol_const, p->magtol_pscale, p->magtol_txscale, p->magtol_min, p->magtol_max,
+                        p->p_charge_cut, p->C_nhits[0], p->C_nhits[1], p->C_nhits[2], p->C_nhits[3]};
+    for (float v : ps) if (std::isnan(v)) { why = "params: NaN value"; return 0; }
+    return 1;
+}
+
+lfk::KParams to_kparams(const lf_geometry &g, const lf_params &p) {
+    lfk::KParams k{};
+    for (int l = 0; l < LF_NLAYERS; ++l) { k.z[l] = g.z[l]; k.dxdy[l] = g.dxdy[l]; }
+    k.z_in = g.z_in; k.z_mag = g.z_mag; k.z_ref = g.z_ref; k.z_T = g.z_T;
+    k.kick = g.kick; k.kappa = g.kappa; k.dRatio = g.dRatio; k.polarity = g.polarity;
+    k.T_triplet = p.T_triplet; k.T_x = p.T_x; k.T_uv_scale = p.T_uv_scale; k.T_uv_floor = p.T_uv_floor;
+    k.T_ty = p.T_ty; k.T_y = p.T_y; k.T_Q = p.T_Q;
+    k.xtol_const = p.xtol_const; k.xtol_pscale = p.xtol_pscale; k.xasym = p.xasym;
+    k.uv_halfwidth = p.uv_halfwidth; k.K_first = p.K_first; k.K_last = p.K_last;
+    k.magtol_const = p.magtol_const; k.magtol_pscale = p.magtol_pscale; k.magtol_txscale = p.magtol_txscale;
+    k.magtol_min = p.magtol_min; k.magtol_max = p.magtol_max; k.p_charge_cut = p.p_charge_cut;
+    for (int i = 0; i < 4; ++i) k.C_nhits[i] = p.C_nhits[i];
+    k.n_hits_window = p.n_hits_window; k.n_triplets = p.n_triplets;
+    return k;
+}
+
+// Host validation of a batch (see lf_batch in lf.h).
+int validate(const lf_batch *b, std::string &why) {
+    const uint32_t E = b->n_events;
+    if (!b->hit_off || !b->trk_off) { why = "batch: NULL offset array"; return 0; }
+    if (b->hit_off[0] != 0 || b->trk_off[0] != 0) { why = "batch: offsets must start at 0"; return 0; }
+    const size_t nb = (size_t)E * 24;
+    for (size_t i = 0; i < nb; ++i)
+        if (b->hit_off[i + 1] < b->hit_off[i]) { why = "batch: hit_off decreases at bucket " + std::to_string(i); return 0; }
+    for (size_t e = 0; e < E; ++e)
+        if (b->trk_off[e + 1] < b->trk_off[e]) { why = "batch: trk_off decreases at event " + std::to_string(e); return 0; }
+    const uint64_t H = b->hit_off[nb], T = b->trk_off[E];
+    if (H >= 0x7fffffffull || T >= 0x7fffffffull) { why = "batch: more than 2^31-1 hits or tracks"; return 0; }
+    if (H && (!b->hit_x || !b->hit_z || !b->hit_dxdy)) { why = "batch: NULL hit array"; return 0; }
+    if (T && (!b->trk_x || !b->trk_y || !b->trk_tx || !b->trk_ty || !b->trk_qop)) { why = "batch: NULL track array"; return 0; }
+    for (size_t i = 0; i < H; ++i)
+        if (!finitef(b->hit_x[i]) || !finitef(b->hit_z[i]) || !finitef(b->hit_dxdy[i])) {
+            why = "batch: non-finite hit " + std::to_string(i);
+            return 0;
+        }
+    for (size_t k = 0; k < nb; ++k)
+        for (uint32_t i = b->hit_off[k] + 1; i < b->hit_off[k + 1]; ++i)
+            if (b->hit_x[i] < b->hit_x[i - 1]) { why = "batch: bucket " + std::to_string(k) + " not sorted by x"; return 0; }
+    for (size_t t = 0; t < T; ++t) {
+        if (!finitef(b->trk_x[t]) || !finitef(b->trk_y[t]) || !finitef(b->trk_tx[t]) || !finitef(b->trk_ty[t]) ||
+            !finitef(b->trk_qop[t])) {
+            why = "batch: non-finite track state " + std::to_string(t);
+            return 0;
+        }
+        if (b->trk_qop[t] == 0.0f) { why = "batch: q/p == 0 for track " + std::to_string(t); return 0; }
+    }
+    return 1;
+}
+
+// Device layout of a batch: one allocation, every array 256-byte aligned.
+struct Layout {
+    size_t hit_off, hx, hz, hd, trk_off, trk_ev, tx, ty, ttx, tty, tqop;
+    size_t found, nhits, hit_idx, a, b, c, y0, ty_o, qop, Q, counter, total;
+};
+
+Layout layout(uint32_t E, uint32_t H, uint32_t T) {
+    Layout L{};
+    size_t o = 0;
+    auto put = [&](size_t bytes) { size_t at = o; o += align256(bytes ? bytes : 1); return at; };
+    L.hit_off = put(((size_t)E * 24 + 1) * 4);
+    L.hx = put((size_t)H * 4); L.hz = put((size_t)H * 4); L.hd = put((size_t)H * 4);
+    L.trk_off = put(((size_t)E + 1) * 4);
+    L.trk_ev = put((size_t)T * 4);
+    L.tx = put((size_t)T * 4); L.ty = put((size_t)T * 4); L.ttx = put((size_t)T * 4);
+    L.tty = put((size_t)T * 4); L.tqop = put((size_t)T * 4);
+    L.found = put(T); L.nhits = put(T); L.hit_idx = put((size_t)T * 48);
+    L.a = put((size_t)T * 4); L.b = put((size_t)T * 4); L.c = put((size_t)T * 4);
+    L.y0 = put((size_t)T * 4); L.ty_o = put((size_t)T * 4); L.qop = put((size_t)T * 4); L.Q = put((size_t)T * 4);
+    L.counter = put(8);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lf_default_params(lf_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    // Table of parameters and tolerances, "Forward" column.
+    p->T_triplet = 8.0f;
+    p->T_x = 2.0f;
+    p->T_uv_scale = 50.0f;
+    p->T_uv_floor = 2.0f;
+    p->T_ty = 0.02f;
+    p->T_y = 800.0f;
+    p->T_Q = 0.5f;
+    p->n_hits_window = 32;
+    p->n_triplets = 12;
+    // Search windows: x_tol = 150 mm + 2000 mm GeV / p, 100 mm asymmetry, +-800 mm on u/v.
+    p->xtol_const = 150.0f;
+    p->xtol_pscale = 2000.0f;
+    p->xasym = 100.0f;
+    p->uv_halfwidth = 800.0f;
+    // Middle-hit corrections of the two seed sets (Triplet Seeding).
+    p->K_first = 1.00177513f;
+    p->K_last = 1.00142634f;
+    // Magnet opening tolerance between 8 and 40 mm, function of p and the doublet slope.
+    p->magtol_const = 8.0f;
+    p->magtol_pscale = 24.0f;
+    p->magtol_txscale = 20.0f;
+    p->magtol_min = 8.0f;
+    p->magtol_max = 40.0f;
+    p->p_charge_cut = 5.0f;
+    // C(n_hits) table.
+    p->C_nhits[0] = 5.0f;
+    p->C_nhits[1] = 1.0f;
+    p->C_nhits[2] = 0.8f;
+    p->C_nhits[3] = 0.5f;
+}
+
+int lf_check_batch(const lf_batch *b) {
+    if (!b) return fail(nullptr, LF_ERR_INVALID, "lf_check_batch: NULL batch");
+    std::string why;
+    if (!validate(b, why)) return fail(nullptr, LF_ERR_INVALID, "lf_check_batch: " + why);
+    g_create_error.clear();
+    return LF_OK;
+}
+
+int lf_create(const lf_geometry *geom, const lf_params *params, size_t device_budget_bytes, lf_ctx **out) {
+    if (!geom || !params || !out) return fail(nullptr, LF_ERR_INVALID, "lf_create: NULL argument");
+    *out = nullptr;
+    std::string why;
+    if (!check_params(geom, params, why)) return fail(nullptr, LF_ERR_INVALID, "lf_create: " + why);
+    lf_ctx *c = new (std::nothrow) lf_ctx();
+    if (!c) return fail(nullptr, LF_ERR_NOMEM, "lf_create: out of host memory");
+    c->geom = *geom;
+    c->params = *params;
+    c->budget = device_budget_bytes;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    int ncu = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&c->d_params), sizeof(lfk::KParams));
+    if (e == hipSuccess) {
+        const lfk::KParams k = to_kparams(*geom, *params);
+        e = hipMemcpy(c->d_params, &k, sizeof(k), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        std::string msg = std::string("lf_create: ") + hipGetErrorString(e);
+        lf_destroy(c);
+        return fail(nullptr, LF_ERR_DEVICE, msg);
+    }
+    c->exec.n_cu = ncu;
+    c->exec.blocks_per_cu = lfk::persistent_blocks_per_cu(params->n_hits_window, c->exec.waves_per_block);
+    if (c->exec.blocks_per_cu < 1) c->exec.blocks_per_cu = 1;
+    *out = c;
+    return LF_OK;
+}
+
+int lf_set_exec(lf_ctx *c, const lf_exec *x) {
+    if (!c || !x) return LF_ERR_INVALID;
+    lfk::ExecCfg n = c->exec;
+    if (x->waves_per_block) {
+        if (x->waves_per_block != 1 && x->waves_per_block != 2 && x->waves_per_block != 4)
+            return fail(c, LF_ERR_INVALID, "lf_set_exec: waves_per_block must be 1, 2 or 4");
+        n.waves_per_block = x->waves_per_block;
+        n.blocks_per_cu = lfk::persistent_blocks_per_cu(c->params.n_hits_window, n.waves_per_block);
+        if (n.blocks_per_cu < 1) n.blocks_per_cu = 1;
+    }
+    if (x->items_per_grab) {
+        if (x->items_per_grab < 1 || x->items_per_grab > 16)
+            return fail(c, LF_ERR_INVALID, "lf_set_exec: items_per_grab must be 1..16");
+        n.items_per_grab = x->items_per_grab;
+    }
+    if (x->blocks_per_cu) {
+        if (x->blocks_per_cu < 1 || x->blocks_per_cu > 64)
+            return fail(c, LF_ERR_INVALID, "lf_set_exec: blocks_per_cu must be 1..64");
+        n.blocks_per_cu = x->blocks_per_cu;
+    }
+    c->exec = n;
+    return LF_OK;
+}
+
+int lf_upload_events(lf_ctx *c, const lf_batch *b, void *hip_stream, uint64_t *batch_id) {
+    if (!c) return LF_ERR_INVALID;
+    if (!b || !batch_id) return fail(c, LF_ERR_INVALID, "lf_upload_events: NULL argument");
+    std::string why;
+    if (!validate(b, why)) return fail(c, LF_ERR_INVALID, "lf_upload_events: " + why);
+    const uint32_t E = b->n_events, H = b->hit_off[(size_t)E * 24], T = b->trk_off[E];
+    const Layout L = layout(E, H, T);
+    if (c->budget && c->used + L.total > c->budget)
+        return fail(c, LF_ERR_TOO_LARGE, "lf_upload_events: batch needs " + std::to_string(L.total) +
+                                             " device bytes, " + std::to_string(c->budget - c->used) + " left");
+    Batch bt;
+    bt.bytes = L.total;
+    bt.n_events = E; bt.n_tracks = T; bt.n_hits = H;
+    try {
+        bt.trk_off.assign(b->trk_off, b->trk_off + E + 1);
+    } catch (...) {
+        return fail(c, LF_ERR_NOMEM, "lf_upload_events: out of host memory");
+    }
+    hipError_t e = hipMalloc(&bt.dmem, L.total);
+    if (e != hipSuccess) return fail(c, LF_ERR_NOMEM, std::string("lf_upload_events: hipMalloc: ") + hipGetErrorString(e));
+    char *base = static_cast<char *>(bt.dmem);
+    lfk::DevBatch &d = bt.dev;
+    d.hit_off = reinterpret_cast<const uint32_t *>(base + L.hit_off);
+    d.hx = reinterpret_cast<const float *>(base + L.hx);
+    d.hz = reinterpret_cast<const float *>(base + L.hz);
+    d.hd = reinterpret_cast<const float *>(base + L.hd);
+    d.trk_off = reinterpret_cast<const uint32_t *>(base + L.trk_off);
+    d.trk_ev = reinterpret_cast<const uint32_t *>(base + L.trk_ev);
+    d.tx_ = reinterpret_cast<const float *>(base + L.tx);
+    d.ty_ = reinterpret_cast<const float *>(base + L.ty);
+    d.ttx = reinterpret_cast<const float *>(base + L.ttx);
+    d.tty = reinterpret_cast<const float *>(base + L.tty);
+    d.tqop = reinterpret_cast<const float *>(base + L.tqop);
+    d.found = reinterpret_cast<uint8_t *>(base + L.found);
+    d.nhits = reinterpret_cast<uint8_t *>(base + L.nhits);
+    d.hit_idx = reinterpret_cast<int32_t *>(base + L.hit_idx);
+    d.a = reinterpret_cast<float *>(base + L.a);
+    d.b = reinterpret_cast<float *>(base + L.b);
+    d.c = reinterpret_cast<float *>(base + L.c);
+    d.y0 = reinterpret_cast<float *>(base + L.y0);
+    d.ty = reinterpret_cast<float *>(base + L.ty_o);
+    d.qop = reinterpret_cast<float *>(base + L.qop);
+    d.Q = reinterpret_cast<float *>(base + L.Q);
+    d.counter = reinterpret_cast<uint32_t *>(base + L.counter);
+    d.n_events = E;
+    d.n_tracks = T;
+    hipStream_t s = pick(c, hip_stream);
+    struct { size_t off; const void *src; size_t n; } cp[] = {
+        {L.hit_off, b->hit_off, ((size_t)E * 24 + 1) * 4}, {L.hx, b->hit_x, (size_t)H * 4},
+        {L.hz, b->hit_z, (size_t)H * 4}, {L.hd, b->hit_dxdy, (size_t)H * 4},
+        {L.trk_off, b->trk_off, ((size_t)E + 1) * 4}, {L.tx, b->trk_x, (size_t)T * 4},
+        {L.ty, b->trk_y, (size_t)T * 4}, {L.ttx, b->trk_tx, (size_t)T * 4},
+        {L.tty, b->trk_ty, (size_t)T * 4}, {L.tqop, b->trk_qop, (size_t)T * 4}};
+    for (auto &x : cp) {
+        if (!x.n) continue;
+        e = hipMemcpyAsync(base + x.off, x.src, x.n, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(d.counter, 0, 8, s);
+    if (e == hipSuccess) e = lfk::launch_track_event(d, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(bt.dmem);
+        return hip_fail(c, e, "lf_upload_events");
+    }
+    const uint64_t id = c->next_id++;
+    c->used += bt.bytes;
+    c->batches.emplace(id, std::move(bt));
+    *batch_id = id;
+    return LF_OK;
+}
+
+int lf_find_tracks(lf_ctx *c, uint64_t batch_id, int mode, void *hip_stream) {
+    if (!c) return LF_ERR_INVALID;
+    auto it = c->batches.find(batch_id);
+    if (it == c->batches.end()) return fail(c, LF_ERR_STATE, "lf_find_tracks: unknown batch id");
+    if (mode != LF_MODE_PLAIN && mode != LF_MODE_BATCHED && mode != LF_MODE_GRID)
+        return fail(c, LF_ERR_INVALID, "lf_find_tracks: unknown mode");
+    Batch &bt = it->second;
+    const hipError_t e = lfk::launch_find(bt.dev, c->d_params, c->params.n_hits_window, mode, c->exec,
+                                          bt.trk_off.data(), pick(c, hip_stream));
+    if (e != hipSuccess) return hip_fail(c, e, "lf_find_tracks");
+    return LF_OK;
+}
+
+int lf_fetch_tracks(lf_ctx *c, uint64_t batch_id, lf_tracks_out *out, size_t cap_tracks, void *hip_stream) {
+    if (!c) return LF_ERR_INVALID;
+    auto it = c->batches.find(batch_id);
+    if (it == c->batches.end()) return fail(c, LF_ERR_STATE, "lf_fetch_tracks: unknown batch id");
+    Batch &bt = it->second;
+    const size_t T = bt.n_tracks;
+    if (!out || cap_tracks < T) return fail(c, LF_ERR_INVALID, "lf_fetch_tracks: output capacity below track count");
+    if (T && (!out->found || !out->n_hits || !out->hit_idx || !out->a || !out->b || !out->c || !out->y0 ||
+              !out->ty || !out->qop || !out->Q))
+        return fail(c, LF_ERR_INVALID, "lf_fetch_tracks: NULL output array");
+    hipStream_t s = pick(c, hip_stream);
+    hipError_t e = hipSuccess;
+    if (T) {
+        const lfk::DevBatch &d = bt.dev;
+        struct { void *dst; const void *src; size_t n; } cp[] = {
+            {out->found, d.found, T}, {out->n_hits, d.nhits, T}, {out->hit_idx, d.hit_idx, T * 48},
+            {out->a, d.a, T * 4}, {out->b, d.b, T * 4}, {out->c, d.c, T * 4}, {out->y0, d.y0, T * 4},
+            {out->ty, d.ty, T * 4}, {out->qop, d.qop, T * 4}, {out->Q, d.Q, T * 4}};
+        for (auto &x : cp) {
+            e = hipMemcpyAsync(x.dst, x.src, x.n, hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) break;
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "lf_fetch_tracks");
+    (void)hipFree(bt.dmem);
+    c->used -= bt.bytes;
+    c->batches.erase(it);
+    return LF_OK;
+}
+
+int lf_release_batch(lf_ctx *c, uint64_t batch_id) {
+    if (!c) return LF_ERR_INVALID;
+    auto it = c->batches.find(batch_id);
+    if (it == c->batches.end()) return fail(c, LF_ERR_STATE, "lf_release_batch: unknown batch id");
+    // work on the batch may still be queued on any stream: wait for the device
+    const hipError_t e = hipDeviceSynchronize();
+    (void)hipFree(it->second.dmem);
+    c->used -= it->second.bytes;
+    c->batches.erase(it);
+    if (e != hipSuccess) return hip_fail(c, e, "lf_release_batch");
+    return LF_OK;
+}
+
+int lf_batch_info(lf_ctx *c, uint64_t batch_id, uint32_t *n_events, uint32_t *n_tracks, uint32_t *n_hits,
+                  size_t *device_bytes) {
+    if (!c) return LF_ERR_INVALID;
+    auto it = c->batches.find(batch_id);
+    if (it == c->batches.end()) return fail(c, LF_ERR_STATE, "lf_batch_info: unknown batch id");
+    if (n_events) *n_events = it->second.n_events;
+    if (n_tracks) *n_tracks = it->second.n_tracks;
+    if (n_hits) *n_hits = it->second.n_hits;
+    if (device_bytes) *device_bytes = it->second.bytes;
+    return LF_OK;
+}
+
+size_t lf_device_bytes_in_use(const lf_ctx *c) { return c ? c->used : 0; }
+
+void lf_destroy(lf_ctx *c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : c->batches) (void)hipFree(kv.second.dmem);
+    if (c->d_params) (void)hipFree(c->d_params);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char *lf_last_error(const lf_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+// lf_internal.h -- structures shared by the host side (lf_api.cpp) and the
+// kernels (lf_kernels.hip) of the GPU library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lfk {
+
+constexpr int NL = 12;
+constexpr int MAX_WINDOW = 64;    // n_hits_window upper bound (6-bit window-relative indices)
+constexpr int MAX_TRIPLETS = 32;  // n_triplets upper bound
+
+// Geometry and parameters, passed to every kernel by value.
+struct KParams {
+    float z[NL], dxdy[NL];
+    float z_in, z_mag, z_ref, z_T, kick, kappa, dRatio;
+    int32_t polarity;
+    float T_triplet, T_x, T_uv_scale, T_uv_floor, T_ty, T_y, T_Q;
+    float xtol_const, xtol_pscale, xasym, uv_halfwidth, K_first, K_last;
+    float magtol_const, magtol_pscale, magtol_txscale, magtol_min, magtol_max, p_charge_cut;
+    float C_nhits[4];
+    int32_t n_hits_window, n_triplets;
+};
+
+// Device view of one resident batch (SoA, all in HBM).
+struct DevBatch {
+    const uint32_t *hit_off;   // [24*E+1]
+    const float *hx, *hz, *hd; // [H]
+    const uint32_t *trk_off;   // [E+1]
+    const uint32_t *trk_ev;    // [T] event of each track
+    const float *tx_, *ty_, *ttx, *tty, *tqop;  // [T]
+    uint8_t *found, *nhits;    // [T]
+    int32_t *hit_idx;          // [12*T]
+    float *a, *b, *c, *y0, *ty, *qop, *Q;  // [T]
+    uint32_t *counter;         // [2] work-queue head and exited-wave count (batched mode), zero between launches
+    uint32_t n_events, n_tracks;
+};
+
+struct ExecCfg {
+    int waves_per_block;
+    int items_per_grab;
+    int blocks_per_cu;
+    int n_cu;
+};
+
+// Fills trk_ev from trk_off (one thread per track).
+hipError_t launch_track_event(const DevBatch &b, hipStream_t s);
+// The hot path.  P points to a KParams in device memory.  mode: 0 plain
+// (per-event launches), 1 persistent queue, 2 one wavefront per track.
+// trk_off_host is read by mode 0 only.
+hipError_t launch_find(const DevBatch &b, const KParams *P, int n_hits_window, int mode,
+                       const ExecCfg &cfg, const uint32_t *trk_off_host, hipStream_t s);
+// Resident blocks per compute unit of the persistent kernel (0 on error).
+int persistent_blocks_per_cu(int n_hits_window, int waves_per_block);
+
+}  // namespace lfk

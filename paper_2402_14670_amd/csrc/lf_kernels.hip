@@ -1,0 +1,640 @@
+// lf_kernels.hip -- Looking Forward track following, gfx950 kernels.
+//
+// One wavefront (64 lanes) carries one upstream input track through every
+// step of the method (arXiv 2402.14670, "Algorithm logic"):
+//
+//   windows    36 lanes: (layer, bound) binary searches over the x-sorted
+//              bucket in HBM; 12 lanes apply the symmetric cap
+//              ("Defining the search windows").
+//   staging    the <= 12 x n_hits_window window hits (x, z, dxdy) are read
+//              coalesced from HBM into this wave's LDS slice.
+//   doublets   all (h0, h2) pairs of both seed sets, one pair per lane,
+//              filtered by charge and magnet opening; survivors compacted
+//              with ballot + mbcnt into an LDS queue ("Triplet Seeding").
+//   triplets   64 queued doublets per pass search the middle layer for the
+//              closest hit; accepted triplets merge into an exact top-n list
+//              keyed by (chi2, set, h0, h2) by rank counting.
+//   extension  lanes = (candidate, missing layer): closest hit to the
+//              triplet's x(z) model ("Extending triplets to other layers").
+//   fit        one lane per candidate: x and y least squares, Q, cuts
+//              ("Quality Filter"); wave argmin over (Q, rank) picks the
+//              track; q/p from the slope change ("Calculation of momentum").
+//
+// The arithmetic is binary32 in a fixed order (the library is built with
+// -ffp-contract=off, correctly rounded division, no fast-math), so every
+// decision is identical to a serial evaluation of the same expressions.
+// Nothing in this file allocates; all scratch is LDS.
+#include "lf_internal.h"
+
+namespace lfk {
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int QCAP = 128;             // doublet queue: < 64 pending + one pass of 64
+constexpr int NSLOT = 9;              // extension work per candidate: 3 x layers + 6 u/v layers
+constexpr float INV1024 = 0.0009765625f;            // 2^-10, exact
+constexpr float INV1024SQ = 0.00000095367431640625f; // 2^-20, exact
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ bool is_uv(int l) {
+    const int k = l & 3;
+    return k == 1 || k == 2;
+}
+
+// x(z) model term g(u) = u^2 (1 + dRatio u), u = z - z_ref.
+__device__ __forceinline__ float g_of(float u, float dR) { return u * u * (1.0f + dR * u); }
+
+template <int NW>
+struct WaveLds {
+    float wx[NL][NW];          // window hits: x at y = 0
+    float wz[NL][NW];          //              z
+    float wd[NL][NW];          //              stereo tangent
+    int32_t wfirst[NL];        // event-local index of each window's first hit
+    int32_t wlen[NL];
+    uint32_t qkey[QCAP];       // queued doublets: set << 16 | i0 << 8 | i2
+    float qtx[QCAP];           //                  their slope
+    uint64_t tk[2][MAX_TRIPLETS];   // top-n keys (double buffered), sorted
+    uint8_t th1[2][MAX_TRIPLETS];   // middle hit of each kept triplet
+    uint64_t bk[WAVE];         // triplets of the current pass
+    uint8_t bh1[WAVE];
+    float ca[MAX_TRIPLETS], cb[MAX_TRIPLETS], cc[MAX_TRIPLETS];  // triplet x(z) models
+    int8_t ch[MAX_TRIPLETS][NL];    // candidate hits, window-relative, -1 = none
+};
+
+template <int NW>
+struct Track {
+    const DevBatch &B;
+    const KParams *__restrict__ P;
+    WaveLds<NW> &L;
+    int nL;    // kept triplets
+    int buf;   // live half of the top-n double buffer
+
+    // Merge this pass's accepted triplets (one per lane) into the top-n list.
+    __device__ void merge(bool valid, uint64_t key, int h1) {
+        const int lane = lane_id();
+        const uint64_t bal = __ballot(valid);
+        const int nb = __popcll(bal);
+        if (nb == 0) return;
+        if (valid) {
+            const int pos = lanes_below(bal);
+            L.bk[pos] = key;
+            L.bh1[pos] = (uint8_t)h1;
+        }
+        wave_sync();
+        const int NT = P->n_triplets;
+        const int nu = nL + nb;
+        for (int j = lane; j < nu; j += WAVE) {
+            uint64_t kj;
+            uint8_t hj;
+            if (j < nL) { kj = L.tk[buf][j]; hj = L.th1[buf][j]; }
+            else { kj = L.bk[j - nL]; hj = L.bh1[j - nL]; }
+            int rank = 0;
+            for (int i = 0; i < nL; ++i) rank += L.tk[buf][i] < kj ? 1 : 0;
+            for (int i = 0; i < nb; ++i) rank += L.bk[i] < kj ? 1 : 0;
+            if (rank < NT) {
+                L.tk[buf ^ 1][rank] = kj;
+                L.th1[buf ^ 1][rank] = hj;
+            }
+        }
+        nL = nu < NT ? nu : NT;
+        buf ^= 1;
+        wave_sync();
+    }
+
+    // Complete the first `count` queued doublets with their closest middle hit.
+    __device__ void flush(int count) {
+        const int lane = lane_id();
+        bool valid = false;
+        uint64_t key = 0;
+        int best = -1;
+        if (lane < count) {
+            const uint32_t e = L.qkey[lane];
+            const float txd = L.qtx[lane];
+            const int s = (int)(e >> 16), i0 = (int)((e >> 8) & 0xffu), i2 = (int)(e & 0xffu);
+            const int l0 = s ? 3 : 0, l1 = s ? 7 : 4;
+            const float K = s ? P->K_last : P->K_first;
+            const float x0 = L.wx[l0][i0], z0 = L.wz[l0][i0];
+            const float x1e = P->z[l1] * txd + (x0 - txd * z0) * K;
+            float bd = INFINITY;
+            const int n1 = L.wlen[l1];
+            for (int j = 0; j < n1; ++j) {
+                const float d = fabsf(L.wx[l1][j] - x1e);
+                if (d < bd) { bd = d; best = j; }
+            }
+            if (best >= 0) {
+                const float chi2 = bd * bd;
+                if (chi2 < P->T_triplet) {
+                    valid = true;
+                    key = ((uint64_t)__float_as_uint(chi2) << 32) |
+                          (uint64_t)(uint32_t)((s << 12) | (i0 << 6) | i2);
+                }
+            }
+        }
+        merge(valid, key, best);
+    }
+
+    __device__ void run(uint32_t t, uint32_t ev) {
+        const int lane = lane_id();
+        const float x_in = B.tx_[t], y_in = B.ty_[t], tx_in = B.ttx[t], ty_in = B.tty[t];
+        const float qop = B.tqop[t];
+        const float dR = P->dRatio;
+
+        // ---- kinematics, pt-kick extrapolation ----
+        const float p = 1.0f / fabsf(qop);
+        const int q = qop > 0.0f ? 1 : -1;
+        const int zone = ty_in >= 0.0f ? 1 : 0;
+        const float x_mag = x_in + tx_in * (P->z_mag - P->z_in);
+        const float dtx = P->kick * qop;
+        const float T = tx_in + dtx;
+        const float kd = P->kappa * dtx;
+        const uint32_t ebase = B.hit_off[ev * 24u];
+
+        // ---- search windows: lane 3*l + k searches bound k of layer l ----
+        int pos = 0;
+        if (lane < 3 * NL) {
+            const int l = lane / 3, k = lane - 3 * (lane / 3);
+            const float dz = P->z[l] - P->z_mag;
+            const float dzT = P->z[l] - P->z_T;
+            const float xe = x_mag + T * dz + kd * dzT * dzT;
+            const float ye = y_in + ty_in * (P->z[l] - P->z_in);
+            float xc, xmin, xmax;
+            if (is_uv(l)) {
+                xc = xe - P->dxdy[l] * ye;
+                xmin = xc - P->uv_halfwidth;
+                xmax = xc + P->uv_halfwidth;
+            } else {
+                const float xtol = P->xtol_const + P->xtol_pscale / p;
+                float asymL = 0.0f, asymR = 0.0f;
+                if (q * P->polarity > 0) asymR = P->xasym; else asymL = P->xasym;
+                xc = xe;
+                xmin = xc - xtol - asymL;
+                xmax = xc + xtol + asymR;
+            }
+            const float key = k == 0 ? xmin : (k == 1 ? xc : xmax);
+            const uint32_t b = ev * 24u + 2u * (uint32_t)l + (uint32_t)zone;
+            uint32_t lo = B.hit_off[b];
+            uint32_t n = B.hit_off[b + 1] - lo;
+            // lower bound (x < key) for x_min and the centre, upper bound (x <= key) for x_max
+            while (n > 0) {
+                const uint32_t half = n >> 1;
+                const float v = B.hx[lo + half];
+                const bool right = k == 2 ? (v <= key) : (v < key);
+                if (right) { lo += half + 1; n -= half + 1; } else { n = half; }
+            }
+            pos = (int)(lo - ebase);
+        }
+        {
+            const int src = lane < NL ? 3 * lane : 0;
+            const int lo = __shfl(pos, src), c0 = __shfl(pos, src + 1), hi0 = __shfl(pos, src + 2);
+            if (lane < NL) {
+                int hi = hi0 < lo ? lo : hi0;
+                int c = c0 < lo ? lo : (c0 > hi ? hi : c0);
+                const int N = P->n_hits_window;
+                int first = lo, len = hi - lo;
+                if (hi - lo > N) {
+                    first = c - N / 2;
+                    if (first < lo) first = lo;
+                    if (first > hi - N) first = hi - N;
+                    len = N;
+                }
+                L.wfirst[lane] = first;
+                L.wlen[lane] = len;
+            }
+        }
+        wave_sync();
+
+        // ---- stage window hits into LDS ----
+        for (int it = lane; it < NL * NW; it += WAVE) {
+            const int l = it / NW, j = it - NW * (it / NW);
+            if (j < L.wlen[l]) {
+                const uint32_t g = ebase + (uint32_t)(L.wfirst[l] + j);
+                L.wx[l][j] = B.hx[g];
+                L.wz[l][j] = B.hz[g];
+                L.wd[l][j] = B.hd[g];
+            }
+        }
+        wave_sync();
+
+        // ---- doublets of both seed sets, filtered, queued; triplets by passes ----
+        nL = 0;
+        buf = 0;
+        const float tolc = P->magtol_const + P->magtol_pscale / p;
+        const bool low_p = p < P->p_charge_cut;
+        int qn = 0;
+        for (int s = 0; s < 2; ++s) {
+            const int l0 = s ? 3 : 0, l2 = s ? 11 : 8;
+            const int n0 = L.wlen[l0], n2 = L.wlen[l2];
+            const int total = n0 * n2;
+            if (total == 0) continue;
+            // i0 = idx / n2 by multiply-shift: exact for idx < 2^20 / n2 (idx < 4096, n2 <= 64)
+            const uint32_t m = ((1u << 20) + (uint32_t)n2 - 1u) / (uint32_t)n2;
+            for (int base = 0; base < total; base += WAVE) {
+                const int idx = base + lane;
+                bool pass = false;
+                float txd = 0.0f;
+                int i0 = 0, i2 = 0;
+                if (idx < total) {
+                    i0 = (int)(((uint32_t)idx * m) >> 20);
+                    i2 = idx - i0 * n2;
+                    const float x0 = L.wx[l0][i0], z0 = L.wz[l0][i0];
+                    const float x2 = L.wx[l2][i2], z2 = L.wz[l2][i2];
+                    txd = (x2 - x0) / (z2 - z0);
+                    pass = !(low_p && !((txd - tx_in) * qop > 0.0f));
+                    const float xm = x0 + txd * (P->z_mag - z0);
+                    float tol = tolc + P->magtol_txscale * fabsf(txd);
+                    if (tol < P->magtol_min) tol = P->magtol_min;
+                    if (tol > P->magtol_max) tol = P->magtol_max;
+                    if (!(fabsf(xm - x_mag) < tol)) pass = false;
+                }
+                const uint64_t bal = __ballot(pass);
+                if (pass) {
+                    const int at = qn + lanes_below(bal);
+                    L.qkey[at] = ((uint32_t)s << 16) | ((uint32_t)i0 << 8) | (uint32_t)i2;
+                    L.qtx[at] = txd;
+                }
+                qn += __popcll(bal);
+                if (qn >= WAVE) {
+                    wave_sync();
+                    flush(WAVE);
+                    const int rest = qn - WAVE;
+                    uint32_t k2 = 0;
+                    float t2 = 0.0f;
+                    if (lane < rest) { k2 = L.qkey[WAVE + lane]; t2 = L.qtx[WAVE + lane]; }
+                    wave_sync();
+                    if (lane < rest) { L.qkey[lane] = k2; L.qtx[lane] = t2; }
+                    qn = rest;
+                    wave_sync();
+                }
+            }
+        }
+        if (qn > 0) {
+            wave_sync();
+            flush(qn);
+        }
+
+        const size_t o12 = (size_t)t * NL;
+        if (nL == 0) {
+            write_none(t, o12);
+            return;
+        }
+
+        // ---- triplet x(z) models ----
+        if (lane < nL) {
+            const uint32_t lo = (uint32_t)L.tk[buf][lane];
+            const int s = (int)((lo >> 12) & 1u), i0 = (int)((lo >> 6) & 63u), i2 = (int)(lo & 63u);
+            const int i1 = L.th1[buf][lane];
+            const int l0 = s ? 3 : 0, l1 = s ? 7 : 4, l2 = s ? 11 : 8;
+            const float u0 = L.wz[l0][i0] - P->z_ref, u1 = L.wz[l1][i1] - P->z_ref, u2 = L.wz[l2][i2] - P->z_ref;
+            const float X0 = L.wx[l0][i0], X1 = L.wx[l1][i1], X2 = L.wx[l2][i2];
+            const float g0 = g_of(u0, dR), g1 = g_of(u1, dR), g2 = g_of(u2, dR);
+            const float s01 = (X1 - X0) / (u1 - u0);
+            const float s12 = (X2 - X1) / (u2 - u1);
+            const float G01 = (g1 - g0) / (u1 - u0);
+            const float G12 = (g2 - g1) / (u2 - u1);
+            const float c = (s12 - s01) / (G12 - G01);
+            const float b = s01 - c * G01;
+            const float a = X0 - b * u0 - c * g0;
+            L.ca[lane] = a;
+            L.cb[lane] = b;
+            L.cc[lane] = c;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) L.ch[lane][l] = -1;
+            L.ch[lane][l0] = (int8_t)i0;
+            L.ch[lane][l1] = (int8_t)i1;
+            L.ch[lane][l2] = (int8_t)i2;
+        }
+        wave_sync();
+
+        // ---- extension: lanes = (candidate, missing layer) ----
+        const float T_uv0 = P->T_uv_scale * (fabsf(tx_in) + fabsf(ty_in));
+        const float T_uv = T_uv0 < P->T_uv_floor ? P->T_uv_floor : T_uv0;
+        for (int it = lane; it < nL * NSLOT; it += WAVE) {
+            const int r = it / NSLOT, slot = it - NSLOT * (it / NSLOT);
+            const int s = (int)(((uint32_t)L.tk[buf][r] >> 12) & 1u);
+            int l;
+            if (slot < 3) l = s ? 4 * slot : 4 * slot + 3;
+            else l = 4 * ((slot - 3) >> 1) + 1 + ((slot - 3) & 1);
+            const float a = L.ca[r], b = L.cb[r], c = L.cc[r];
+            const float u = P->z[l] - P->z_ref;
+            const float xe = a + b * u + c * g_of(u, dR);
+            const int n = L.wlen[l];
+            int best = -1;
+            float bd = INFINITY;
+            if (slot < 3) {
+                for (int j = 0; j < n; ++j) {
+                    const float d = fabsf(L.wx[l][j] - xe);
+                    if (d < bd) { bd = d; best = j; }
+                }
+                if (best >= 0 && bd * bd < P->T_x) L.ch[r][l] = (int8_t)best;
+            } else {
+                const float yp = y_in + ty_in * (P->z[l] - P->z_in);
+                for (int j = 0; j < n; ++j) {
+                    const float d = fabsf(L.wx[l][j] + L.wd[l][j] * yp - xe);
+                    if (d < bd) { bd = d; best = j; }
+                }
+                if (best >= 0 && bd * bd < T_uv) L.ch[r][l] = (int8_t)best;
+            }
+        }
+        wave_sync();
+
+        // ---- fits and quality, one lane per candidate ----
+        bool acc = false;
+        float Qb = 0.0f, fa = 0.0f, fb = 0.0f, fc = 0.0f, fy0 = 0.0f, fty = 0.0f;
+        int nb = 0;
+        if (lane < nL) {
+            int hits[NL];
+            int n = 0, n_uv = 0;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                hits[l] = L.ch[lane][l];
+                if (hits[l] >= 0) { ++n; if (is_uv(l)) ++n_uv; }
+            }
+            bool st_ok = true;
+#pragma unroll
+            for (int st = 0; st < 3; ++st)
+                if (hits[4 * st + 1] < 0 && hits[4 * st + 2] < 0) st_ok = false;
+            if (n >= 9 && st_ok) {
+                const float a = L.ca[lane], b = L.cb[lane], c = L.cc[lane];
+                float su[NL], sh[NL], rho[NL];
+                float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, S11 = 0.0f, S12 = 0.0f, S22 = 0.0f;
+                float R0 = 0.0f, R1 = 0.0f, R2 = 0.0f;
+#pragma unroll
+                for (int l = 0; l < NL; ++l) {
+                    su[l] = 0.0f; sh[l] = 0.0f; rho[l] = 0.0f;
+                    const int j = hits[l];
+                    if (j < 0) continue;
+                    const float zh = L.wz[l][j];
+                    const float u = zh - P->z_ref;
+                    float xm;
+                    if (is_uv(l)) {
+                        const float yv = y_in + ty_in * (zh - P->z_in);
+                        xm = L.wx[l][j] + L.wd[l][j] * yv;
+                    } else {
+                        xm = L.wx[l][j];
+                    }
+                    const float sv = u * INV1024;
+                    const float h = sv * sv * (1.0f + dR * u);
+                    const float r = xm - (a + b * u + c * g_of(u, dR));
+                    su[l] = sv; sh[l] = h; rho[l] = r;
+                    S0 = S0 + 1.0f;
+                    S1 = S1 + sv;
+                    S2 = S2 + h;
+                    S11 = S11 + sv * sv;
+                    S12 = S12 + sv * h;
+                    S22 = S22 + h * h;
+                    R0 = R0 + r;
+                    R1 = R1 + sv * r;
+                    R2 = R2 + h * r;
+                }
+                const float m00 = S11 * S22 - S12 * S12;
+                const float m01 = S1 * S22 - S12 * S2;
+                const float m02 = S1 * S12 - S11 * S2;
+                const float det = S0 * m00 - S1 * m01 + S2 * m02;
+                if (fabsf(det) > 0.0f) {
+                    const float da = (R0 * m00 - S1 * (R1 * S22 - S12 * R2) + S2 * (R1 * S12 - S11 * R2)) / det;
+                    const float db = (S0 * (R1 * S22 - S12 * R2) - R0 * m01 + S2 * (S1 * R2 - R1 * S2)) / det;
+                    const float dc = (S0 * (S11 * R2 - R1 * S12) - S1 * (S1 * R2 - R1 * S2) + R0 * m02) / det;
+                    float res[NL];
+                    float Qx = 0.0f;
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        res[l] = 0.0f;
+                        if (hits[l] < 0) continue;
+                        res[l] = rho[l] - (da + db * su[l] + dc * sh[l]);
+                        Qx = Qx + res[l] * res[l] / (is_uv(l) ? T_uv : P->T_x);
+                    }
+                    float YS0 = 0.0f, YS1 = 0.0f, YS11 = 0.0f, Y0 = 0.0f, Y1 = 0.0f;
+                    float eta[NL];
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        eta[l] = 0.0f;
+                        if (hits[l] < 0 || !is_uv(l)) continue;
+                        eta[l] = -res[l] / L.wd[l][hits[l]];
+                        YS0 = YS0 + 1.0f;
+                        YS1 = YS1 + su[l];
+                        YS11 = YS11 + su[l] * su[l];
+                        Y0 = Y0 + eta[l];
+                        Y1 = Y1 + su[l] * eta[l];
+                    }
+                    const float D = YS0 * YS11 - YS1 * YS1;
+                    if (fabsf(D) > 0.0f) {
+                        const float dy0 = (Y0 * YS11 - YS1 * Y1) / D;
+                        const float dty = (YS0 * Y1 - YS1 * Y0) / D;
+                        const float dslope = dty * INV1024;
+                        if (fabsf(dslope) < P->T_ty) {
+                            float Qy = 0.0f;
+#pragma unroll
+                            for (int l = 0; l < NL; ++l) {
+                                if (hits[l] < 0 || !is_uv(l)) continue;
+                                const float ry = eta[l] - (dy0 + dty * su[l]);
+                                Qy = Qy + ry * ry / P->T_y;
+                            }
+                            const float Q = (Qx / (float)(n - 3) + Qy / (float)(n_uv - 2)) * P->C_nhits[n - 9];
+                            if (Q < P->T_Q) {
+                                acc = true;
+                                Qb = Q;
+                                nb = n;
+                                fa = a + da;
+                                fb = b + db * INV1024;
+                                fc = c + dc * INV1024SQ;
+                                fy0 = (y_in + ty_in * (P->z_ref - P->z_in)) + dy0;
+                                fty = ty_in + dslope;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+
+        // ---- best candidate: argmin (Q, rank) over the wave ----
+        if (__ballot(acc) == 0) {
+            write_none(t, o12);
+            return;
+        }
+        float bq = acc ? Qb : INFINITY;
+        int br = acc ? lane : (1 << 30);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const float oq = __shfl_xor(bq, off);
+            const int orr = __shfl_xor(br, off);
+            if (oq < bq || (oq == bq && orr < br)) { bq = oq; br = orr; }
+        }
+        if (lane == br) {
+            const float uT = P->z_T - P->z_ref;
+            const float txT = fb + 2.0f * fc * uT + 3.0f * fc * dR * uT * uT;
+            B.found[t] = 1;
+            B.nhits[t] = (uint8_t)nb;
+            B.a[t] = fa;
+            B.b[t] = fb;
+            B.c[t] = fc;
+            B.y0[t] = fy0;
+            B.ty[t] = fty;
+            B.qop[t] = (txT - tx_in) / P->kick;
+            B.Q[t] = Qb;
+        }
+        if (lane < NL) {
+            const int h = L.ch[br][lane];
+            B.hit_idx[o12 + lane] = h >= 0 ? L.wfirst[lane] + h : -1;
+        }
+    }
+
+    __device__ void write_none(uint32_t t, size_t o12) {
+        const int lane = lane_id();
+        if (lane < NL) B.hit_idx[o12 + lane] = -1;
+        if (lane == 0) {
+            B.found[t] = 0;
+            B.nhits[t] = 0;
+            B.a[t] = 0.0f; B.b[t] = 0.0f; B.c[t] = 0.0f; B.y0[t] = 0.0f;
+            B.ty[t] = 0.0f; B.qop[t] = 0.0f; B.Q[t] = 0.0f;
+        }
+    }
+};
+
+template <int NW, int WPB>
+__global__ __launch_bounds__(WPB * WAVE) void k_plain(DevBatch B, const KParams *__restrict__ P, uint32_t ev) {
+    __shared__ WaveLds<NW> lds[WPB];
+    const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const uint32_t t = B.trk_off[ev] + blockIdx.x * WPB + w;
+    if (t >= B.trk_off[ev + 1]) return;
+    Track<NW> tr{B, P, lds[w], 0, 0};
+    tr.run(t, ev);
+}
+
+template <int NW, int WPB>
+__global__ __launch_bounds__(WPB * WAVE) void k_grid(DevBatch B, const KParams *__restrict__ P) {
+    __shared__ WaveLds<NW> lds[WPB];
+    const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const uint32_t t = blockIdx.x * WPB + w;
+    if (t >= B.n_tracks) return;
+    Track<NW> tr{B, P, lds[w], 0, 0};
+    tr.run(t, B.trk_ev[t]);
+}
+
+// Persistent: waves claim `items` consecutive tracks at a time from the
+// queue head until it passes the end; every wave exits once the queue is
+// drained.  q[0] is the head, q[1] counts exited waves: the last wave out
+// puts both back to zero, so the next launch on the batch starts clean
+// without a reset kernel (or a memset node in a captured graph).
+template <int NW, int WPB>
+__global__ __launch_bounds__(WPB * WAVE) void k_persistent(DevBatch B, const KParams *__restrict__ P,
+                                                            uint32_t items) {
+    __shared__ WaveLds<NW> lds[WPB];
+    const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    Track<NW> tr{B, P, lds[w], 0, 0};
+    uint32_t *q = B.counter;
+    for (;;) {
+        uint32_t t0 = 0;
+        if (lane_id() == 0) t0 = atomicAdd(&q[0], items);
+        t0 = __builtin_amdgcn_readfirstlane(t0);
+        if (t0 >= B.n_tracks) break;
+        const uint32_t t1 = t0 + items < B.n_tracks ? t0 + items : B.n_tracks;
+        for (uint32_t t = t0; t < t1; ++t) tr.run(t, B.trk_ev[t]);
+    }
+    if (lane_id() == 0) {
+        const uint32_t waves = gridDim.x * WPB;
+        __threadfence();  // this wave's last claim is performed before it counts itself out
+        if (atomicAdd(&q[1], 1u) == waves - 1u) {
+            atomicExch(&q[0], 0u);
+            atomicExch(&q[1], 0u);
+        }
+    }
+}
+
+__global__ void k_track_event(const uint32_t *__restrict__ trk_off, uint32_t n_events, uint32_t n_tracks,
+                              uint32_t *__restrict__ trk_ev) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tracks) return;
+    // last event e with trk_off[e] <= t
+    uint32_t lo = 0, n = n_events + 1;
+    while (n > 0) {
+        const uint32_t half = n >> 1;
+        if (trk_off[lo + half] <= t) { lo += half + 1; n -= half + 1; } else { n = half; }
+    }
+    trk_ev[t] = lo - 1;
+}
+
+template <int NW, int WPB>
+hipError_t launch_nw_wpb(const DevBatch &b, const KParams *P, int mode, const ExecCfg &cfg,
+                         const uint32_t *trk_off_host, hipStream_t s) {
+    const dim3 block(WPB * WAVE);
+    if (mode == 0) {
+        for (uint32_t e = 0; e < b.n_events; ++e) {
+            const uint32_t nt = trk_off_host[e + 1] - trk_off_host[e];
+            if (nt == 0) continue;
+            hipLaunchKernelGGL((k_plain<NW, WPB>), dim3((nt + WPB - 1) / WPB), block, 0, s, b, P, e);
+        }
+    } else if (mode == 1) {
+        uint32_t grid = (uint32_t)(cfg.blocks_per_cu * cfg.n_cu);
+        const uint32_t need = (b.n_tracks + WPB - 1) / WPB;
+        if (grid > need) grid = need;
+        if (grid == 0) grid = 1;
+        hipLaunchKernelGGL((k_persistent<NW, WPB>), dim3(grid), block, 0, s, b, P,
+                           (uint32_t)cfg.items_per_grab);
+    } else {
+        const uint32_t grid = (b.n_tracks + WPB - 1) / WPB;
+        if (grid) hipLaunchKernelGGL((k_grid<NW, WPB>), dim3(grid), block, 0, s, b, P);
+    }
+    return hipGetLastError();
+}
+
+template <int NW>
+hipError_t launch_nw(const DevBatch &b, const KParams *P, int mode, const ExecCfg &cfg,
+                     const uint32_t *trk_off_host, hipStream_t s) {
+    switch (cfg.waves_per_block) {
+        case 1: return launch_nw_wpb<NW, 1>(b, P, mode, cfg, trk_off_host, s);
+        case 2: return launch_nw_wpb<NW, 2>(b, P, mode, cfg, trk_off_host, s);
+        default: return launch_nw_wpb<NW, 4>(b, P, mode, cfg, trk_off_host, s);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_track_event(const DevBatch &b, hipStream_t s) {
+    if (b.n_tracks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_track_event, dim3((b.n_tracks + 255) / 256), dim3(256), 0, s, b.trk_off, b.n_events,
+                       b.n_tracks, const_cast<uint32_t *>(b.trk_ev));
+    return hipGetLastError();
+}
+
+hipError_t launch_find(const DevBatch &b, const KParams *P, int n_hits_window, int mode, const ExecCfg &cfg,
+                       const uint32_t *trk_off_host, hipStream_t s) {
+    if (b.n_tracks == 0) return hipSuccess;
+    if (n_hits_window <= 32) return launch_nw<32>(b, P, mode, cfg, trk_off_host, s);
+    return launch_nw<64>(b, P, mode, cfg, trk_off_host, s);
+}
+
+namespace {
+template <int NW, int WPB>
+int occ() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_persistent<NW, WPB>),
+                                                     WPB * WAVE, 0) != hipSuccess)
+        return 0;
+    return n;
+}
+}  // namespace
+
+int persistent_blocks_per_cu(int n_hits_window, int waves_per_block) {
+    if (n_hits_window <= 32) {
+        if (waves_per_block == 1) return occ<32, 1>();
+        if (waves_per_block == 2) return occ<32, 2>();
+        return occ<32, 4>();
+    }
+    if (waves_per_block == 1) return occ<64, 1>();
+    if (waves_per_block == 2) return occ<64, 2>();
+    return occ<64, 4>();
+}
+
+}  // namespace lfk

@@ -1,0 +1,306 @@
+"""ctypes binding of the Looking Forward GPU library (include/lf.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of liblf_hip.so.  The functions carry the C names; arrays are numpy arrays
+(copied to the device by lf_upload_events); ``stream`` is a hipStream_t
+handle as an integer (``torch.cuda.current_stream().cuda_stream``) or None
+for the context's own stream.  Importing this module fails loudly when the
+library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+NL = 12
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblf_hip.so")
+
+LF_OK = 0
+LF_ERR_INVALID = -1
+LF_ERR_TOO_LARGE = -2
+LF_ERR_NOMEM = -3
+LF_ERR_DEVICE = -4
+LF_ERR_STATE = -5
+LF_MODE_PLAIN = 0
+LF_MODE_BATCHED = 1
+LF_MODE_GRID = 2
+MODES = {"plain": LF_MODE_PLAIN, "batched": LF_MODE_BATCHED, "grid": LF_MODE_GRID}
+
+
+class LFError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class lf_geometry(ctypes.Structure):
+    _fields_ = [("z", ctypes.c_float * NL), ("dxdy", ctypes.c_float * NL),
+                ("z_in", ctypes.c_float), ("z_mag", ctypes.c_float), ("z_ref", ctypes.c_float),
+                ("z_T", ctypes.c_float), ("kick", ctypes.c_float), ("kappa", ctypes.c_float),
+                ("dRatio", ctypes.c_float), ("polarity", ctypes.c_int32)]
+
+
+_PARAM_FLOATS = ("T_triplet", "T_x", "T_uv_scale", "T_uv_floor", "T_ty", "T_y", "T_Q",
+                 "xtol_const", "xtol_pscale", "xasym", "uv_halfwidth", "K_first", "K_last",
+                 "magtol_const", "magtol_pscale", "magtol_txscale", "magtol_min", "magtol_max",
+                 "p_charge_cut")
+
+
+class lf_params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_float) for n in _PARAM_FLOATS] + [
+        ("C_nhits", ctypes.c_float * 4), ("n_hits_window", ctypes.c_int32), ("n_triplets", ctypes.c_int32)]
+
+
+class lf_batch(ctypes.Structure):
+    _fields_ = [("n_events", ctypes.c_uint32), ("hit_off", ctypes.c_void_p), ("hit_x", ctypes.c_void_p),
+                ("hit_z", ctypes.c_void_p), ("hit_dxdy", ctypes.c_void_p), ("trk_off", ctypes.c_void_p),
+                ("trk_x", ctypes.c_void_p), ("trk_y", ctypes.c_void_p), ("trk_tx", ctypes.c_void_p),
+                ("trk_ty", ctypes.c_void_p), ("trk_qop", ctypes.c_void_p)]
+
+
+class lf_tracks_out(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("found", "n_hits", "hit_idx", "a", "b", "c", "y0", "ty",
+                                                "qop", "Q")]
+
+
+class lf_exec(ctypes.Structure):
+    _fields_ = [("waves_per_block", ctypes.c_int32), ("items_per_grab", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
+
+
+EXPORTS = ("lf_default_params", "lf_check_batch", "lf_create", "lf_upload_events", "lf_find_tracks", "lf_fetch_tracks",
+           "lf_release_batch", "lf_set_exec", "lf_batch_info", "lf_device_bytes_in_use", "lf_destroy",
+           "lf_last_error")
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load liblf_hip.so and declare every exported signature.
+
+    PyTorch is imported first so that the process holds a single HIP
+    runtime: the library then binds to the runtime torch loaded (same
+    soname), and stream handles and device memory are shared with torch.
+    """
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() (no CPU fallback exists)")
+    import torch  # noqa: F401  (loads the process's HIP runtime)
+    lib = ctypes.CDLL(path)
+    P, vp, i32, u64, sz = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t
+    lib.lf_default_params.argtypes = [P(lf_params)]
+    lib.lf_default_params.restype = None
+    lib.lf_check_batch.argtypes = [P(lf_batch)]
+    lib.lf_create.argtypes = [P(lf_geometry), P(lf_params), sz, P(vp)]
+    lib.lf_upload_events.argtypes = [vp, P(lf_batch), vp, P(u64)]
+    lib.lf_find_tracks.argtypes = [vp, u64, i32, vp]
+    lib.lf_fetch_tracks.argtypes = [vp, u64, P(lf_tracks_out), sz, vp]
+    lib.lf_release_batch.argtypes = [vp, u64]
+    lib.lf_set_exec.argtypes = [vp, P(lf_exec)]
+    lib.lf_batch_info.argtypes = [vp, u64, P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32), P(sz)]
+    lib.lf_device_bytes_in_use.argtypes = [vp]
+    lib.lf_device_bytes_in_use.restype = sz
+    lib.lf_destroy.argtypes = [vp]
+    lib.lf_destroy.restype = None
+    lib.lf_last_error.argtypes = [vp]
+    lib.lf_last_error.restype = ctypes.c_char_p
+    for name in ("lf_check_batch", "lf_create", "lf_upload_events", "lf_find_tracks", "lf_fetch_tracks", "lf_release_batch",
+                 "lf_set_exec", "lf_batch_info"):
+        getattr(lib, name).restype = i32
+    return lib
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _check(rc: int, ctx) -> None:
+    if rc != LF_OK:
+        msg = lib().lf_last_error(ctx)
+        raise LFError(rc, msg.decode() if msg else "")
+
+
+def _stream(s) -> ctypes.c_void_p:
+    return ctypes.c_void_p(int(s) if s else 0)
+
+
+def _arr(a, dtype) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ------------------------------------------------------------------ C names
+def lf_default_params() -> dict:
+    p = lf_params()
+    lib().lf_default_params(ctypes.byref(p))
+    d = {n: getattr(p, n) for n in _PARAM_FLOATS}
+    d["C_nhits"] = list(p.C_nhits)
+    d["n_hits_window"] = p.n_hits_window
+    d["n_triplets"] = p.n_triplets
+    return d
+
+
+def make_geometry(world: dict) -> lf_geometry:
+    g = lf_geometry()
+    for i in range(NL):
+        g.z[i] = world["z"][i]
+        g.dxdy[i] = world["dxdy"][i]
+    g.z_in = world["z_in"]
+    g.z_mag = world["z_mag"]
+    g.z_ref = world.get("z_ref", 8520.0)
+    g.z_T = world["z_T"]
+    g.kick = world["kick"]
+    g.kappa = world["kappa"]
+    g.dRatio = world.get("dRatio", 0.0)
+    g.polarity = int(world.get("polarity", 1))
+    return g
+
+
+def make_params(params: dict | None = None) -> lf_params:
+    p = lf_params()
+    lib().lf_default_params(ctypes.byref(p))
+    for k, v in (params or {}).items():
+        if k == "C_nhits":
+            for i in range(4):
+                p.C_nhits[i] = v[i]
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def lf_create(world: dict, params: dict | None = None, budget_bytes: int = 0) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    g, p = make_geometry(world), make_params(params)
+    rc = lib().lf_create(ctypes.byref(g), ctypes.byref(p), budget_bytes, ctypes.byref(ctx))
+    if rc != LF_OK:
+        raise LFError(rc, lib().lf_last_error(None).decode())
+    return ctx
+
+
+class _Hold:
+    """Keeps the host arrays of a batch alive while the call runs."""
+
+    def __init__(self, ev):
+        self.hit_off = _arr(ev.hit_off, np.uint32)
+        self.hit_x = _arr(ev.hit_x, np.float32)
+        self.hit_z = _arr(ev.hit_z, np.float32)
+        self.hit_dxdy = _arr(ev.hit_dxdy, np.float32)
+        self.trk_off = _arr(ev.trk_off, np.uint32)
+        self.trk = [_arr(getattr(ev, k), np.float32) for k in ("trk_x", "trk_y", "trk_tx", "trk_ty", "trk_qop")]
+        self.n_events = int(ev.n_events)
+
+    def struct(self) -> lf_batch:
+        b = lf_batch()
+        b.n_events = self.n_events
+        b.hit_off = self.hit_off.ctypes.data
+        b.hit_x = self.hit_x.ctypes.data
+        b.hit_z = self.hit_z.ctypes.data
+        b.hit_dxdy = self.hit_dxdy.ctypes.data
+        b.trk_off = self.trk_off.ctypes.data
+        b.trk_x, b.trk_y, b.trk_tx, b.trk_ty, b.trk_qop = (a.ctypes.data for a in self.trk)
+        return b
+
+
+def lf_check_batch(ev) -> None:
+    """Host-side validation of a batch; raises LFError if malformed."""
+    h = _Hold(ev)
+    b = h.struct()
+    rc = lib().lf_check_batch(ctypes.byref(b))
+    if rc != LF_OK:
+        raise LFError(rc, lib().lf_last_error(None).decode())
+
+
+def lf_upload_events(ctx, ev, stream=None) -> int:
+    """Upload a batch (any object with the lf_batch arrays as attributes)."""
+    h = _Hold(ev)
+    b = h.struct()
+    bid = ctypes.c_uint64()
+    _check(lib().lf_upload_events(ctx, ctypes.byref(b), _stream(stream), ctypes.byref(bid)), ctx)
+    return bid.value
+
+
+def lf_find_tracks(ctx, batch_id: int, mode=LF_MODE_BATCHED, stream=None) -> None:
+    if isinstance(mode, str):
+        mode = MODES[mode]
+    _check(lib().lf_find_tracks(ctx, ctypes.c_uint64(batch_id), int(mode), _stream(stream)), ctx)
+
+
+def lf_fetch_tracks(ctx, batch_id: int, n_tracks: int | None = None, stream=None) -> dict:
+    if n_tracks is None:
+        n_tracks = lf_batch_info(ctx, batch_id)["n_tracks"]
+    T = int(n_tracks)
+    out = dict(found=np.zeros(T, np.uint8), n_hits=np.zeros(T, np.uint8), hit_idx=np.full((T, NL), -1, np.int32))
+    for k in ("a", "b", "c", "y0", "ty", "qop", "Q"):
+        out[k] = np.zeros(T, np.float32)
+    o = lf_tracks_out(*[out[k].ctypes.data for k in ("found", "n_hits", "hit_idx", "a", "b", "c", "y0", "ty",
+                                                      "qop", "Q")])
+    _check(lib().lf_fetch_tracks(ctx, ctypes.c_uint64(batch_id), ctypes.byref(o), T, _stream(stream)), ctx)
+    return out
+
+
+def lf_release_batch(ctx, batch_id: int) -> None:
+    _check(lib().lf_release_batch(ctx, ctypes.c_uint64(batch_id)), ctx)
+
+
+def lf_set_exec(ctx, waves_per_block: int = 0, items_per_grab: int = 0, blocks_per_cu: int = 0) -> None:
+    x = lf_exec(waves_per_block, items_per_grab, blocks_per_cu)
+    _check(lib().lf_set_exec(ctx, ctypes.byref(x)), ctx)
+
+
+def lf_batch_info(ctx, batch_id: int) -> dict:
+    e, t, h, b = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_size_t()
+    _check(lib().lf_batch_info(ctx, ctypes.c_uint64(batch_id), ctypes.byref(e), ctypes.byref(t),
+                               ctypes.byref(h), ctypes.byref(b)), ctx)
+    return dict(n_events=e.value, n_tracks=t.value, n_hits=h.value, device_bytes=b.value)
+
+
+def lf_device_bytes_in_use(ctx) -> int:
+    return int(lib().lf_device_bytes_in_use(ctx))
+
+
+def lf_destroy(ctx) -> None:
+    lib().lf_destroy(ctx)
+
+
+def lf_last_error(ctx=None) -> str:
+    m = lib().lf_last_error(ctx)
+    return m.decode() if m else ""
+
+
+# ------------------------------------------------------------------ convenience
+class Forward:
+    """One context: upload, run and fetch in one call (``find``)."""
+
+    def __init__(self, world: dict, params: dict | None = None, budget_bytes: int = 0):
+        self.ctx = lf_create(world, params, budget_bytes)
+
+    def find(self, ev, mode="batched", stream=None) -> dict:
+        bid = lf_upload_events(self.ctx, ev, stream)
+        try:
+            lf_find_tracks(self.ctx, bid, mode, stream)
+        except Exception:
+            lf_release_batch(self.ctx, bid)
+            raise
+        return lf_fetch_tracks(self.ctx, bid, int(ev.trk_off[-1]), stream)
+
+    def close(self) -> None:
+        if self.ctx:
+            lf_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

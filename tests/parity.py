@@ -1,0 +1,74 @@
+"""Helpers of the GPU parity tests: run both sides on the same batch and
+compare slot by slot (indices bit-exact, parameters within 1e-5 relative)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import lfgen
+import oracle
+
+W = lfgen.world()
+PARAM_KEYS = ("a", "b", "c", "y0", "ty", "qop", "Q")
+RTOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(ev, mode="batched", params=None, exec_cfg=None, stream=None):
+    from paper_2402_14670_amd import lf
+    ctx = lf.lf_create(W, params)
+    try:
+        if exec_cfg:
+            lf.lf_set_exec(ctx, **exec_cfg)
+        bid = lf.lf_upload_events(ctx, ev, stream)
+        lf.lf_find_tracks(ctx, bid, mode, stream)
+        return lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream)
+    finally:
+        lf.lf_destroy(ctx)
+
+
+def compare(ref: dict, got: dict, rows=None, label: str = "") -> dict:
+    """Indices and flags bit-exact; parameters within RTOL relative (0 stays 0)."""
+    sel = slice(None) if rows is None else rows
+    for k in ("found", "n_hits", "hit_idx"):
+        r, g = ref[k][sel], got[k][sel]
+        if not np.array_equal(r, g):
+            bad = np.nonzero((r != g).reshape(len(r), -1).any(1))[0]
+            raise AssertionError(f"{label}: {k} differs on {len(bad)} tracks, first {bad[:8].tolist()}")
+    exact = 0
+    total = 0
+    for k in PARAM_KEYS:
+        r, g = ref[k][sel].astype(np.float64), got[k][sel].astype(np.float64)
+        ok = np.abs(g - r) <= RTOL * np.abs(r)
+        if not ok.all():
+            i = int(np.nonzero(~ok)[0][0])
+            raise AssertionError(f"{label}: {k} off by more than {RTOL} relative, first slot {i}: "
+                                 f"gpu {g[i]!r} oracle {r[i]!r}")
+        exact += int((ref[k][sel].view(np.uint32) == got[k][sel].view(np.uint32)).sum())
+        total += len(r)
+    return dict(bit_exact_params=exact, params=total, found=int(ref["found"][sel].sum()))
+
+
+def oracle_rows(ev, events):
+    """Global track rows of the given events."""
+    rows = [np.arange(int(ev.trk_off[e]), int(ev.trk_off[e + 1])) for e in events]
+    return np.concatenate(rows) if rows else np.zeros(0, np.int64)
+
+
+def oracle_on_events(ev, events, params=None):
+    """Oracle results for the listed events, placed in a full-size result."""
+    sub = lfgen.select_events(ev, events)
+    o = oracle.run(sub, W, params)
+    T = ev.n_tracks
+    full = dict(found=np.zeros(T, np.uint8), n_hits=np.zeros(T, np.uint8), hit_idx=np.full((T, 12), -1, np.int32))
+    for k in PARAM_KEYS:
+        full[k] = np.zeros(T, np.float32)
+    rows = oracle_rows(ev, events)
+    for k in full:
+        full[k][rows] = o[k]
+    return full, rows

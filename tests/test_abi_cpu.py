@@ -1,0 +1,84 @@
+"""The C-ABI library on the CPU: it loads, exports every symbol lf.h
+declares, and validates batches on the host.  No call here touches a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import lfgen
+import pins
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lf.h")
+
+
+@pytest.fixture(scope="module")
+def lf():
+    from paper_2402_14670_amd import lf as binding
+    return binding
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lf_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lf):
+    lib = ctypes.CDLL(lf.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in lf.h but not exported"
+    assert set(names) == set(lf.EXPORTS)
+
+
+def test_default_params_match_paper(lf):
+    d = lf.lf_default_params()
+    gold = pins.golden_constants()
+    f32 = np.float32
+    for k, v in gold.items():
+        if k.startswith("C_"):
+            assert f32(d["C_nhits"][int(k[2:]) - 9]) == f32(v), k
+        elif k == "z_ref":
+            assert f32(lf.make_geometry(lfgen.world()).z_ref) == f32(v)
+        else:
+            assert f32(d[k]) == f32(v), k
+
+
+def test_check_batch_accepts_generated(lf):
+    lf.lf_check_batch(lfgen.generate("nominal", n_events=2))
+    lf.lf_check_batch(lfgen.select_events(lfgen.generate("single"), []))
+
+
+def _mutated(ev, **kw):
+    d = dict(ev.__dict__)
+    d.update(kw)
+    return lfgen.Events(**d)
+
+
+@pytest.mark.parametrize("case", ["nan_hit", "inf_track", "qop_zero", "unsorted", "offset_decrease",
+                                  "offset_start"])
+def test_check_batch_rejects_malformed(lf, case):
+    ev = lfgen.generate("single")
+    if case == "nan_hit":
+        x = ev.hit_x.copy(); x[5] = np.nan; bad = _mutated(ev, hit_x=x)
+    elif case == "inf_track":
+        t = ev.trk_tx.copy(); t[3] = np.inf; bad = _mutated(ev, trk_tx=t)
+    elif case == "qop_zero":
+        q = ev.trk_qop.copy(); q[0] = 0.0; bad = _mutated(ev, trk_qop=q)
+    elif case == "unsorted":
+        x = ev.hit_x.copy(); b0, b1 = int(ev.hit_off[3]), int(ev.hit_off[4])
+        assert b1 - b0 >= 2
+        x[b0], x[b0 + 1] = x[b0 + 1] + 1.0, x[b0]
+        bad = _mutated(ev, hit_x=x)
+    elif case == "offset_decrease":
+        o = ev.hit_off.copy(); o[5] = o[6] + 1; bad = _mutated(ev, hit_off=o)
+    else:
+        o = ev.trk_off.copy(); o[0] = 1; bad = _mutated(ev, trk_off=o)
+    with pytest.raises(lf.LFError) as e:
+        lf.lf_check_batch(bad)
+    assert e.value.code == lf.LF_ERR_INVALID
+    assert "batch" in str(e.value)
