@@ -38,7 +38,7 @@ struct lf_ctx {
     size_t used = 0;
     int device = 0;
     hipStream_t stream = nullptr;
-    lfk::ExecCfg exec{2, 1, 0, 0};
+    lfk::ExecCfg exec{2, 4, 0, 0};
     std::map<uint64_t, Batch> batches;
     uint64_t next_id = 1;
     std::string err;
@@ -144,7 +144,7 @@ Layout layout(uint32_t E, uint32_t H, uint32_t T) {
     L.found = put(T); L.nhits = put(T); L.hit_idx = put((size_t)T * 48);
     L.a = put((size_t)T * 4); L.b = put((size_t)T * 4); L.c = put((size_t)T * 4);
     L.y0 = put((size_t)T * 4); L.ty_o = put((size_t)T * 4); L.qop = put((size_t)T * 4); L.Q = put((size_t)T * 4);
-    L.counter = put(8);
+    L.counter = put(1024);
     L.total = o;
     return L;
 }
@@ -309,7 +309,7 @@ int lf_upload_events(lf_ctx *c, const lf_batch *b, void *hip_stream, uint64_t *b
         e = hipMemcpyAsync(base + x.off, x.src, x.n, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) break;
     }
-    if (e == hipSuccess) e = hipMemsetAsync(d.counter, 0, 8, s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.counter, 0, 1024, s);
     if (e == hipSuccess) e = lfk::launch_track_event(d, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {

@@ -33,7 +33,7 @@ struct DevBatch {
     uint8_t *found, *nhits;    // [T]
     int32_t *hit_idx;          // [12*T]
     float *a, *b, *c, *y0, *ty, *qop, *Q;  // [T]
-    uint32_t *counter;         // [2] work-queue head and exited-wave count (batched mode), zero between launches
+    uint32_t *counter;         // [256] per-XCD queue heads and exited-wave count (batched mode), zero between launches
     uint32_t n_events, n_tracks;
 };
 

@@ -136,9 +136,11 @@ struct Track {
             if (best >= 0) {
                 const float chi2 = bd * bd;
                 if (chi2 < P->T_triplet) {
-                    valid = true;
                     key = ((uint64_t)__float_as_uint(chi2) << 32) |
                           (uint64_t)(uint32_t)((s << 12) | (i0 << 6) | i2);
+                    // a full list only admits keys below its last one (exactly what the
+                    // rank count of merge() would keep)
+                    valid = nL < P->n_triplets || key < L.tk[buf][nL - 1];
                 }
             }
         }
@@ -512,42 +514,69 @@ __global__ __launch_bounds__(WPB * WAVE) void k_plain(DevBatch B, const KParams 
     tr.run(t, ev);
 }
 
+// Blocks are dispatched to the 8 XCDs round-robin (block b -> XCD b % 8);
+// the remap gives each XCD a contiguous run of tracks, so the tracks of an
+// event share one L2 and its hits are fetched from HBM once per XCD.
+constexpr uint32_t NXCD = 8;
+
 template <int NW, int WPB>
 __global__ __launch_bounds__(WPB * WAVE) void k_grid(DevBatch B, const KParams *__restrict__ P) {
     __shared__ WaveLds<NW> lds[WPB];
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    const uint32_t t = blockIdx.x * WPB + w;
+    const uint32_t per = gridDim.x / NXCD;
+    const uint32_t lb = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+    const uint32_t t = lb * WPB + w;
     if (t >= B.n_tracks) return;
     Track<NW> tr{B, P, lds[w], 0, 0};
     tr.run(t, B.trk_ev[t]);
 }
 
-// Persistent: waves claim `items` consecutive tracks at a time from the
-// queue head until it passes the end; every wave exits once the queue is
-// drained.  q[0] is the head, q[1] counts exited waves: the last wave out
-// puts both back to zero, so the next launch on the batch starts clean
-// without a reset kernel (or a memset node in a captured graph).
+// Persistent: one work queue per XCD over a contiguous eighth of the
+// tracks.  Waves claim `items` consecutive tracks at a time from their own
+// XCD's queue, then help the other queues in turn; a wave exits once every
+// queue is drained.  Heads sit 64 bytes apart (q[16 k]); q[16 NXCD] counts
+// exited waves, and the last wave out puts every word back to zero, so the
+// next launch on the batch starts clean without a reset kernel (or a memset
+// node in a captured graph).
 template <int NW, int WPB>
 __global__ __launch_bounds__(WPB * WAVE) void k_persistent(DevBatch B, const KParams *__restrict__ P,
                                                             uint32_t items) {
     __shared__ WaveLds<NW> lds[WPB];
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    Track<NW> tr{B, P, lds[w], 0, 0};
     uint32_t *q = B.counter;
-    for (;;) {
-        uint32_t t0 = 0;
-        if (lane_id() == 0) t0 = atomicAdd(&q[0], items);
-        t0 = __builtin_amdgcn_readfirstlane(t0);
-        if (t0 >= B.n_tracks) break;
-        const uint32_t t1 = t0 + items < B.n_tracks ? t0 + items : B.n_tracks;
-        for (uint32_t t = t0; t < t1; ++t) tr.run(t, B.trk_ev[t]);
+    const uint32_t T = B.n_tracks;
+    uint32_t qi = blockIdx.x % NXCD;
+    for (uint32_t tried = 0; tried < NXCD;) {
+        const uint32_t lo = (uint32_t)(((uint64_t)T * qi) / NXCD);
+        const uint32_t n = (uint32_t)(((uint64_t)T * (qi + 1)) / NXCD) - lo;
+        uint32_t c = 0;
+        if (lane_id() == 0) {
+            // skip the atomic once the queue is seen drained
+            uint32_t *head = &q[16 * qi];
+            c = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (c < n) c = atomicAdd(head, items);
+        }
+        c = __builtin_amdgcn_readfirstlane(c);
+        if (c >= n) {
+            qi = qi + 1 == NXCD ? 0 : qi + 1;
+            ++tried;
+            continue;
+        }
+        const uint32_t e = c + items < n ? c + items : n;
+        for (uint32_t t = lo + c; t < lo + e; ++t) {
+            // keep per-track loads inside the loop: hoisting them across tracks
+            // costs ~30 VGPRs of loop-carried state and two waves per SIMD
+            asm volatile("" ::: "memory");
+            Track<NW> tr{B, P, lds[w], 0, 0};
+            tr.run(t, B.trk_ev[t]);
+        }
     }
     if (lane_id() == 0) {
         const uint32_t waves = gridDim.x * WPB;
-        __threadfence();  // this wave's last claim is performed before it counts itself out
-        if (atomicAdd(&q[1], 1u) == waves - 1u) {
-            atomicExch(&q[0], 0u);
-            atomicExch(&q[1], 0u);
+        __threadfence();  // this wave's claims are performed before it counts itself out
+        if (atomicAdd(&q[16 * NXCD], 1u) == waves - 1u) {
+            for (uint32_t k = 0; k < NXCD; ++k) atomicExch(&q[16 * k], 0u);
+            atomicExch(&q[16 * NXCD], 0u);
         }
     }
 }
@@ -583,7 +612,8 @@ hipError_t launch_nw_wpb(const DevBatch &b, const KParams *P, int mode, const Ex
         hipLaunchKernelGGL((k_persistent<NW, WPB>), dim3(grid), block, 0, s, b, P,
                            (uint32_t)cfg.items_per_grab);
     } else {
-        const uint32_t grid = (b.n_tracks + WPB - 1) / WPB;
+        const uint32_t need = (b.n_tracks + WPB - 1) / WPB;
+        const uint32_t grid = (need + NXCD - 1) / NXCD * NXCD;
         if (grid) hipLaunchKernelGGL((k_grid<NW, WPB>), dim3(grid), block, 0, s, b, P);
     }
     return hipGetLastError();
