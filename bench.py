@@ -25,22 +25,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Peak VALU lane-operations per second without FMA or packed FP32:
-# 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Peak VALU lane-operations per second for single (non-FMA, non-packed)
+# binary32/int32 operations: 256 CUs x 4 SIMDs x 32 lanes per clock x
+# 2.4 GHz = 78.6 T/s, i.e. the fp32 vector peak of 157.3 TFLOP/s counted as
+# one operation per lane instead of two per FMA.  (A 16-lane reading, 39.3 T/s,
+# is contradicted by the counters: the kernel retires VALU lane-operations
+# faster than that.)
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
-# Algorithmic VALU lane-operations per input track of the nominal workload:
-# ~1,160 (windows) + 17 x 1,288 doublet pairs + 81 x 22.0 filtered doublets
-# + 20 x 7.5 triplets + 1,273 x 6.9 kept candidates (model, extension scans)
-# + 514 x 2.45 accepted fits; work-unit means measured on this workload.
-OPS_PER_TRACK = 35.0e3
-# Algorithmic HBM bytes per event of the nominal workload: 12 B per hit in
-# (x, z, dxdy), 20 B per input track in, 78 B per track out, offsets.
+# Algorithmic VALU lane-operations per work unit (the arithmetic and
+# compares of the fixed evaluation order; loads, stores and address
+# arithmetic not counted).  Units come from lf_work_counts on the workload.
+OPS_PER_UNIT = {
+    "tracks": 1160,        # extrapolation and bounds 12 x 14, 36 searches x 8 probes x 3, caps
+    "staged_hits": 2,      # common-z / common-stereo checks
+    "seed_items": 45,      # slope bracket of one first-layer hit and its two searches
+    "pairs_tested": 17,    # doublet slope, charge and magnet filters
+    "doublets": 35,        # middle-hit prediction, sorted closest-hit search, chi2 cut, key
+    "triplets": 20,        # rank counting into the top-n list
+    "kept": 328,           # triplet model 28, nine closest-hit searches 270, candidate rule 30
+    "fitted": 514,         # x and y least squares, residuals, Q
+}
+# Algorithmic HBM bytes: 12 B per hit in (x, z, dxdy), 20 B per input track
+# in, 78 B per track out, plus the offsets.
 BYTES_PER_HIT_IN = 12
 BYTES_PER_TRACK_IN = 20
 BYTES_PER_TRACK_OUT = 78
+# HBM traffic of the batched kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
+# (per launch, scaled by the counters' reading of a known-size copy), valid
+# only for the kernel source it was measured on.
+TRAFFIC = {"kernel_sha256": None, "bytes_per_launch": None}
 WORKLOAD = "nominal"
-KERNEL = "k_persistent"
+KERNEL = "k_grid"   # the batched mode's kernel (one wavefront per input track)
+KERNEL_SRC = os.path.join(ROOT, "paper_2402_14670_amd", "csrc", "lf_kernels.hip")
 
 
 def parse():
@@ -52,8 +69,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle baseline sample (0 disables it)")
     ap.add_argument("--events", type=int, default=1000)
-    ap.add_argument("--modes", default="batched,grid,plain",
-                    help="comma-separated subset of batched,grid,plain to time (batched is always timed)")
+    ap.add_argument("--modes", default="batched,persistent,plain",
+                    help="comma-separated subset of batched,persistent,plain to time (batched is always timed)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a known-size reference for HBM "
                          "byte counters under a profiler)")
@@ -135,7 +152,7 @@ def main():
     bid = lf.lf_upload_events(ctx, ev, stream.cuda_stream)
     res = {}
     wanted = set(args.modes.split(",")) | {"batched"}
-    for mode, steps, warm in (("batched", args.steps, args.warmup), ("grid", args.steps, args.warmup),
+    for mode, steps, warm in (("batched", args.steps, args.warmup), ("persistent", args.steps, args.warmup),
                               ("plain", args.plain_steps, 1)):
         if mode not in wanted:
             continue
@@ -143,13 +160,17 @@ def main():
         res[mode] = ms
         print(f"bench: {mode:8s} {ms:8.3f} ms/step  {ev.n_events / ms * 1e3:12.0f} events/s", file=sys.stderr,
               flush=True)
+    work = lf.lf_work_counts(ctx, bid, stream.cuda_stream)
     out = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
     lf.lf_destroy(ctx)
 
     ms = res["batched"]
     value = ev.n_events / (ms * 1e-3)
-    ops = OPS_PER_TRACK * ev.n_tracks
+    ops = sum(OPS_PER_UNIT[k] * work[k] for k in OPS_PER_UNIT)
     achieved = ops / (ms * 1e-3) / 1e12
+    import hashlib
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    traffic = TRAFFIC["bytes_per_launch"] if TRAFFIC["kernel_sha256"] == sha else None
     nbytes = algorithmic_bytes(ev)
     line = {
         "metric": "events/s on 1 MI355X (batched persistent launch)",
@@ -172,8 +193,8 @@ def main():
         "batched_over_plain": round(res["plain"] / ms, 2) if "plain" in res else None,
         "found_tracks": int(out["found"].sum()),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                     "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-                     "kernel": KERNEL, "ops_per_launch": ops,
+                     "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": traffic,
+                     "kernel": KERNEL, "ops_per_launch": ops, "work_units": work,
                      "hbm": {"algorithmic_bytes": nbytes, "achieved_GBs": round(nbytes / (ms * 1e-3) / 1e9, 1),
                              "peak_GBs": HBM_PEAK_GBS,
                              "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}},

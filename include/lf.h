@@ -53,11 +53,29 @@ enum {
     LF_ERR_STATE = -5      /* unknown batch id, or a call out of order */
 };
 
-/* Execution modes of lf_find_tracks. */
+/* Execution modes of lf_find_tracks (all write identical results). */
 enum {
-    LF_MODE_PLAIN = 0,     /* one kernel launch per event */
-    LF_MODE_BATCHED = 1,   /* one persistent launch over the whole batch, (event, track) work queue */
-    LF_MODE_GRID = 2       /* one launch, one wavefront per input track (no queue) */
+    LF_MODE_PLAIN = 0,      /* one kernel launch per event */
+    LF_MODE_BATCHED = 1,    /* one launch over the whole batch, one wavefront per input track,
+                               tracks ordered so each XCD takes a contiguous run of events */
+    LF_MODE_PERSISTENT = 2  /* one launch of resident wavefronts pulling (event, track) work
+                               items from per-XCD device queues */
+};
+
+/* Work counters filled by lf_work_counts, indices into its counts array. */
+enum {
+    LF_WC_TRACKS = 0,        /* input tracks */
+    LF_WC_PAIRS_ALL = 1,     /* (h0, h2) pairs of both seed sets in the windows */
+    LF_WC_SEED_ITEMS = 2,    /* first-layer hits whose h2 range was bracketed */
+    LF_WC_PAIRS_TESTED = 3,  /* pairs the doublet filters were evaluated on */
+    LF_WC_DOUBLETS = 4,      /* pairs passing both doublet filters */
+    LF_WC_TRIPLETS = 5,      /* triplets with chi2 < T_triplet */
+    LF_WC_KEPT = 6,          /* triplets kept (at most n_triplets per track) */
+    LF_WC_FITTED = 7,        /* candidates passing the 9-hit / station rule (fitted) */
+    LF_WC_ACCEPTED = 8,      /* candidates with Q < T_Q */
+    LF_WC_STAGED_HITS = 9,   /* window hits staged */
+    LF_WC_FOUND = 10,        /* tracks found */
+    LF_WC_N = 11
 };
 
 /* Detector and field description.  Layers 0..11 are three stations of
@@ -139,8 +157,8 @@ typedef struct {
  * current value. */
 typedef struct {
     int32_t waves_per_block;   /* 1, 2 or 4 wavefronts per workgroup */
-    int32_t items_per_grab;    /* tracks a wavefront takes per queue claim (batched mode), 1..16 */
-    int32_t blocks_per_cu;     /* persistent grid = blocks_per_cu * compute units (batched mode) */
+    int32_t items_per_grab;    /* tracks a wavefront takes per queue claim (persistent mode), 1..16 */
+    int32_t blocks_per_cu;     /* persistent grid = blocks_per_cu * compute units (persistent mode) */
 } lf_exec;
 
 /* Fills *p with the default parameters. */
@@ -167,10 +185,17 @@ int lf_upload_events(lf_ctx *ctx, const lf_batch *batch, void *hip_stream, uint6
 
 /* Enqueues the whole hot path for a resident batch on hip_stream and
  * returns without waiting.  mode is LF_MODE_PLAIN, LF_MODE_BATCHED or
- * LF_MODE_GRID; all modes write identical results.  May be called again on
+ * LF_MODE_PERSISTENT; all modes write identical results.  May be called again on
  * the same batch (results are rewritten).  Errors: LF_ERR_STATE (unknown
  * batch), LF_ERR_INVALID (mode), LF_ERR_DEVICE. */
 int lf_find_tracks(lf_ctx *ctx, uint64_t batch_id, int mode, void *hip_stream);
+
+/* Runs the hot path once more over a resident batch in a counting build of
+ * the kernel and writes the total work counters (LF_WC_*) to counts[0..n):
+ * the units the roofline's algorithmic operation count is built from.
+ * Synchronous; the results of the batch are rewritten (identically).
+ * Errors: LF_ERR_STATE, LF_ERR_INVALID (NULL counts), LF_ERR_DEVICE. */
+int lf_work_counts(lf_ctx *ctx, uint64_t batch_id, void *hip_stream, int64_t *counts, size_t n_counts);
 
 /* Copies the results of a batch into caller buffers holding at least
  * cap_tracks >= number of input tracks slots, waits for completion and

@@ -128,7 +128,7 @@ int validate(const lf_batch *b, std::string &why) {
 // Device layout of a batch: one allocation, every array 256-byte aligned.
 struct Layout {
     size_t hit_off, hx, hz, hd, trk_off, trk_ev, tx, ty, ttx, tty, tqop;
-    size_t found, nhits, hit_idx, a, b, c, y0, ty_o, qop, Q, counter, total;
+    size_t found, nhits, hit_idx, a, b, c, y0, ty_o, qop, Q, counter, stats, total;
 };
 
 Layout layout(uint32_t E, uint32_t H, uint32_t T) {
@@ -145,6 +145,7 @@ Layout layout(uint32_t E, uint32_t H, uint32_t T) {
     L.a = put((size_t)T * 4); L.b = put((size_t)T * 4); L.c = put((size_t)T * 4);
     L.y0 = put((size_t)T * 4); L.ty_o = put((size_t)T * 4); L.qop = put((size_t)T * 4); L.Q = put((size_t)T * 4);
     L.counter = put(1024);
+    L.stats = put(16 * 8);
     L.total = o;
     return L;
 }
@@ -295,6 +296,7 @@ int lf_upload_events(lf_ctx *c, const lf_batch *b, void *hip_stream, uint64_t *b
     d.qop = reinterpret_cast<float *>(base + L.qop);
     d.Q = reinterpret_cast<float *>(base + L.Q);
     d.counter = reinterpret_cast<uint32_t *>(base + L.counter);
+    d.stats = reinterpret_cast<unsigned long long *>(base + L.stats);
     d.n_events = E;
     d.n_tracks = T;
     hipStream_t s = pick(c, hip_stream);
@@ -327,12 +329,29 @@ int lf_find_tracks(lf_ctx *c, uint64_t batch_id, int mode, void *hip_stream) {
     if (!c) return LF_ERR_INVALID;
     auto it = c->batches.find(batch_id);
     if (it == c->batches.end()) return fail(c, LF_ERR_STATE, "lf_find_tracks: unknown batch id");
-    if (mode != LF_MODE_PLAIN && mode != LF_MODE_BATCHED && mode != LF_MODE_GRID)
+    if (mode != LF_MODE_PLAIN && mode != LF_MODE_BATCHED && mode != LF_MODE_PERSISTENT)
         return fail(c, LF_ERR_INVALID, "lf_find_tracks: unknown mode");
     Batch &bt = it->second;
     const hipError_t e = lfk::launch_find(bt.dev, c->d_params, c->params.n_hits_window, mode, c->exec,
                                           bt.trk_off.data(), pick(c, hip_stream));
     if (e != hipSuccess) return hip_fail(c, e, "lf_find_tracks");
+    return LF_OK;
+}
+
+int lf_work_counts(lf_ctx *c, uint64_t batch_id, void *hip_stream, int64_t *counts, size_t n_counts) {
+    if (!c) return LF_ERR_INVALID;
+    auto it = c->batches.find(batch_id);
+    if (it == c->batches.end()) return fail(c, LF_ERR_STATE, "lf_work_counts: unknown batch id");
+    if (!counts) return fail(c, LF_ERR_INVALID, "lf_work_counts: NULL counts");
+    Batch &bt = it->second;
+    hipStream_t s = pick(c, hip_stream);
+    unsigned long long host[16] = {0};
+    hipError_t e = hipMemsetAsync(bt.dev.stats, 0, sizeof(host), s);
+    if (e == hipSuccess) e = lfk::launch_count(bt.dev, c->d_params, c->params.n_hits_window, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, bt.dev.stats, sizeof(host), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "lf_work_counts");
+    for (size_t k = 0; k < n_counts; ++k) counts[k] = k < 16 ? (int64_t)host[k] : 0;
     return LF_OK;
 }
 

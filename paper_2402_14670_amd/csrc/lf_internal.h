@@ -34,6 +34,7 @@ struct DevBatch {
     int32_t *hit_idx;          // [12*T]
     float *a, *b, *c, *y0, *ty, *qop, *Q;  // [T]
     uint32_t *counter;         // [256] per-XCD queue heads and exited-wave count (batched mode), zero between launches
+    unsigned long long *stats; // [16] work counters (counting launch only)
     uint32_t n_events, n_tracks;
 };
 
@@ -47,10 +48,14 @@ struct ExecCfg {
 // Fills trk_ev from trk_off (one thread per track).
 hipError_t launch_track_event(const DevBatch &b, hipStream_t s);
 // The hot path.  P points to a KParams in device memory.  mode: 0 plain
-// (per-event launches), 1 persistent queue, 2 one wavefront per track.
+// (per-event launches), 1 batched (one wavefront per track), 2 persistent
+// (resident wavefronts pulling from per-XCD work queues).
 // trk_off_host is read by mode 0 only.
 hipError_t launch_find(const DevBatch &b, const KParams *P, int n_hits_window, int mode,
                        const ExecCfg &cfg, const uint32_t *trk_off_host, hipStream_t s);
+// Counting launch: one wavefront per track, adds the work counters of every
+// track into b.stats (which must be zeroed first).
+hipError_t launch_count(const DevBatch &b, const KParams *P, int n_hits_window, hipStream_t s);
 // Resident blocks per compute unit of the persistent kernel (0 on error).
 int persistent_blocks_per_cu(int n_hits_window, int waves_per_block);
 

@@ -56,6 +56,67 @@ __device__ __forceinline__ bool is_uv(int l) {
 // x(z) model term g(u) = u^2 (1 + dRatio u), u = z - z_ref.
 __device__ __forceinline__ float g_of(float u, float dR) { return u * u * (1.0f + dR * u); }
 
+// Number of v[0..n) below key (lower bound) in a non-decreasing LDS array.
+__device__ __forceinline__ int count_below(const float *v, int n, float key) {
+    int lo = 0;
+    while (n > 0) {
+        const int half = n >> 1;
+        if (v[lo + half] < key) { lo += half + 1; n -= half + 1; } else { n = half; }
+    }
+    return lo;
+}
+
+// Number of v[0..n) at or below key (upper bound).
+__device__ __forceinline__ int count_upto(const float *v, int n, float key) {
+    int lo = 0;
+    while (n > 0) {
+        const int half = n >> 1;
+        if (v[lo + half] <= key) { lo += half + 1; n -= half + 1; } else { n = half; }
+    }
+    return lo;
+}
+
+// Closest hit of a window: the first index j minimising d_j = |val(j) - xe|
+// (the result of a linear scan with a strict '<' update), or -1 when no d_j
+// is below infinity.  val(j) must be non-decreasing in j.  Then
+// RN(val(j) - xe) is non-decreasing too, so d falls up to the first j with
+// val(j) >= xe and rises after it: only that index, its left neighbour and
+// the plateau of equal d ending at the left neighbour can hold the answer.
+template <class Val>
+__device__ __forceinline__ int closest_sorted(Val val, int n, float xe, float &bd) {
+    int p = 0;
+    for (int len = n; len > 0;) {
+        const int half = len >> 1;
+        if (val(p + half) < xe) { p += half + 1; len -= half + 1; } else { len = half; }
+    }
+    int best = p;
+    float d = p < n ? fabsf(val(p) - xe) : INFINITY;
+    if (p > 0) {
+        const float dl = fabsf(val(p - 1) - xe);
+        if (!(d < dl)) {
+            best = p - 1;
+            d = dl;
+            while (best > 0 && fabsf(val(best - 1) - xe) == dl) --best;
+        }
+    }
+    if (!(d < INFINITY)) return -1;
+    bd = d;
+    return best;
+}
+
+// The same by linear scan, for windows whose values are not sorted.
+template <class Val>
+__device__ __forceinline__ int closest_scan(Val val, int n, float xe, float &bd) {
+    int best = -1;
+    float d = INFINITY;
+    for (int j = 0; j < n; ++j) {
+        const float dj = fabsf(val(j) - xe);
+        if (dj < d) { d = dj; best = j; }
+    }
+    bd = d;
+    return best;
+}
+
 template <int NW>
 struct WaveLds {
     float wx[NL][NW];          // window hits: x at y = 0
@@ -73,13 +134,18 @@ struct WaveLds {
     int8_t ch[MAX_TRIPLETS][NL];    // candidate hits, window-relative, -1 = none
 };
 
-template <int NW>
+// Work counters of one track (only in the counting build, CNT = true).
+enum { C_TRACKS, C_PAIRS_ALL, C_ITEMS, C_PAIRS_TESTED, C_DOUBLETS, C_TRIPLETS, C_KEPT, C_FITTED,
+       C_ACCEPTED, C_STAGED, C_FOUND, C_N };
+
+template <int NW, bool CNT = false>
 struct Track {
     const DevBatch &B;
     const KParams *__restrict__ P;
     WaveLds<NW> &L;
     int nL;    // kept triplets
     int buf;   // live half of the top-n double buffer
+    uint32_t cnt[CNT ? C_N : 1];
 
     // Merge this pass's accepted triplets (one per lane) into the top-n list.
     __device__ void merge(bool valid, uint64_t key, int h1) {
@@ -116,7 +182,7 @@ struct Track {
     // Complete the first `count` queued doublets with their closest middle hit.
     __device__ void flush(int count) {
         const int lane = lane_id();
-        bool valid = false;
+        bool tri = false, valid = false;
         uint64_t key = 0;
         int best = -1;
         if (lane < count) {
@@ -128,14 +194,12 @@ struct Track {
             const float x0 = L.wx[l0][i0], z0 = L.wz[l0][i0];
             const float x1e = P->z[l1] * txd + (x0 - txd * z0) * K;
             float bd = INFINITY;
-            const int n1 = L.wlen[l1];
-            for (int j = 0; j < n1; ++j) {
-                const float d = fabsf(L.wx[l1][j] - x1e);
-                if (d < bd) { bd = d; best = j; }
-            }
+            const float *wx1 = L.wx[l1];
+            best = closest_sorted([wx1](int j) { return wx1[j]; }, L.wlen[l1], x1e, bd);
             if (best >= 0) {
                 const float chi2 = bd * bd;
                 if (chi2 < P->T_triplet) {
+                    tri = true;
                     key = ((uint64_t)__float_as_uint(chi2) << 32) |
                           (uint64_t)(uint32_t)((s << 12) | (i0 << 6) | i2);
                     // a full list only admits keys below its last one (exactly what the
@@ -144,11 +208,16 @@ struct Track {
                 }
             }
         }
+        if constexpr (CNT) cnt[C_TRIPLETS] += (uint32_t)__popcll(__ballot(tri));
         merge(valid, key, best);
     }
 
     __device__ void run(uint32_t t, uint32_t ev) {
         const int lane = lane_id();
+        if constexpr (CNT) {
+            for (int k = 0; k < C_N; ++k) cnt[k] = 0;
+            cnt[C_TRACKS] = 1;
+        }
         const float x_in = B.tx_[t], y_in = B.ty_[t], tx_in = B.ttx[t], ty_in = B.tty[t];
         const float qop = B.tqop[t];
         const float dR = P->dRatio;
@@ -228,6 +297,25 @@ struct Track {
             }
         }
         wave_sync();
+        // layers whose window hits do not all share one z (resp. one stereo
+        // slope): those take the general paths below
+        uint32_t zvar = 0, dvar = 0;
+        for (int it = lane; it < NL * NW; it += WAVE) {
+            const int l = it / NW, j = it - NW * (it / NW);
+            if (j > 0 && j < L.wlen[l]) {
+                if (L.wz[l][j] != L.wz[l][0]) zvar |= 1u << l;
+                if (L.wd[l][j] != L.wd[l][0]) dvar |= 1u << l;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            zvar |= __shfl_xor(zvar, off);
+            dvar |= __shfl_xor(dvar, off);
+        }
+        if constexpr (CNT) {
+            for (int l = 0; l < NL; ++l) cnt[C_STAGED] += (uint32_t)L.wlen[l];
+            cnt[C_PAIRS_ALL] = (uint32_t)(L.wlen[0] * L.wlen[8] + L.wlen[3] * L.wlen[11]);
+        }
 
         // ---- doublets of both seed sets, filtered, queued; triplets by passes ----
         nL = 0;
@@ -235,22 +323,63 @@ struct Track {
         const float tolc = P->magtol_const + P->magtol_pscale / p;
         const bool low_p = p < P->p_charge_cut;
         int qn = 0;
-        for (int s = 0; s < 2; ++s) {
+        // One item per (set, h0).  Each item gets the range of h2 in its third
+        // window that can pass the magnet filter: with a common z per window,
+        // a passing slope t satisfies |x0 - x_mag + (z_mag - z0) t| < tol(t)
+        // <= tolb, so t lies within tolb/|z_mag - z0| of t_c = (x_mag - x0) /
+        // (z_mag - z0), and x2 = x0 + t (z2 - z0).  The x2 interval is widened
+        // by 0.5 mm + 1e-5 relative, orders of magnitude above the rounding
+        // of the filter itself, and every pair in it is tested with the exact
+        // filter below; pairs outside cannot pass.  Sets without a common z
+        // per window (or a degenerate lever arm) test every pair.
+        const int n00 = L.wlen[0], n01 = L.wlen[3];
+        const int items_total = n00 + n01;
+        if constexpr (CNT) cnt[C_ITEMS] = (uint32_t)items_total;
+        for (int base = 0; base < items_total; base += WAVE) {
+            const int item = base + lane;
+            const int s = item < n00 ? 0 : 1;
+            const int i0 = item - (s ? n00 : 0);
             const int l0 = s ? 3 : 0, l2 = s ? 11 : 8;
-            const int n0 = L.wlen[l0], n2 = L.wlen[l2];
-            const int total = n0 * n2;
-            if (total == 0) continue;
-            // i0 = idx / n2 by multiply-shift: exact for idx < 2^20 / n2 (idx < 4096, n2 <= 64)
-            const uint32_t m = ((1u << 20) + (uint32_t)n2 - 1u) / (uint32_t)n2;
-            for (int base = 0; base < total; base += WAVE) {
-                const int idx = base + lane;
+            const int n2 = L.wlen[l2];
+            int jlo = 0, jhi = 0;
+            float x0 = 0.0f, z0 = 0.0f;
+            if (item < items_total) {
+                x0 = L.wx[l0][i0];
+                z0 = L.wz[l0][i0];
+                jhi = n2;
+                if (n2 > 0 && !((zvar >> l0) & 1u) && !((zvar >> l2) & 1u)) {
+                    const float lev = P->z_mag - z0;
+                    const float dz = L.wz[l2][0] - z0;
+                    if (fabsf(lev) > 1.0f && fabsf(dz) > 1.0f) {
+                        const float tc = (x_mag - x0) / lev;
+                        const float dt0 = P->magtol_max / fabsf(lev);
+                        float tolb = tolc + (P->magtol_txscale > 0.0f ? P->magtol_txscale : 0.0f) *
+                                                (fabsf(tc) + dt0);
+                        if (tolb < P->magtol_min) tolb = P->magtol_min;
+                        if (tolb > P->magtol_max) tolb = P->magtol_max;
+                        const float dt = tolb / fabsf(lev);
+                        const float e1 = x0 + (tc - dt) * dz, e2 = x0 + (tc + dt) * dz;
+                        const float margin = 0.5f + 1e-5f * (fabsf(e1) + fabsf(e2));
+                        const float xlo = (e1 < e2 ? e1 : e2) - margin;
+                        const float xhi = (e1 < e2 ? e2 : e1) + margin;
+                        if (fabsf(xlo) < 1e30f && fabsf(xhi) < 1e30f) {
+                            jlo = count_below(L.wx[l2], n2, xlo);
+                            jhi = count_upto(L.wx[l2], n2, xhi);
+                        }
+                    }
+                }
+            }
+            int span = jhi - jlo;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const int o = __shfl_xor(span, off);
+                span = o > span ? o : span;
+            }
+            for (int k = 0; k < span; ++k) {
+                const int i2 = jlo + k;
                 bool pass = false;
                 float txd = 0.0f;
-                int i0 = 0, i2 = 0;
-                if (idx < total) {
-                    i0 = (int)(((uint32_t)idx * m) >> 20);
-                    i2 = idx - i0 * n2;
-                    const float x0 = L.wx[l0][i0], z0 = L.wz[l0][i0];
+                if (i2 < jhi) {
                     const float x2 = L.wx[l2][i2], z2 = L.wz[l2][i2];
                     txd = (x2 - x0) / (z2 - z0);
                     pass = !(low_p && !((txd - tx_in) * qop > 0.0f));
@@ -261,6 +390,10 @@ struct Track {
                     if (!(fabsf(xm - x_mag) < tol)) pass = false;
                 }
                 const uint64_t bal = __ballot(pass);
+                if constexpr (CNT) {
+                    cnt[C_PAIRS_TESTED] += (uint32_t)__popcll(__ballot(i2 < jhi));
+                    cnt[C_DOUBLETS] += (uint32_t)__popcll(bal);
+                }
                 if (pass) {
                     const int at = qn + lanes_below(bal);
                     L.qkey[at] = ((uint32_t)s << 16) | ((uint32_t)i0 << 8) | (uint32_t)i2;
@@ -287,6 +420,7 @@ struct Track {
         }
 
         const size_t o12 = (size_t)t * NL;
+        if constexpr (CNT) cnt[C_KEPT] = (uint32_t)nL;
         if (nL == 0) {
             write_none(t, o12);
             return;
@@ -332,27 +466,25 @@ struct Track {
             const float u = P->z[l] - P->z_ref;
             const float xe = a + b * u + c * g_of(u, dR);
             const int n = L.wlen[l];
-            int best = -1;
+            const float *wxl = L.wx[l];
             float bd = INFINITY;
             if (slot < 3) {
-                for (int j = 0; j < n; ++j) {
-                    const float d = fabsf(L.wx[l][j] - xe);
-                    if (d < bd) { bd = d; best = j; }
-                }
+                const int best = closest_sorted([wxl](int j) { return wxl[j]; }, n, xe, bd);
                 if (best >= 0 && bd * bd < P->T_x) L.ch[r][l] = (int8_t)best;
             } else {
+                // the hit's x at y = 0 moved along its fibre to the predicted y; with a
+                // common stereo slope in the window these values stay sorted
                 const float yp = y_in + ty_in * (P->z[l] - P->z_in);
-                for (int j = 0; j < n; ++j) {
-                    const float d = fabsf(L.wx[l][j] + L.wd[l][j] * yp - xe);
-                    if (d < bd) { bd = d; best = j; }
-                }
+                const float *wdl = L.wd[l];
+                auto val = [wxl, wdl, yp](int j) { return wxl[j] + wdl[j] * yp; };
+                const int best = ((dvar >> l) & 1u) ? closest_scan(val, n, xe, bd) : closest_sorted(val, n, xe, bd);
                 if (best >= 0 && bd * bd < T_uv) L.ch[r][l] = (int8_t)best;
             }
         }
         wave_sync();
 
         // ---- fits and quality, one lane per candidate ----
-        bool acc = false;
+        bool acc = false, fit_lane = false;
         float Qb = 0.0f, fa = 0.0f, fb = 0.0f, fc = 0.0f, fy0 = 0.0f, fty = 0.0f;
         int nb = 0;
         if (lane < nL) {
@@ -367,6 +499,7 @@ struct Track {
 #pragma unroll
             for (int st = 0; st < 3; ++st)
                 if (hits[4 * st + 1] < 0 && hits[4 * st + 2] < 0) st_ok = false;
+            if constexpr (CNT) fit_lane = n >= 9 && st_ok;
             if (n >= 9 && st_ok) {
                 const float a = L.ca[lane], b = L.cb[lane], c = L.cc[lane];
                 float su[NL], sh[NL], rho[NL];
@@ -461,6 +594,11 @@ struct Track {
         }
 
         // ---- best candidate: argmin (Q, rank) over the wave ----
+        if constexpr (CNT) {
+            cnt[C_FITTED] = (uint32_t)__popcll(__ballot(fit_lane));
+            cnt[C_ACCEPTED] = (uint32_t)__popcll(__ballot(acc));
+            cnt[C_FOUND] = __ballot(acc) != 0;
+        }
         if (__ballot(acc) == 0) {
             write_none(t, o12);
             return;
@@ -510,7 +648,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_plain(DevBatch B, const KParams 
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const uint32_t t = B.trk_off[ev] + blockIdx.x * WPB + w;
     if (t >= B.trk_off[ev + 1]) return;
-    Track<NW> tr{B, P, lds[w], 0, 0};
+    Track<NW> tr{B, P, lds[w], 0, 0, {}};
     tr.run(t, ev);
 }
 
@@ -519,7 +657,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_plain(DevBatch B, const KParams 
 // event share one L2 and its hits are fetched from HBM once per XCD.
 constexpr uint32_t NXCD = 8;
 
-template <int NW, int WPB>
+template <int NW, int WPB, bool CNT = false>
 __global__ __launch_bounds__(WPB * WAVE) void k_grid(DevBatch B, const KParams *__restrict__ P) {
     __shared__ WaveLds<NW> lds[WPB];
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -527,8 +665,12 @@ __global__ __launch_bounds__(WPB * WAVE) void k_grid(DevBatch B, const KParams *
     const uint32_t lb = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
     const uint32_t t = lb * WPB + w;
     if (t >= B.n_tracks) return;
-    Track<NW> tr{B, P, lds[w], 0, 0};
+    Track<NW, CNT> tr{B, P, lds[w], 0, 0, {}};
     tr.run(t, B.trk_ev[t]);
+    if constexpr (CNT) {
+        if (lane_id() == 0)
+            for (int k = 0; k < C_N; ++k) atomicAdd(&B.stats[k], (unsigned long long)tr.cnt[k]);
+    }
 }
 
 // Persistent: one work queue per XCD over a contiguous eighth of the
@@ -567,7 +709,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_persistent(DevBatch B, const KPa
             // keep per-track loads inside the loop: hoisting them across tracks
             // costs ~30 VGPRs of loop-carried state and two waves per SIMD
             asm volatile("" ::: "memory");
-            Track<NW> tr{B, P, lds[w], 0, 0};
+            Track<NW> tr{B, P, lds[w], 0, 0, {}};
             tr.run(t, B.trk_ev[t]);
         }
     }
@@ -598,20 +740,20 @@ template <int NW, int WPB>
 hipError_t launch_nw_wpb(const DevBatch &b, const KParams *P, int mode, const ExecCfg &cfg,
                          const uint32_t *trk_off_host, hipStream_t s) {
     const dim3 block(WPB * WAVE);
-    if (mode == 0) {
+    if (mode == 0) {   // plain: one launch per event
         for (uint32_t e = 0; e < b.n_events; ++e) {
             const uint32_t nt = trk_off_host[e + 1] - trk_off_host[e];
             if (nt == 0) continue;
             hipLaunchKernelGGL((k_plain<NW, WPB>), dim3((nt + WPB - 1) / WPB), block, 0, s, b, P, e);
         }
-    } else if (mode == 1) {
+    } else if (mode == 2) {   // persistent: resident waves, per-XCD work queues
         uint32_t grid = (uint32_t)(cfg.blocks_per_cu * cfg.n_cu);
         const uint32_t need = (b.n_tracks + WPB - 1) / WPB;
         if (grid > need) grid = need;
         if (grid == 0) grid = 1;
         hipLaunchKernelGGL((k_persistent<NW, WPB>), dim3(grid), block, 0, s, b, P,
                            (uint32_t)cfg.items_per_grab);
-    } else {
+    } else {   // batched: one launch, one wavefront per track, XCD-ordered
         const uint32_t need = (b.n_tracks + WPB - 1) / WPB;
         const uint32_t grid = (need + NXCD - 1) / NXCD * NXCD;
         if (grid) hipLaunchKernelGGL((k_grid<NW, WPB>), dim3(grid), block, 0, s, b, P);
@@ -630,6 +772,15 @@ hipError_t launch_nw(const DevBatch &b, const KParams *P, int mode, const ExecCf
 }
 
 }  // namespace
+
+hipError_t launch_count(const DevBatch &b, const KParams *P, int n_hits_window, hipStream_t s) {
+    if (b.n_tracks == 0) return hipSuccess;
+    const uint32_t need = (b.n_tracks + 1) / 2;
+    const uint32_t grid = (need + NXCD - 1) / NXCD * NXCD;
+    if (n_hits_window <= 32) hipLaunchKernelGGL((k_grid<32, 2, true>), dim3(grid), dim3(2 * WAVE), 0, s, b, P);
+    else hipLaunchKernelGGL((k_grid<64, 2, true>), dim3(grid), dim3(2 * WAVE), 0, s, b, P);
+    return hipGetLastError();
+}
 
 hipError_t launch_track_event(const DevBatch &b, hipStream_t s) {
     if (b.n_tracks == 0) return hipSuccess;

@@ -26,8 +26,10 @@ LF_ERR_DEVICE = -4
 LF_ERR_STATE = -5
 LF_MODE_PLAIN = 0
 LF_MODE_BATCHED = 1
-LF_MODE_GRID = 2
-MODES = {"plain": LF_MODE_PLAIN, "batched": LF_MODE_BATCHED, "grid": LF_MODE_GRID}
+LF_MODE_PERSISTENT = 2
+MODES = {"plain": LF_MODE_PLAIN, "batched": LF_MODE_BATCHED, "persistent": LF_MODE_PERSISTENT}
+WORK_COUNTERS = ("tracks", "pairs_all", "seed_items", "pairs_tested", "doublets", "triplets", "kept",
+                 "fitted", "accepted", "staged_hits", "found")
 
 
 class LFError(RuntimeError):
@@ -71,9 +73,9 @@ class lf_exec(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32)]
 
 
-EXPORTS = ("lf_default_params", "lf_check_batch", "lf_create", "lf_upload_events", "lf_find_tracks", "lf_fetch_tracks",
-           "lf_release_batch", "lf_set_exec", "lf_batch_info", "lf_device_bytes_in_use", "lf_destroy",
-           "lf_last_error")
+EXPORTS = ("lf_default_params", "lf_check_batch", "lf_create", "lf_upload_events", "lf_find_tracks",
+           "lf_work_counts", "lf_fetch_tracks", "lf_release_batch", "lf_set_exec", "lf_batch_info",
+           "lf_device_bytes_in_use", "lf_destroy", "lf_last_error")
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -95,6 +97,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lf_upload_events.argtypes = [vp, P(lf_batch), vp, P(u64)]
     lib.lf_find_tracks.argtypes = [vp, u64, i32, vp]
     lib.lf_fetch_tracks.argtypes = [vp, u64, P(lf_tracks_out), sz, vp]
+    lib.lf_work_counts.argtypes = [vp, u64, vp, P(ctypes.c_int64), sz]
     lib.lf_release_batch.argtypes = [vp, u64]
     lib.lf_set_exec.argtypes = [vp, P(lf_exec)]
     lib.lf_batch_info.argtypes = [vp, u64, P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32), P(sz)]
@@ -104,8 +107,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lf_destroy.restype = None
     lib.lf_last_error.argtypes = [vp]
     lib.lf_last_error.restype = ctypes.c_char_p
-    for name in ("lf_check_batch", "lf_create", "lf_upload_events", "lf_find_tracks", "lf_fetch_tracks", "lf_release_batch",
-                 "lf_set_exec", "lf_batch_info"):
+    for name in ("lf_check_batch", "lf_create", "lf_upload_events", "lf_find_tracks", "lf_work_counts",
+                 "lf_fetch_tracks", "lf_release_batch", "lf_set_exec", "lf_batch_info"):
         getattr(lib, name).restype = i32
     return lib
 
@@ -228,6 +231,14 @@ def lf_find_tracks(ctx, batch_id: int, mode=LF_MODE_BATCHED, stream=None) -> Non
     if isinstance(mode, str):
         mode = MODES[mode]
     _check(lib().lf_find_tracks(ctx, ctypes.c_uint64(batch_id), int(mode), _stream(stream)), ctx)
+
+
+def lf_work_counts(ctx, batch_id: int, stream=None) -> dict:
+    """Work counters of one counting pass over a resident batch."""
+    n = len(WORK_COUNTERS)
+    arr = (ctypes.c_int64 * n)()
+    _check(lib().lf_work_counts(ctx, ctypes.c_uint64(batch_id), _stream(stream), arr, n), ctx)
+    return {k: int(arr[i]) for i, k in enumerate(WORK_COUNTERS)}
 
 
 def lf_fetch_tracks(ctx, batch_id: int, n_tracks: int | None = None, stream=None) -> dict:

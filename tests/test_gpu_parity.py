@@ -10,7 +10,7 @@ import oracle
 from parity import W, compare, oracle_on_events, run_gpu, say
 
 pytestmark = pytest.mark.gpu
-MODES = ("plain", "batched", "grid")
+MODES = ("plain", "batched", "persistent")
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -98,7 +98,7 @@ def test_geometry_variants():
 def test_launch_configurations(exec_cfg):
     ev = lfgen.generate("nominal", n_events=6)
     ref = oracle.run(ev, W)
-    for mode in ("batched", "grid", "plain"):
+    for mode in ("batched", "persistent", "plain"):
         say(f"[gpu] exec {exec_cfg} mode={mode}")
         compare(ref, run_gpu(ev, mode, None, exec_cfg), label=f"exec/{mode}")
 
@@ -125,6 +125,35 @@ def test_large_batches_sampled():
         ref, rows = oracle_on_events(ev, events)
         st = compare(ref, got, rows=rows, label=f"{name}[{n}]")
         say(f"    found={st['found']} bit-exact params {st['bit_exact_params']}/{st['params']}")
+
+
+def test_work_counters_match_oracle():
+    """The counting build's per-stage totals equal the oracle's intermediate counts."""
+    from paper_2402_14670_amd import lf
+    ev = lfgen.generate("nominal", n_events=10)
+    o = oracle.run(ev, W, debug=True)
+    n = (o["win"][:, :, 1] - o["win"][:, :, 0]).astype(np.int64)
+    ctx = lf.lf_create(W)
+    try:
+        bid = lf.lf_upload_events(ctx, ev)
+        say("[gpu] work counters, nominal[10]")
+        wc = lf.lf_work_counts(ctx, bid)
+        got = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks)
+    finally:
+        lf.lf_destroy(ctx)
+    compare(oracle.run(ev, W), got, label="counting build")
+    c = o["counts"]
+    assert wc["tracks"] == ev.n_tracks
+    assert wc["staged_hits"] == int(n.sum())
+    assert wc["pairs_all"] == int((n[:, 0] * n[:, 8] + n[:, 3] * n[:, 11]).sum())
+    assert wc["seed_items"] == int((n[:, 0] + n[:, 3]).sum())
+    assert wc["doublets"] == int(c[:, 1].sum())
+    assert wc["triplets"] == int(c[:, 2].sum())
+    assert wc["kept"] == int(np.minimum(c[:, 2], 12).sum())
+    assert wc["accepted"] == int(c[:, 3].sum())
+    assert wc["found"] == int(o["found"].sum())
+    assert wc["doublets"] <= wc["pairs_tested"] < wc["pairs_all"]
+    say(f"    {wc}")
 
 
 def test_determinism_and_event_order():
