@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--events", type=int, default=1000)
     ap.add_argument("--modes", default="batched,persistent,plain",
                     help="comma-separated subset of batched,persistent,plain to time (batched is always timed)")
+    ap.add_argument("--serve-requests", type=int, default=200000,
+                    help="requests per serving run (0 skips the serving runs)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a known-size reference for HBM "
                          "byte counters under a profiler)")
@@ -97,6 +99,39 @@ def time_mode(lf, ctx, bid, mode, steps, warmup, stream):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return start.elapsed_time(end) / steps, wall
+
+
+def serving(lf, ctx, ev, batched_out, n_requests, seed=40):
+    """Serving loop on the nominal events as a request pool: first saturated
+    (every request arrives at t = 0: the transfer-inclusive batched rate),
+    then open-loop Poisson arrivals at 50%, 80% and 95% of that rate.  Every
+    request's result digest is checked against the batched run's result."""
+    import numpy as np
+    ref = lf.result_digests(batched_out, ev.trk_off)
+    rng = np.random.default_rng(seed)
+    req = rng.integers(0, ev.n_events, size=n_requests).astype(np.uint32)
+    cfg = {"max_batch_events": 1024, "n_slots": 4, "n_pack_threads": 8, "device_budget_bytes": 8 << 30}
+    dig, lat, st = lf.lf_serve_run(ctx, ev, req, np.zeros(n_requests), cfg)
+    ok = bool(np.array_equal(dig, ref[req]))
+    sat = st["events_per_s"]
+    print(f"bench: serving saturated {sat:12.0f} events/s, mean batch {st['mean_batch_events']:.0f}",
+          file=sys.stderr, flush=True)
+    rates = []
+    for frac in (0.5, 0.8, 0.95):
+        arr = np.cumsum(rng.exponential(1.0 / (frac * sat), size=n_requests))
+        dig, lat, s2 = lf.lf_serve_run(ctx, ev, req, arr, cfg)
+        ok = ok and bool(np.array_equal(dig, ref[req]))
+        rates.append({"frac": frac, "offered_events_per_s": round(frac * sat, 1),
+                      "events_per_s": round(s2["events_per_s"], 1),
+                      "p50_ms": round(s2["lat_p50_s"] * 1e3, 4), "p99_ms": round(s2["lat_p99_s"] * 1e3, 4),
+                      "p999_ms": round(s2["lat_p999_s"] * 1e3, 4), "max_ms": round(s2["lat_max_s"] * 1e3, 4),
+                      "mean_batch_events": round(s2["mean_batch_events"], 1), "max_queue": s2["max_queue"]})
+        print(f"bench: serving {frac:4.2f}  {s2['events_per_s']:12.0f} events/s  p50 {s2['lat_p50_s']*1e3:.3f} ms"
+              f"  p99 {s2['lat_p99_s']*1e3:.3f} ms  mean batch {s2['mean_batch_events']:.0f}",
+              file=sys.stderr, flush=True)
+    return {"requests_per_run": n_requests, "pool_events": ev.n_events, "config": cfg,
+            "saturated_events_per_s": round(sat, 1), "rates": rates, "results_equal_batched": ok,
+            "latency": "arrival to results in host memory; uploads and downloads included"}
 
 
 def cpu_baseline(ev, world, min_seconds):
@@ -162,6 +197,7 @@ def main():
               flush=True)
     work = lf.lf_work_counts(ctx, bid, stream.cuda_stream)
     out = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
+    serve = serving(lf, ctx, ev, out, args.serve_requests) if args.serve_requests else None
     lf.lf_destroy(ctx)
 
     ms = res["batched"]
@@ -198,7 +234,10 @@ def main():
                      "hbm": {"algorithmic_bytes": nbytes, "achieved_GBs": round(nbytes / (ms * 1e-3) / 1e9, 1),
                              "peak_GBs": HBM_PEAK_GBS,
                              "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}},
-        "latency_ms": None,
+        "latency_ms": ({"p50": serve["rates"][1]["p50_ms"], "p99": serve["rates"][1]["p99_ms"],
+                        "p999": serve["rates"][1]["p999_ms"], "at": "serving, 80% of saturated throughput"}
+                       if serve else None),
+        "serving": serve,
     }
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(ev, world, args.cpu_seconds)

@@ -219,6 +219,50 @@ int lf_batch_info(lf_ctx *ctx, uint64_t batch_id, uint32_t *n_events, uint32_t *
 /* Device bytes held by resident batches. */
 size_t lf_device_bytes_in_use(const lf_ctx *ctx);
 
+/* Serving loop (continuous batching).  Configuration; zero fields take the
+ * defaults in brackets. */
+typedef struct {
+    uint32_t max_batch_events;   /* events per launch, at most [1024] */
+    uint32_t min_batch_events;   /* arrived events to wait for before launching [1] ... */
+    uint32_t max_wait_us;        /* ... unless the oldest has waited this long [0] */
+    uint32_t n_slots;            /* batches in flight, one stream each, 1..16 [4] */
+    uint32_t n_pack_threads;     /* host threads packing a batch, 1..32 [4] */
+    uint32_t reserved;
+    size_t device_budget_bytes;  /* admission budget for resident events [8 GiB] */
+} lf_serve_config;
+
+typedef struct {
+    uint64_t n_requests, n_batches;
+    uint64_t max_queue;          /* most arrived requests waiting for admission at once */
+    uint64_t max_device_bytes;   /* most device bytes held by admitted events at once */
+    double wall_s;               /* first arrival to last completion */
+    double events_per_s;         /* n_requests / wall_s */
+    double lat_p50_s, lat_p99_s, lat_p999_s, lat_max_s;  /* arrival to results in host memory */
+    double mean_batch_events;
+} lf_serve_stats;
+
+/* Runs a stream of requests through the serving loop and returns when all
+ * have completed.  The pool is a batch of distinct events (host memory,
+ * lf_batch layout; copied to pinned memory before the clock starts);
+ * request i is event req_event[i] of the pool arriving arrival_s[i] seconds
+ * after the start (non-decreasing; open loop: arrivals do not wait for
+ * service).  Arrived requests queue on the host and are admitted into a
+ * device ring of device_budget_bytes in arrival order (a request that does
+ * not fit waits: backpressure, nothing is dropped).  Whenever one of
+ * n_slots in-flight slots is free, every admitted request (up to
+ * max_batch_events) is packed into one batch and runs upload -> hot path
+ * (LF_MODE_BATCHED) -> digest -> download on the slot's stream.
+ * req_digest[i] (optional) receives a 64-bit digest of request i's results
+ * (FNV-1a over each track slot's 20 words -- found | n_hits << 8, 12 hit
+ * indices, bits of a b c y0 ty qop Q -- summed as splitmix64(h ^ index *
+ * 0x9E3779B97F4A7C15) over the event's tracks); req_latency_s[i]
+ * (optional) its arrival-to-results-on-host latency.
+ * Errors: LF_ERR_INVALID, LF_ERR_TOO_LARGE (an event exceeds the budget),
+ * LF_ERR_NOMEM, LF_ERR_DEVICE. */
+int lf_serve_run(lf_ctx *ctx, const lf_batch *pool, uint32_t n_requests, const uint32_t *req_event,
+                 const double *arrival_s, const lf_serve_config *config, uint64_t *req_digest,
+                 double *req_latency_s, lf_serve_stats *stats);
+
 /* Destroys the context and frees every resident batch.  NULL is ignored. */
 void lf_destroy(lf_ctx *ctx);
 

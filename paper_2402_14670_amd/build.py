@@ -13,13 +13,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblf_hip.so")
-SOURCES = [os.path.join(CSRC, "lf_api.cpp"), os.path.join(CSRC, "lf_kernels.hip")]
+SOURCES = [os.path.join(CSRC, "lf_api.cpp"), os.path.join(CSRC, "lf_serve.cpp"), os.path.join(CSRC, "lf_kernels.hip")]
 HEADERS = [os.path.join(CSRC, "lf_internal.h"), os.path.join(ROOT, "include", "lf.h")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LF_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
     "-ffp-contract=off", "-fno-fast-math", "-fno-gpu-flush-denormals-to-zero",
     "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

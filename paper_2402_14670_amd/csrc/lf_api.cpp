@@ -152,6 +152,14 @@ Layout layout(uint32_t E, uint32_t H, uint32_t T) {
 
 }  // namespace
 
+namespace lfapi {
+int ctx_fail(lf_ctx *c, int code, const std::string &msg) { return fail(c, code, msg); }
+const lfk::KParams *ctx_dparams(const lf_ctx *c) { return c->d_params; }
+int ctx_nhits_window(const lf_ctx *c) { return c->params.n_hits_window; }
+const lfk::ExecCfg &ctx_exec(const lf_ctx *c) { return c->exec; }
+int check_batch(const lf_batch *b, std::string &why) { return validate(b, why); }
+}  // namespace lfapi
+
 extern "C" {
 
 void lf_default_params(lf_params *p) {

@@ -771,7 +771,45 @@ hipError_t launch_nw(const DevBatch &b, const KParams *P, int mode, const ExecCf
     }
 }
 
+// Digest of one event's results: FNV-1a (64-bit) over the 20 words of each
+// track slot -- found | n_hits << 8, the 12 hit indices, the bits of a, b,
+// c, y0, ty, q/p, Q -- then the sum over the event's tracks of
+// splitmix64(h ^ (index * 0x9E3779B97F4A7C15)).  One block per event.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(WAVE) void k_digest(DevBatch B, const uint32_t *__restrict__ trk_off,
+                                                  unsigned long long *__restrict__ out) {
+    const uint32_t e = blockIdx.x;
+    const uint32_t t0 = trk_off[e], t1 = trk_off[e + 1];
+    unsigned long long acc = 0;
+    for (uint32_t t = t0 + threadIdx.x; t < t1; t += WAVE) {
+        uint32_t w[20];
+        w[0] = (uint32_t)B.found[t] | ((uint32_t)B.nhits[t] << 8);
+        for (int l = 0; l < NL; ++l) w[1 + l] = (uint32_t)B.hit_idx[(size_t)t * NL + l];
+        w[13] = __float_as_uint(B.a[t]); w[14] = __float_as_uint(B.b[t]); w[15] = __float_as_uint(B.c[t]);
+        w[16] = __float_as_uint(B.y0[t]); w[17] = __float_as_uint(B.ty[t]); w[18] = __float_as_uint(B.qop[t]);
+        w[19] = __float_as_uint(B.Q[t]);
+        unsigned long long h = 0xCBF29CE484222325ull;
+        for (int k = 0; k < 20; ++k) { h ^= w[k]; h *= 0x100000001B3ull; }
+        acc += mix64(h ^ ((unsigned long long)(t - t0) * 0x9E3779B97F4A7C15ull));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (threadIdx.x == 0) out[e] = acc;
+}
+
 }  // namespace
+
+hipError_t launch_digest(const DevBatch &b, const uint32_t *trk_off, uint32_t n_events, unsigned long long *out,
+                         hipStream_t s) {
+    if (n_events == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_digest, dim3(n_events), dim3(WAVE), 0, s, b, trk_off, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_count(const DevBatch &b, const KParams *P, int n_hits_window, hipStream_t s) {
     if (b.n_tracks == 0) return hipSuccess;

@@ -1,0 +1,479 @@
+// lf_serve.cpp -- trigger-style serving loop of the Looking Forward library.
+//
+// Requests are events that arrive over time (open loop: arrival times are
+// given, independent of service).  The loop keeps a FIFO of arrived
+// requests, admits them into a device-memory ring of a fixed budget, packs
+// whatever has been admitted into one batch as soon as an in-flight slot is
+// free (continuous batching: requests arriving while others run on the GPU
+// join the next batch), and runs upload -> hot path -> digest -> download on
+// that slot's stream, so copies and kernels of consecutive batches overlap.
+// A request completes when its results are in host memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <functional>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/lf.h"
+#include "lf_internal.h"
+
+namespace lfk {
+hipError_t launch_digest(const DevBatch &b, const uint32_t *trk_off, uint32_t n_events, unsigned long long *out,
+                         hipStream_t s);
+}
+
+// Context accessors shared with lf_api.cpp.
+namespace lfapi {
+int ctx_fail(lf_ctx *c, int code, const std::string &msg);
+const lfk::KParams *ctx_dparams(const lf_ctx *c);
+int ctx_nhits_window(const lf_ctx *c);
+const lfk::ExecCfg &ctx_exec(const lf_ctx *c);
+int check_batch(const lf_batch *b, std::string &why);
+}  // namespace lfapi
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Pool events as contiguous blobs in pinned host memory:
+// [hit_off local u32 x 25][x H][z H][dxdy H][trk x,y,tx,ty,qop: 5 x T].
+struct Pool {
+    char *blob = nullptr;
+    size_t bytes = 0;
+    std::vector<size_t> off;       // blob offset of each event
+    std::vector<uint32_t> nh, nt;  // hits, tracks per event
+};
+
+// Byte layout of one batch region (device ring and pinned staging share it).
+struct BatchLayout {
+    size_t hit_off, hx, hz, hd, trk_off, trk_ev, tx, ty, ttx, tty, tqop, in_bytes;
+    size_t dig, found, nhits, hit_idx, fl, out_bytes, total;
+    uint32_t E, H, T;
+};
+
+BatchLayout batch_layout(uint32_t E, uint32_t H, uint32_t T) {
+    BatchLayout L{};
+    L.E = E; L.H = H; L.T = T;
+    size_t o = 0;
+    auto put = [&](size_t n) { size_t at = o; o += a256(n ? n : 1); return at; };
+    L.hit_off = put(((size_t)E * 24 + 1) * 4);
+    L.hx = put((size_t)H * 4); L.hz = put((size_t)H * 4); L.hd = put((size_t)H * 4);
+    L.trk_off = put(((size_t)E + 1) * 4); L.trk_ev = put((size_t)T * 4);
+    L.tx = put((size_t)T * 4); L.ty = put((size_t)T * 4); L.ttx = put((size_t)T * 4);
+    L.tty = put((size_t)T * 4); L.tqop = put((size_t)T * 4);
+    L.in_bytes = o;
+    // outputs: one contiguous block so a single copy brings them back
+    const size_t ob = o;
+    L.dig = put((size_t)E * 8);
+    L.found = put(T); L.nhits = put(T); L.hit_idx = put((size_t)T * 48);
+    L.fl = put((size_t)T * 28);
+    L.out_bytes = o - ob;
+    L.total = o;
+    return L;
+}
+
+// Fixed set of worker threads splitting a range of work.
+class Workers {
+  public:
+    explicit Workers(int n) : n_(n < 1 ? 1 : n) {
+        for (int i = 1; i < n_; ++i) th_.emplace_back([this, i] { loop(i); });
+    }
+    ~Workers() {
+        {
+            std::lock_guard<std::mutex> g(m_);
+            stop_ = true;
+            ++gen_;
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
+    }
+    // Runs f(i, n) on every worker i of n (the caller is worker 0) and waits.
+    void run(const std::function<void(int, int)> &f) {
+        {
+            std::lock_guard<std::mutex> g(m_);
+            f_ = &f;
+            left_ = n_ - 1;
+            ++gen_;
+        }
+        cv_.notify_all();
+        f(0, n_);
+        std::unique_lock<std::mutex> g(m_);
+        done_.wait(g, [this] { return left_ == 0; });
+    }
+
+  private:
+    void loop(int i) {
+        uint64_t seen = 0;
+        for (;;) {
+            const std::function<void(int, int)> *f;
+            {
+                std::unique_lock<std::mutex> g(m_);
+                cv_.wait(g, [&] { return gen_ != seen; });
+                seen = gen_;
+                if (stop_) return;
+                f = f_;
+            }
+            (*f)(i, n_);
+            {
+                std::lock_guard<std::mutex> g(m_);
+                if (--left_ == 0) done_.notify_one();
+            }
+        }
+    }
+    int n_;
+    std::vector<std::thread> th_;
+    std::mutex m_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int, int)> *f_ = nullptr;
+    int left_ = 0;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    char *stage = nullptr;   // pinned, inputs of one batch
+    char *out = nullptr;     // pinned, outputs of one batch
+    size_t stage_cap = 0, out_cap = 0;
+    bool busy = false;
+    size_t ring_at = 0, ring_bytes = 0;
+    BatchLayout lay{};
+    std::vector<uint32_t> reqs;  // requests in this batch
+};
+
+// FIFO allocator over the device budget.  Batches free in submission order
+// (the oldest in-flight region is released first).
+struct Ring {
+    size_t cap = 0, head = 0, used = 0;
+    std::deque<std::pair<size_t, size_t>> live;  // (start, bytes incl. wrap waste)
+    bool alloc(size_t n, size_t &at, size_t &charged) {
+        if (n > cap) return false;
+        size_t start = head, waste = 0;
+        if (start + n > cap) { waste = cap - start; start = 0; }
+        if (used + waste + n > cap) return false;
+        at = start;
+        charged = waste + n;
+        head = start + n;
+        used += charged;
+        live.emplace_back(at, charged);
+        return true;
+    }
+    void free_front() {
+        used -= live.front().second;
+        live.pop_front();
+        if (live.empty()) { head = 0; used = 0; }
+    }
+};
+
+}  // namespace
+
+extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requests, const uint32_t *req_event,
+                            const double *arrival_s, const lf_serve_config *cfg_in, uint64_t *req_digest,
+                            double *req_latency_s, lf_serve_stats *stats) {
+    if (!ctx) return LF_ERR_INVALID;
+    if (!pool_b || !req_event || !arrival_s || !cfg_in)
+        return lfapi::ctx_fail(ctx, LF_ERR_INVALID, "lf_serve_run: NULL argument");
+    std::string why;
+    if (!lfapi::check_batch(pool_b, why)) return lfapi::ctx_fail(ctx, LF_ERR_INVALID, "lf_serve_run: pool " + why);
+    lf_serve_config cfg = *cfg_in;
+    if (cfg.max_batch_events == 0) cfg.max_batch_events = 1024;
+    if (cfg.n_slots == 0) cfg.n_slots = 4;
+    if (cfg.n_pack_threads == 0) cfg.n_pack_threads = 4;
+    if (cfg.device_budget_bytes == 0) cfg.device_budget_bytes = size_t(8) << 30;
+    if (cfg.n_slots > 16 || cfg.n_pack_threads > 32 || cfg.max_batch_events > (1u << 20))
+        return lfapi::ctx_fail(ctx, LF_ERR_INVALID, "lf_serve_run: configuration out of range");
+    const uint32_t PE = pool_b->n_events;
+    for (uint32_t i = 0; i < n_requests; ++i) {
+        if (req_event[i] >= PE) return lfapi::ctx_fail(ctx, LF_ERR_INVALID, "lf_serve_run: request event out of range");
+        if (!(arrival_s[i] >= 0.0) || (i && arrival_s[i] < arrival_s[i - 1]))
+            return lfapi::ctx_fail(ctx, LF_ERR_INVALID, "lf_serve_run: arrival times must be >= 0 and non-decreasing");
+    }
+
+    // ---- pool blobs in pinned memory (the events as delivered to the host) ----
+    Pool pool;
+    pool.off.resize(PE);
+    pool.nh.resize(PE);
+    pool.nt.resize(PE);
+    size_t pbytes = 0;
+    for (uint32_t e = 0; e < PE; ++e) {
+        pool.nh[e] = pool_b->hit_off[24 * (size_t)e + 24] - pool_b->hit_off[24 * (size_t)e];
+        pool.nt[e] = pool_b->trk_off[e + 1] - pool_b->trk_off[e];
+        pool.off[e] = pbytes;
+        pbytes += a256(25 * 4 + (size_t)pool.nh[e] * 12 + (size_t)pool.nt[e] * 20);
+    }
+    size_t max_event_bytes = 0;
+    for (uint32_t e = 0; e < PE; ++e) {
+        const BatchLayout one = batch_layout(1, pool.nh[e], pool.nt[e]);
+        max_event_bytes = std::max(max_event_bytes, one.total);
+    }
+    if (max_event_bytes > cfg.device_budget_bytes)
+        return lfapi::ctx_fail(ctx, LF_ERR_TOO_LARGE, "lf_serve_run: an event is larger than the device budget");
+
+    std::vector<Slot> slots(cfg.n_slots);
+    void *ring_mem = nullptr;
+    hipError_t err = hipHostMalloc(reinterpret_cast<void **>(&pool.blob), pbytes ? pbytes : 1, hipHostMallocDefault);
+    if (err != hipSuccess) return lfapi::ctx_fail(ctx, LF_ERR_NOMEM, "lf_serve_run: pinned pool allocation failed");
+    pool.bytes = pbytes;
+    auto cleanup = [&]() {
+        for (auto &s : slots) {
+            if (s.stream) (void)hipStreamSynchronize(s.stream);
+            if (s.done) (void)hipEventDestroy(s.done);
+            if (s.stream) (void)hipStreamDestroy(s.stream);
+            if (s.stage) (void)hipHostFree(s.stage);
+            if (s.out) (void)hipHostFree(s.out);
+        }
+        if (ring_mem) (void)hipFree(ring_mem);
+        if (pool.blob) (void)hipHostFree(pool.blob);
+    };
+    for (uint32_t e = 0; e < PE; ++e) {
+        char *p = pool.blob + pool.off[e];
+        const uint32_t h0 = pool_b->hit_off[24 * (size_t)e], t0 = pool_b->trk_off[e];
+        uint32_t *ho = reinterpret_cast<uint32_t *>(p);
+        for (int b = 0; b < 25; ++b) ho[b] = pool_b->hit_off[24 * (size_t)e + b] - h0;
+        char *q = p + 100;
+        const size_t H = pool.nh[e], T = pool.nt[e];
+        std::memcpy(q, pool_b->hit_x + h0, H * 4); q += H * 4;
+        std::memcpy(q, pool_b->hit_z + h0, H * 4); q += H * 4;
+        std::memcpy(q, pool_b->hit_dxdy + h0, H * 4); q += H * 4;
+        const float *src[5] = {pool_b->trk_x, pool_b->trk_y, pool_b->trk_tx, pool_b->trk_ty, pool_b->trk_qop};
+        for (int k = 0; k < 5; ++k) { std::memcpy(q, src[k] + t0, T * 4); q += T * 4; }
+    }
+
+    // ---- device ring, slots ----
+    Ring ring;
+    ring.cap = cfg.device_budget_bytes;
+    err = hipMalloc(&ring_mem, ring.cap);
+    if (err != hipSuccess) {
+        cleanup();
+        return lfapi::ctx_fail(ctx, LF_ERR_NOMEM, "lf_serve_run: device budget allocation failed");
+    }
+    // staging sized for the largest batch the budget and the event cap allow
+    uint64_t big_h = 0, big_t = 0;
+    {
+        std::vector<uint32_t> hs(pool.nh), ts(pool.nt);
+        std::sort(hs.rbegin(), hs.rend());
+        std::sort(ts.rbegin(), ts.rend());
+        for (uint32_t i = 0; i < std::min<uint32_t>(cfg.max_batch_events, PE); ++i) { big_h += hs[i]; big_t += ts[i]; }
+        // a batch may repeat the largest event
+        if (cfg.max_batch_events > PE) {
+            big_h += (uint64_t)hs[0] * (cfg.max_batch_events - PE);
+            big_t += (uint64_t)ts[0] * (cfg.max_batch_events - PE);
+        }
+    }
+    if (big_h >= 0x7fffffffull || big_t >= 0x7fffffffull) {
+        cleanup();
+        return lfapi::ctx_fail(ctx, LF_ERR_INVALID, "lf_serve_run: max_batch_events too large for 32-bit indices");
+    }
+    const BatchLayout biggest = batch_layout(cfg.max_batch_events, (uint32_t)big_h, (uint32_t)big_t);
+    for (auto &s : slots) {
+        err = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
+        if (err == hipSuccess) err = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+        if (err == hipSuccess) err = hipHostMalloc(reinterpret_cast<void **>(&s.stage), biggest.in_bytes, hipHostMallocDefault);
+        if (err == hipSuccess) err = hipHostMalloc(reinterpret_cast<void **>(&s.out), biggest.out_bytes, hipHostMallocDefault);
+        if (err != hipSuccess) {
+            cleanup();
+            return lfapi::ctx_fail(ctx, LF_ERR_NOMEM, "lf_serve_run: slot allocation failed");
+        }
+        s.stage_cap = biggest.in_bytes;
+        s.out_cap = biggest.out_bytes;
+    }
+    Workers workers((int)cfg.n_pack_threads);
+    const lfk::KParams *P = lfapi::ctx_dparams(ctx);
+    const int nhw = lfapi::ctx_nhits_window(ctx);
+    const lfk::ExecCfg exec = lfapi::ctx_exec(ctx);
+
+    // ---- the loop ----
+    std::vector<double> lat(n_requests, 0.0);
+    std::deque<uint32_t> queue;       // arrived, not yet in a batch
+    std::deque<uint32_t> inflight;    // slot indices in submission order
+    uint32_t next_arrival = 0, completed = 0;
+    uint64_t n_batches = 0, batched_events = 0, max_queue = 0;
+    size_t max_dev = 0;
+    int rc = LF_OK;
+    const Clock::time_point t0 = Clock::now();
+    auto now_s = [&]() { return std::chrono::duration<double>(Clock::now() - t0).count(); };
+    double last_done = 0.0;
+
+    while (completed < n_requests && rc == LF_OK) {
+        bool progress = false;
+        // completions, in submission order
+        while (!inflight.empty()) {
+            Slot &s = slots[inflight.front()];
+            const hipError_t q = hipEventQuery(s.done);
+            if (q == hipErrorNotReady) break;
+            if (q != hipSuccess) { rc = lfapi::ctx_fail(ctx, LF_ERR_DEVICE, std::string("lf_serve_run: ") + hipGetErrorString(q)); break; }
+            const double t = now_s();
+            const unsigned long long *dig = reinterpret_cast<const unsigned long long *>(s.out);
+            for (size_t k = 0; k < s.reqs.size(); ++k) {
+                const uint32_t r = s.reqs[k];
+                lat[r] = t - arrival_s[r];
+                if (req_digest) req_digest[r] = dig[k];
+            }
+            completed += (uint32_t)s.reqs.size();
+            last_done = t;
+            ring.free_front();
+            s.busy = false;
+            inflight.pop_front();
+            progress = true;
+        }
+        if (rc != LF_OK) break;
+        // arrivals
+        const double t = now_s();
+        while (next_arrival < n_requests && arrival_s[next_arrival] <= t) queue.push_back(next_arrival++);
+        max_queue = std::max<uint64_t>(max_queue, queue.size());
+        // form a batch on a free slot
+        int free_slot = -1;
+        for (uint32_t i = 0; i < cfg.n_slots; ++i)
+            if (!slots[i].busy) { free_slot = (int)i; break; }
+        if (free_slot >= 0 && !queue.empty()) {
+            const bool more_coming = next_arrival < n_requests;
+            const double waited = t - arrival_s[queue.front()];
+            if (queue.size() >= std::max<uint32_t>(1, cfg.min_batch_events) || !more_coming ||
+                waited * 1e6 >= cfg.max_wait_us) {
+                Slot &s = slots[free_slot];
+                // take requests while the batch fits the staging buffers and the ring
+                uint64_t H = 0, T = 0;
+                uint32_t E = 0;
+                size_t at = 0, charged = 0;
+                BatchLayout lay{};
+                while (E < queue.size() && E < cfg.max_batch_events) {
+                    const uint32_t ev = req_event[queue[E]];
+                    const BatchLayout trial = batch_layout(E + 1, (uint32_t)(H + pool.nh[ev]), (uint32_t)(T + pool.nt[ev]));
+                    if (trial.in_bytes > s.stage_cap || trial.out_bytes > s.out_cap) break;
+                    if (ring.used + trial.total > ring.cap) break;   // admission: the budget is full
+                    H += pool.nh[ev];
+                    T += pool.nt[ev];
+                    ++E;
+                    lay = trial;
+                }
+                if (E > 0 && ring.alloc(lay.total, at, charged)) {
+                    s.reqs.assign(queue.begin(), queue.begin() + E);
+                    queue.erase(queue.begin(), queue.begin() + E);
+                    s.lay = lay;
+                    s.ring_at = at;
+                    s.ring_bytes = charged;
+                    max_dev = std::max(max_dev, ring.used);
+                    // offsets of every event in the batch
+                    std::vector<uint64_t> hb(E + 1), tb(E + 1);
+                    hb[0] = tb[0] = 0;
+                    for (uint32_t k = 0; k < E; ++k) {
+                        const uint32_t ev = req_event[s.reqs[k]];
+                        hb[k + 1] = hb[k] + pool.nh[ev];
+                        tb[k + 1] = tb[k] + pool.nt[ev];
+                    }
+                    char *st = s.stage;
+                    uint32_t *ho = reinterpret_cast<uint32_t *>(st + lay.hit_off);
+                    uint32_t *to = reinterpret_cast<uint32_t *>(st + lay.trk_off);
+                    uint32_t *tev = reinterpret_cast<uint32_t *>(st + lay.trk_ev);
+                    float *tr[5] = {reinterpret_cast<float *>(st + lay.tx), reinterpret_cast<float *>(st + lay.ty),
+                                    reinterpret_cast<float *>(st + lay.ttx), reinterpret_cast<float *>(st + lay.tty),
+                                    reinterpret_cast<float *>(st + lay.tqop)};
+                    float *hx = reinterpret_cast<float *>(st + lay.hx);
+                    float *hz = reinterpret_cast<float *>(st + lay.hz);
+                    float *hd = reinterpret_cast<float *>(st + lay.hd);
+                    const std::vector<uint32_t> &reqs = s.reqs;
+                    workers.run([&](int w, int nw) {
+                        const uint32_t e0 = (uint32_t)((uint64_t)E * w / nw), e1 = (uint32_t)((uint64_t)E * (w + 1) / nw);
+                        for (uint32_t k = e0; k < e1; ++k) {
+                            const uint32_t ev = req_event[reqs[k]];
+                            const char *p = pool.blob + pool.off[ev];
+                            const uint32_t *lo = reinterpret_cast<const uint32_t *>(p);
+                            for (int b = 0; b < 24; ++b) ho[24 * (size_t)k + b] = (uint32_t)hb[k] + lo[b];
+                            const size_t nh = pool.nh[ev], nt = pool.nt[ev];
+                            const char *q = p + 100;
+                            std::memcpy(hx + hb[k], q, nh * 4); q += nh * 4;
+                            std::memcpy(hz + hb[k], q, nh * 4); q += nh * 4;
+                            std::memcpy(hd + hb[k], q, nh * 4); q += nh * 4;
+                            for (int j = 0; j < 5; ++j) { std::memcpy(tr[j] + tb[k], q, nt * 4); q += nt * 4; }
+                            to[k] = (uint32_t)tb[k];
+                            for (size_t i = 0; i < nt; ++i) tev[tb[k] + i] = k;
+                        }
+                    });
+                    ho[24 * (size_t)E] = (uint32_t)H;
+                    to[E] = (uint32_t)T;
+                    // device view of the region
+                    char *dr = static_cast<char *>(ring_mem) + at;
+                    lfk::DevBatch d{};
+                    d.hit_off = reinterpret_cast<const uint32_t *>(dr + lay.hit_off);
+                    d.hx = reinterpret_cast<const float *>(dr + lay.hx);
+                    d.hz = reinterpret_cast<const float *>(dr + lay.hz);
+                    d.hd = reinterpret_cast<const float *>(dr + lay.hd);
+                    d.trk_off = reinterpret_cast<const uint32_t *>(dr + lay.trk_off);
+                    d.trk_ev = reinterpret_cast<const uint32_t *>(dr + lay.trk_ev);
+                    d.tx_ = reinterpret_cast<const float *>(dr + lay.tx);
+                    d.ty_ = reinterpret_cast<const float *>(dr + lay.ty);
+                    d.ttx = reinterpret_cast<const float *>(dr + lay.ttx);
+                    d.tty = reinterpret_cast<const float *>(dr + lay.tty);
+                    d.tqop = reinterpret_cast<const float *>(dr + lay.tqop);
+                    d.found = reinterpret_cast<uint8_t *>(dr + lay.found);
+                    d.nhits = reinterpret_cast<uint8_t *>(dr + lay.nhits);
+                    d.hit_idx = reinterpret_cast<int32_t *>(dr + lay.hit_idx);
+                    float *fl = reinterpret_cast<float *>(dr + lay.fl);
+                    d.a = fl; d.b = fl + T; d.c = fl + 2 * T; d.y0 = fl + 3 * T;
+                    d.ty = fl + 4 * T; d.qop = fl + 5 * T; d.Q = fl + 6 * T;
+                    d.counter = nullptr;
+                    d.stats = nullptr;
+                    d.n_events = E;
+                    d.n_tracks = (uint32_t)T;
+                    hipError_t e = hipMemcpyAsync(dr, st, lay.in_bytes, hipMemcpyHostToDevice, s.stream);
+                    if (e == hipSuccess) e = lfk::launch_find(d, P, nhw, 1, exec, nullptr, s.stream);
+                    if (e == hipSuccess)
+                        e = lfk::launch_digest(d, d.trk_off, E, reinterpret_cast<unsigned long long *>(dr + lay.dig),
+                                               s.stream);
+                    if (e == hipSuccess)
+                        e = hipMemcpyAsync(s.out, dr + lay.dig, lay.out_bytes, hipMemcpyDeviceToHost, s.stream);
+                    if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
+                    if (e != hipSuccess) {
+                        rc = lfapi::ctx_fail(ctx, LF_ERR_DEVICE, std::string("lf_serve_run: ") + hipGetErrorString(e));
+                        break;
+                    }
+                    s.busy = true;
+                    inflight.push_back((uint32_t)free_slot);
+                    ++n_batches;
+                    batched_events += E;
+                    progress = true;
+                }
+            }
+        }
+        if (!progress) std::this_thread::yield();
+    }
+    for (auto &s : slots) (void)hipStreamSynchronize(s.stream);
+    cleanup();
+    if (rc != LF_OK) return rc;
+
+    if (req_latency_s) std::memcpy(req_latency_s, lat.data(), n_requests * sizeof(double));
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        std::vector<double> l(lat);
+        std::sort(l.begin(), l.end());
+        auto pct = [&](double p) {
+            if (l.empty()) return 0.0;
+            size_t k = (size_t)(p * (double)(l.size() - 1) + 0.5);
+            return l[std::min(k, l.size() - 1)];
+        };
+        const double first = n_requests ? arrival_s[0] : 0.0;
+        stats->n_requests = n_requests;
+        stats->n_batches = n_batches;
+        stats->wall_s = last_done - first;
+        stats->events_per_s = stats->wall_s > 0 ? n_requests / stats->wall_s : 0.0;
+        stats->lat_p50_s = pct(0.50);
+        stats->lat_p99_s = pct(0.99);
+        stats->lat_p999_s = pct(0.999);
+        stats->lat_max_s = l.empty() ? 0.0 : l.back();
+        stats->mean_batch_events = n_batches ? (double)batched_events / n_batches : 0.0;
+        stats->max_device_bytes = max_dev;
+        stats->max_queue = max_queue;
+    }
+    return LF_OK;
+}

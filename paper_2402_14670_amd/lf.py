@@ -68,6 +68,21 @@ class lf_tracks_out(ctypes.Structure):
                                                 "qop", "Q")]
 
 
+class lf_serve_config(ctypes.Structure):
+    _fields_ = [("max_batch_events", ctypes.c_uint32), ("min_batch_events", ctypes.c_uint32),
+                ("max_wait_us", ctypes.c_uint32), ("n_slots", ctypes.c_uint32),
+                ("n_pack_threads", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("device_budget_bytes", ctypes.c_size_t)]
+
+
+class lf_serve_stats(ctypes.Structure):
+    _fields_ = [("n_requests", ctypes.c_uint64), ("n_batches", ctypes.c_uint64), ("max_queue", ctypes.c_uint64),
+                ("max_device_bytes", ctypes.c_uint64), ("wall_s", ctypes.c_double),
+                ("events_per_s", ctypes.c_double), ("lat_p50_s", ctypes.c_double), ("lat_p99_s", ctypes.c_double),
+                ("lat_p999_s", ctypes.c_double), ("lat_max_s", ctypes.c_double),
+                ("mean_batch_events", ctypes.c_double)]
+
+
 class lf_exec(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int32), ("items_per_grab", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32)]
@@ -75,7 +90,7 @@ class lf_exec(ctypes.Structure):
 
 EXPORTS = ("lf_default_params", "lf_check_batch", "lf_create", "lf_upload_events", "lf_find_tracks",
            "lf_work_counts", "lf_fetch_tracks", "lf_release_batch", "lf_set_exec", "lf_batch_info",
-           "lf_device_bytes_in_use", "lf_destroy", "lf_last_error")
+           "lf_device_bytes_in_use", "lf_serve_run", "lf_destroy", "lf_last_error")
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -101,6 +116,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lf_release_batch.argtypes = [vp, u64]
     lib.lf_set_exec.argtypes = [vp, P(lf_exec)]
     lib.lf_batch_info.argtypes = [vp, u64, P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32), P(sz)]
+    lib.lf_serve_run.argtypes = [vp, P(lf_batch), ctypes.c_uint32, vp, vp, P(lf_serve_config), vp, vp,
+                                 P(lf_serve_stats)]
     lib.lf_device_bytes_in_use.argtypes = [vp]
     lib.lf_device_bytes_in_use.restype = sz
     lib.lf_destroy.argtypes = [vp]
@@ -108,7 +125,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lf_last_error.argtypes = [vp]
     lib.lf_last_error.restype = ctypes.c_char_p
     for name in ("lf_check_batch", "lf_create", "lf_upload_events", "lf_find_tracks", "lf_work_counts",
-                 "lf_fetch_tracks", "lf_release_batch", "lf_set_exec", "lf_batch_info"):
+                 "lf_fetch_tracks", "lf_release_batch", "lf_set_exec", "lf_batch_info", "lf_serve_run"):
         getattr(lib, name).restype = i32
     return lib
 
@@ -270,6 +287,26 @@ def lf_batch_info(ctx, batch_id: int) -> dict:
     return dict(n_events=e.value, n_tracks=t.value, n_hits=h.value, device_bytes=b.value)
 
 
+def lf_serve_run(ctx, pool, req_event, arrival_s, config: dict | None = None):
+    """Serve a request stream (see lf.h).  Returns (digests u64[n], latencies f64[n], stats dict)."""
+    h = _Hold(pool)
+    b = h.struct()
+    req = np.ascontiguousarray(req_event, dtype=np.uint32)
+    arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+    if len(req) != len(arr):
+        raise ValueError("req_event and arrival_s differ in length")
+    cfg = lf_serve_config()
+    for k, v in (config or {}).items():
+        setattr(cfg, k, int(v))
+    dig = np.zeros(len(req), np.uint64)
+    lat = np.zeros(len(req), np.float64)
+    st = lf_serve_stats()
+    _check(lib().lf_serve_run(ctx, ctypes.byref(b), len(req), req.ctypes.data, arr.ctypes.data, ctypes.byref(cfg),
+                              dig.ctypes.data, lat.ctypes.data, ctypes.byref(st)), ctx)
+    stats = {n: getattr(st, n) for n, _ in lf_serve_stats._fields_}
+    return dig, lat, stats
+
+
 def lf_device_bytes_in_use(ctx) -> int:
     return int(lib().lf_device_bytes_in_use(ctx))
 
@@ -281,6 +318,38 @@ def lf_destroy(ctx) -> None:
 def lf_last_error(ctx=None) -> str:
     m = lib().lf_last_error(ctx)
     return m.decode() if m else ""
+
+
+# ------------------------------------------------------------------ digests
+_M64 = (1 << 64) - 1
+
+
+def _mix64(z):
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def result_digests(out: dict, trk_off) -> np.ndarray:
+    """Per-event digest of fetched results, as lf_serve_run defines it in lf.h
+    (host-side, to compare served requests with batched or single runs)."""
+    T = len(out["found"])
+    w = np.zeros((T, 20), np.uint64)
+    w[:, 0] = out["found"].astype(np.uint64) | (out["n_hits"].astype(np.uint64) << np.uint64(8))
+    w[:, 1:13] = out["hit_idx"].astype(np.int32).view(np.uint32).astype(np.uint64)
+    for i, k in enumerate(("a", "b", "c", "y0", "ty", "qop", "Q")):
+        w[:, 13 + i] = out[k].astype(np.float32).view(np.uint32).astype(np.uint64)
+    with np.errstate(over="ignore"):
+        h = np.full(T, 0xCBF29CE484222325, np.uint64)
+        for k in range(20):
+            h = (h ^ w[:, k]) * np.uint64(0x100000001B3)
+        off = np.asarray(trk_off, np.int64)
+        ev = np.repeat(np.arange(len(off) - 1), np.diff(off))
+        idx = (np.arange(T, dtype=np.int64) - off[ev]).astype(np.uint64)
+        m = _mix64(h ^ (idx * np.uint64(0x9E3779B97F4A7C15)))
+        d = np.zeros(len(off) - 1, np.uint64)
+        np.add.at(d, ev, m)
+    return d
 
 
 # ------------------------------------------------------------------ convenience

@@ -72,3 +72,9 @@ def oracle_on_events(ev, events, params=None):
     for k in full:
         full[k][rows] = o[k]
     return full, rows
+
+
+# serving digests: the definition lives with the binding (it is part of lf.h)
+def event_digests(out, trk_off):
+    from paper_2402_14670_amd.lf import result_digests
+    return result_digests(out, trk_off)

@@ -1,0 +1,78 @@
+"""Serving loop on the GPU: continuous batching of an open-loop request
+stream.  Every request's result must equal the oracle's result for that event
+processed alone (compared through the per-event digest), whatever batch it
+rode in, under backpressure and in any slot/batch configuration."""
+import numpy as np
+import pytest
+
+import lfgen
+import oracle
+from parity import W, event_digests, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pool():
+    nom = lfgen.generate("nominal", n_events=40)
+    une = lfgen.generate("uneven", n_events=40)
+    z = np.zeros(0, np.float32)
+    empty = lfgen.Events(**{**lfgen.select_events(une, [0]).__dict__, "trk_off": np.zeros(2, np.uint32),
+                            "trk_x": z, "trk_y": z, "trk_tx": z, "trk_ty": z, "trk_qop": z,
+                            "trk_pid": np.zeros(0, np.int32)})
+    ev = lfgen.concat([nom, empty, une])
+    ref = oracle.run(ev, W)
+    return ev, event_digests(ref, ev.trk_off)
+
+
+def _stream(n_pool, n, rate, seed=40):
+    rng = np.random.default_rng(seed)
+    req = rng.integers(0, n_pool, size=n).astype(np.uint32)
+    arr = np.cumsum(rng.exponential(1.0 / rate, size=n)) if rate else np.zeros(n)
+    return req, arr
+
+
+@pytest.mark.parametrize("cfg,rate", [
+    ({}, 20000.0),
+    ({}, None),
+    ({"n_slots": 1, "max_batch_events": 1}, 5000.0),
+    ({"n_slots": 2, "max_batch_events": 7, "n_pack_threads": 3}, None),
+    ({"min_batch_events": 64, "max_wait_us": 2000}, 50000.0),
+], ids=["poisson", "saturated", "one-by-one", "small-batches", "wait-to-fill"])
+def test_results_same_alone_and_in_the_mix(pool, cfg, rate):
+    from paper_2402_14670_amd import lf
+    ev, ref = pool
+    req, arr = _stream(ev.n_events, 3000, rate)
+    ctx = lf.lf_create(W)
+    try:
+        say(f"[gpu] serving cfg={cfg} rate={rate} requests={len(req)} pool={ev.n_events}")
+        dig, lat, st = lf.lf_serve_run(ctx, ev, req, arr, cfg)
+    finally:
+        lf.lf_destroy(ctx)
+    say(f"    {st}")
+    bad = np.nonzero(dig != ref[req])[0]
+    assert len(bad) == 0, f"{len(bad)} requests differ from the oracle, first {bad[:5]}"
+    assert np.all(lat > 0) and st["n_requests"] == len(req)
+    if cfg.get("max_batch_events") == 1:
+        assert st["n_batches"] == len(req)
+
+
+def test_backpressure_under_small_budget(pool):
+    from paper_2402_14670_amd import lf
+    ev, ref = pool
+    req, arr = _stream(ev.n_events, 2000, None)
+    # room for only a few events at a time
+    per_event = 12 * ev.n_hits / ev.n_events + 120 * ev.n_tracks / ev.n_events
+    budget = int(40 * per_event) + (1 << 20)
+    ctx = lf.lf_create(W)
+    try:
+        say(f"[gpu] serving with a {budget} byte budget")
+        dig, lat, st = lf.lf_serve_run(ctx, ev, req, arr, {"device_budget_bytes": budget})
+        assert np.array_equal(dig, ref[req])
+        assert st["max_device_bytes"] <= budget
+        assert st["max_queue"] > 100 and st["n_batches"] > 20
+        with pytest.raises(lf.LFError) as e:
+            lf.lf_serve_run(ctx, ev, req[:10], arr[:10], {"device_budget_bytes": 4096})
+        assert e.value.code == lf.LF_ERR_TOO_LARGE
+    finally:
+        lf.lf_destroy(ctx)
