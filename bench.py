@@ -55,7 +55,12 @@ BYTES_PER_TRACK_OUT = 78
 # (per launch, scaled by the counters' reading of a known-size copy), valid
 # only for the kernel source it was measured on.
 TRAFFIC = {"kernel_sha256": None, "bytes_per_launch": None}
-WORKLOAD = "nominal"
+WORKLOADS = {
+    "nominal": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",
+    "uneven": "uneven: 20000 events, Poisson(7.6) x 50 particles, 0-13k hits and 0-600 tracks/event",
+    "stress": "stress: 5000 events x 486 input tracks (30% fake), ~41.5k hits/event, p 1.5-10 GeV",
+    "single": "single: 1 event, 40 particles, p 5-50 GeV",
+}
 KERNEL = "k_grid"   # the batched mode's kernel (one wavefront per input track)
 KERNEL_SRC = os.path.join(ROOT, "paper_2402_14670_amd", "csrc", "lf_kernels.hip")
 
@@ -68,7 +73,9 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle baseline sample (0 disables it)")
-    ap.add_argument("--events", type=int, default=1000)
+    ap.add_argument("--workload", default="nominal", choices=sorted(WORKLOADS))
+    ap.add_argument("--events", type=int, default=0, help="events of the workload (0: its full size)")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--modes", default="batched,persistent,plain",
                     help="comma-separated subset of batched,persistent,plain to time (batched is always timed)")
     ap.add_argument("--serve-requests", type=int, default=200000,
@@ -110,7 +117,7 @@ def serving(lf, ctx, ev, batched_out, n_requests, seed=40):
     ref = lf.result_digests(batched_out, ev.trk_off)
     rng = np.random.default_rng(seed)
     req = rng.integers(0, ev.n_events, size=n_requests).astype(np.uint32)
-    cfg = {"max_batch_events": 1024, "n_slots": 4, "n_pack_threads": 8, "device_budget_bytes": 8 << 30}
+    cfg = {"max_batch_events": 256, "n_slots": 4, "n_pack_threads": 8, "device_budget_bytes": 8 << 30}
     dig, lat, st = lf.lf_serve_run(ctx, ev, req, np.zeros(n_requests), cfg)
     ok = bool(np.array_equal(dig, ref[req]))
     sat = st["events_per_s"]
@@ -137,6 +144,7 @@ def serving(lf, ctx, ev, batched_out, n_requests, seed=40):
 def cpu_baseline(ev, world, min_seconds):
     """The oracle, as it stands, on the host: repeated passes over a sample
     of the same workload until min_seconds of CPU time have elapsed."""
+    import lfgen
     import oracle
     oracle.build(force=False)
     n_sample = min(ev.n_events, 250)
@@ -151,7 +159,7 @@ def cpu_baseline(ev, world, min_seconds):
         if el >= min_seconds:
             break
     return dict(value=done / el, unit="events/s", cores=1, kind="oracle",
-                sample=f"first {n_sample} events of the nominal batch, {done} events processed "
+                sample=f"first {n_sample} events of the batch, {done} events processed "
                        f"single-threaded in {el:.1f} s")
 
 
@@ -171,8 +179,10 @@ def main():
     # an explicit stream: the library launches on it and the timing events are recorded on it
     stream = torch.cuda.Stream()
     world = lfgen.world()
-    ev = lfgen.generate(WORKLOAD, n_events=args.events)
-    print(f"bench: {ev.n_events} events, {ev.n_tracks} tracks, {ev.n_hits} hits", file=sys.stderr, flush=True)
+    gen = {"n_events": args.events} if args.events else {}
+    ev = lfgen.generate(args.workload, **gen)
+    print(f"bench: {args.workload}: {ev.n_events} events, {ev.n_tracks} tracks, {ev.n_hits} hits", file=sys.stderr,
+          flush=True)
 
     if args.calib_copy_mb:
         n = args.calib_copy_mb * (1 << 20) // 4
@@ -185,16 +195,46 @@ def main():
 
     ctx = lf.lf_create(world)
     bid = lf.lf_upload_events(ctx, ev, stream.cuda_stream)
+    tuned = None
+    if not args.no_autotune:
+        from paper_2402_14670_amd import autotune
+        tuned = autotune.autotune(ctx, bid, stream, steps=3)
+        print(f"bench: autotuned {tuned['per_mode']}", file=sys.stderr, flush=True)
     res = {}
     wanted = set(args.modes.split(",")) | {"batched"}
     for mode, steps, warm in (("batched", args.steps, args.warmup), ("persistent", args.steps, args.warmup),
                               ("plain", args.plain_steps, 1)):
         if mode not in wanted:
             continue
+        if tuned and mode in tuned["per_mode"]:
+            c = tuned["per_mode"][mode]
+            lf.lf_set_exec(ctx, waves_per_block=c["waves_per_block"])
+            lf.lf_set_exec(ctx, items_per_grab=c["items_per_grab"], blocks_per_cu=c["blocks_per_cu"])
         ms, wall = time_mode(lf, ctx, bid, mode, steps, warm, stream)
         res[mode] = ms
-        print(f"bench: {mode:8s} {ms:8.3f} ms/step  {ev.n_events / ms * 1e3:12.0f} events/s", file=sys.stderr,
+        print(f"bench: {mode:10s} {ms:8.3f} ms/step  {ev.n_events / ms * 1e3:12.0f} events/s", file=sys.stderr,
               flush=True)
+        if mode == "plain":
+            # the same per-event launch sequence, captured once in a HIP graph
+            g = lf.lf_graph_create(ctx, [bid], "plain")
+            try:
+                for _ in range(1):
+                    lf.lf_graph_launch(ctx, g, stream.cuda_stream)
+                torch.cuda.synchronize()
+                st_, en_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                st_.record(stream)
+                for _ in range(steps):
+                    lf.lf_graph_launch(ctx, g, stream.cuda_stream)
+                en_.record(stream)
+                torch.cuda.synchronize()
+                res["plain_graph"] = st_.elapsed_time(en_) / steps
+            finally:
+                lf.lf_graph_destroy(g)
+            print(f"bench: {'plain_graph':10s} {res['plain_graph']:8.3f} ms/step  "
+                  f"{ev.n_events / res['plain_graph'] * 1e3:12.0f} events/s", file=sys.stderr, flush=True)
+    if tuned:
+        c = tuned["per_mode"]["batched"]
+        lf.lf_set_exec(ctx, waves_per_block=c["waves_per_block"])
     work = lf.lf_work_counts(ctx, bid, stream.cuda_stream)
     out = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
     serve = serving(lf, ctx, ev, out, args.serve_requests) if args.serve_requests else None
@@ -221,12 +261,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",
+        "config": {"workload": WORKLOADS[args.workload],
                    "events": ev.n_events, "input_tracks": ev.n_tracks, "hits": ev.n_hits,
                    "n_hits_window": 32, "n_triplets": 12},
         "modes": {m: {"ms_per_step": round(v, 4), "events_per_s": round(ev.n_events / v * 1e3, 1),
                       "input_tracks_per_s": round(ev.n_tracks / v * 1e3, 1)} for m, v in res.items()},
         "batched_over_plain": round(res["plain"] / ms, 2) if "plain" in res else None,
+        "autotune": ({m: {k: v for k, v in c.items() if k != "mode"} for m, c in tuned["per_mode"].items()}
+                     if tuned else None),
         "found_tracks": int(out["found"].sum()),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": traffic,

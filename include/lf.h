@@ -204,6 +204,16 @@ int lf_work_counts(lf_ctx *ctx, uint64_t batch_id, void *hip_stream, int64_t *co
 int lf_fetch_tracks(lf_ctx *ctx, uint64_t batch_id, lf_tracks_out *out, size_t cap_tracks,
                     void *hip_stream);
 
+/* Like lf_fetch_tracks, but the batch stays resident (results can be read
+ * again after further lf_find_tracks calls or graph replays). */
+int lf_copy_tracks(lf_ctx *ctx, uint64_t batch_id, lf_tracks_out *out, size_t cap_tracks, void *hip_stream);
+
+/* Overwrites a resident batch's result slots with a poison pattern (found =
+ * 0xFF, hit indices -2, parameters NaN) on hip_stream, with a kernel (no
+ * memset), so that a later run that failed to write a slot is visible.
+ * Errors: LF_ERR_STATE, LF_ERR_DEVICE. */
+int lf_poison_tracks(lf_ctx *ctx, uint64_t batch_id, void *hip_stream);
+
 /* Frees a resident batch without fetching it.  Errors: LF_ERR_STATE. */
 int lf_release_batch(lf_ctx *ctx, uint64_t batch_id);
 
@@ -218,6 +228,20 @@ int lf_batch_info(lf_ctx *ctx, uint64_t batch_id, uint32_t *n_events, uint32_t *
 
 /* Device bytes held by resident batches. */
 size_t lf_device_bytes_in_use(const lf_ctx *ctx);
+
+/* Captured launch sequences (HIP graphs).  A graph records the hot path
+ * of n resident batches in the given mode, in order, and replays it with
+ * one launch call.  The batches must stay resident (not fetched or
+ * released) while the graph is used.  No memset node is recorded: the
+ * persistent mode's queue words reset themselves. */
+typedef struct lf_graph lf_graph;
+
+/* Errors: LF_ERR_STATE (unknown batch), LF_ERR_INVALID, LF_ERR_DEVICE. */
+int lf_graph_create(lf_ctx *ctx, const uint64_t *batch_ids, uint32_t n_batches, int mode, lf_graph **out);
+/* Replays the graph on hip_stream (asynchronous).  Errors: LF_ERR_INVALID, LF_ERR_DEVICE. */
+int lf_graph_launch(lf_ctx *ctx, lf_graph *graph, void *hip_stream);
+/* Frees a graph (NULL is ignored). */
+void lf_graph_destroy(lf_graph *graph);
 
 /* Serving loop (continuous batching).  Configuration; zero fields take the
  * defaults in brackets. */

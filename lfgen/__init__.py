@@ -152,7 +152,7 @@ def build(force: bool = False) -> str:
     """Compile the generator into a shared library next to its source."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.run(["gcc", "-O2", "-std=gnu11", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"],
+        subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"],
                        check=True)
         os.replace(tmp, _LIB)
     return _LIB

@@ -329,21 +329,66 @@ void lfgen_free(lfgen_out *o) {
     free(o);
 }
 
-/* Generates the events; returns NULL on bad configuration or out of memory. */
+static lfgen_out *new_out(uint32_t n_events) {
+    lfgen_out *o = (lfgen_out *)calloc(1, sizeof(lfgen_out));
+    if (!o) return NULL;
+    o->n_events = n_events;
+    o->hit_off = (uint32_t *)calloc((size_t)n_events * 24 + 1, sizeof(uint32_t));
+    o->trk_off = (uint32_t *)calloc((size_t)n_events + 1, sizeof(uint32_t));
+    o->par_off = (uint32_t *)calloc((size_t)n_events + 1, sizeof(uint32_t));
+    if (!o->hit_off || !o->trk_off || !o->par_off) { lfgen_free(o); return NULL; }
+    return o;
+}
+
+/* Generates the events (in parallel: every event has its own random
+ * stream, so the result does not depend on the thread count); returns NULL
+ * on bad configuration or out of memory. */
 lfgen_out *lfgen_run(const lfgen_config *c) {
     if (!c || c->n_events < 0 || c->first_event < 0 || c->p_min <= 0.0 || c->p_max < c->p_min)
         return NULL;
-    lfgen_out *o = (lfgen_out *)calloc(1, sizeof(lfgen_out));
-    if (!o) return NULL;
-    o->n_events = (uint32_t)c->n_events;
-    o->hit_off = (uint32_t *)calloc((size_t)c->n_events * 24 + 1, sizeof(uint32_t));
-    o->trk_off = (uint32_t *)calloc((size_t)c->n_events + 1, sizeof(uint32_t));
-    o->par_off = (uint32_t *)calloc((size_t)c->n_events + 1, sizeof(uint32_t));
-    if (!o->hit_off || !o->trk_off || !o->par_off) { lfgen_free(o); return NULL; }
-    for (int e = 0; e < c->n_events; ++e) {
-        if (gen_event(c, (uint32_t)(c->first_event + e), o, (uint32_t)e)) { lfgen_free(o); return NULL; }
-        if (o->n_hits > 0xFFFFFFF0ull) { lfgen_free(o); return NULL; }
+    const int E = c->n_events;
+    lfgen_out **parts = (lfgen_out **)calloc((size_t)E + 1, sizeof(lfgen_out *));
+    if (!parts) return NULL;
+    int failed = 0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(| : failed)
+    for (int e = 0; e < E; ++e) {
+        lfgen_out *p = new_out(1);
+        if (!p || gen_event(c, (uint32_t)(c->first_event + e), p, 0)) failed |= 1;
+        parts[e] = p;
     }
+    lfgen_out *o = failed ? NULL : new_out((uint32_t)E);
+    size_t H = 0, T = 0, Pn = 0;
+    if (o) {
+        for (int e = 0; e < E; ++e) { H += parts[e]->n_hits; T += parts[e]->n_trk; Pn += parts[e]->n_par; }
+        if (H > 0xFFFFFFF0ull || reserve_hits(o, H + 1) || reserve_trk(o, T + 1) || reserve_par(o, Pn + 1)) {
+            lfgen_free(o);
+            o = NULL;
+        }
+    }
+    if (o) {
+        size_t h = 0, t = 0, q = 0;
+        for (int e = 0; e < E; ++e) {
+            const lfgen_out *p = parts[e];
+            for (int b = 0; b < 24; ++b) o->hit_off[(size_t)e * 24 + b] = (uint32_t)(h + p->hit_off[b]);
+            o->trk_off[e] = (uint32_t)t;
+            o->par_off[e] = (uint32_t)q;
+            memcpy(o->hx + h, p->hx, p->n_hits * 4); memcpy(o->hz + h, p->hz, p->n_hits * 4);
+            memcpy(o->hdxdy + h, p->hdxdy, p->n_hits * 4); memcpy(o->hpid + h, p->hpid, p->n_hits * 4);
+            memcpy(o->tx_ + t, p->tx_, p->n_trk * 4); memcpy(o->ty_ + t, p->ty_, p->n_trk * 4);
+            memcpy(o->ttx + t, p->ttx, p->n_trk * 4); memcpy(o->tty + t, p->tty, p->n_trk * 4);
+            memcpy(o->tqop + t, p->tqop, p->n_trk * 4); memcpy(o->tpid + t, p->tpid, p->n_trk * 4);
+            memcpy(o->pp + q, p->pp, p->n_par * 4); memcpy(o->pq + q, p->pq, p->n_par * 4);
+            memcpy(o->ptx + q, p->ptx, p->n_par * 4); memcpy(o->pty + q, p->pty, p->n_par * 4);
+            memcpy(o->pmask + q, p->pmask, p->n_par * 2); memcpy(o->phas + q, p->phas, p->n_par);
+            h += p->n_hits; t += p->n_trk; q += p->n_par;
+        }
+        o->hit_off[(size_t)E * 24] = (uint32_t)h;
+        o->trk_off[E] = (uint32_t)t;
+        o->par_off[E] = (uint32_t)q;
+        o->n_hits = h; o->n_trk = t; o->n_par = q;
+    }
+    for (int e = 0; e < E; ++e) lfgen_free(parts[e]);
+    free(parts);
     return o;
 }
 

@@ -346,6 +346,62 @@ int lf_find_tracks(lf_ctx *c, uint64_t batch_id, int mode, void *hip_stream) {
     return LF_OK;
 }
 
+struct lf_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int lf_graph_create(lf_ctx *c, const uint64_t *ids, uint32_t n, int mode, lf_graph **out) {
+    if (!c) return LF_ERR_INVALID;
+    if (!ids || !out || n == 0) return fail(c, LF_ERR_INVALID, "lf_graph_create: no batches");
+    if (mode != LF_MODE_PLAIN && mode != LF_MODE_BATCHED && mode != LF_MODE_PERSISTENT)
+        return fail(c, LF_ERR_INVALID, "lf_graph_create: unknown mode");
+    *out = nullptr;
+    std::vector<Batch *> bs;
+    for (uint32_t i = 0; i < n; ++i) {
+        auto it = c->batches.find(ids[i]);
+        if (it == c->batches.end()) return fail(c, LF_ERR_STATE, "lf_graph_create: unknown batch id");
+        bs.push_back(&it->second);
+    }
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    lf_graph *g = new (std::nothrow) lf_graph();
+    if (!g) { if (cs) (void)hipStreamDestroy(cs); return fail(c, LF_ERR_NOMEM, "lf_graph_create: out of memory"); }
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = hipSuccess;
+        for (Batch *b : bs) {
+            le = lfk::launch_find(b->dev, c->d_params, c->params.n_hits_window, mode, c->exec, b->trk_off.data(), cs);
+            if (le != hipSuccess) break;
+        }
+        e = hipStreamEndCapture(cs, &g->graph);
+        if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        lf_graph_destroy(g);
+        return hip_fail(c, e, "lf_graph_create");
+    }
+    *out = g;
+    return LF_OK;
+}
+
+int lf_graph_launch(lf_ctx *c, lf_graph *g, void *hip_stream) {
+    if (!c) return LF_ERR_INVALID;
+    if (!g || !g->exec) return fail(c, LF_ERR_INVALID, "lf_graph_launch: NULL graph");
+    const hipError_t e = hipGraphLaunch(g->exec, pick(c, hip_stream));
+    if (e != hipSuccess) return hip_fail(c, e, "lf_graph_launch");
+    return LF_OK;
+}
+
+void lf_graph_destroy(lf_graph *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
 int lf_work_counts(lf_ctx *c, uint64_t batch_id, void *hip_stream, int64_t *counts, size_t n_counts) {
     if (!c) return LF_ERR_INVALID;
     auto it = c->batches.find(batch_id);
@@ -363,7 +419,8 @@ int lf_work_counts(lf_ctx *c, uint64_t batch_id, void *hip_stream, int64_t *coun
     return LF_OK;
 }
 
-int lf_fetch_tracks(lf_ctx *c, uint64_t batch_id, lf_tracks_out *out, size_t cap_tracks, void *hip_stream) {
+namespace {
+int copy_tracks(lf_ctx *c, uint64_t batch_id, lf_tracks_out *out, size_t cap_tracks, void *hip_stream, bool release) {
     if (!c) return LF_ERR_INVALID;
     auto it = c->batches.find(batch_id);
     if (it == c->batches.end()) return fail(c, LF_ERR_STATE, "lf_fetch_tracks: unknown batch id");
@@ -388,9 +445,29 @@ int lf_fetch_tracks(lf_ctx *c, uint64_t batch_id, lf_tracks_out *out, size_t cap
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "lf_fetch_tracks");
-    (void)hipFree(bt.dmem);
-    c->used -= bt.bytes;
-    c->batches.erase(it);
+    if (release) {
+        (void)hipFree(bt.dmem);
+        c->used -= bt.bytes;
+        c->batches.erase(it);
+    }
+    return LF_OK;
+}
+}  // namespace
+
+int lf_fetch_tracks(lf_ctx *c, uint64_t batch_id, lf_tracks_out *out, size_t cap_tracks, void *hip_stream) {
+    return copy_tracks(c, batch_id, out, cap_tracks, hip_stream, true);
+}
+
+int lf_copy_tracks(lf_ctx *c, uint64_t batch_id, lf_tracks_out *out, size_t cap_tracks, void *hip_stream) {
+    return copy_tracks(c, batch_id, out, cap_tracks, hip_stream, false);
+}
+
+int lf_poison_tracks(lf_ctx *c, uint64_t batch_id, void *hip_stream) {
+    if (!c) return LF_ERR_INVALID;
+    auto it = c->batches.find(batch_id);
+    if (it == c->batches.end()) return fail(c, LF_ERR_STATE, "lf_poison_tracks: unknown batch id");
+    const hipError_t e = lfk::launch_poison(it->second.dev, pick(c, hip_stream));
+    if (e != hipSuccess) return hip_fail(c, e, "lf_poison_tracks");
     return LF_OK;
 }
 

@@ -56,6 +56,8 @@ hipError_t launch_find(const DevBatch &b, const KParams *P, int n_hits_window, i
 // Counting launch: one wavefront per track, adds the work counters of every
 // track into b.stats (which must be zeroed first).
 hipError_t launch_count(const DevBatch &b, const KParams *P, int n_hits_window, hipStream_t s);
+// Fills the result slots with a poison pattern (kernel, no memset).
+hipError_t launch_poison(const DevBatch &b, hipStream_t s);
 // Resident blocks per compute unit of the persistent kernel (0 on error).
 int persistent_blocks_per_cu(int n_hits_window, int waves_per_block);
 

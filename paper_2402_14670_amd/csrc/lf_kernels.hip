@@ -802,7 +802,23 @@ __global__ __launch_bounds__(WAVE) void k_digest(DevBatch B, const uint32_t *__r
     if (threadIdx.x == 0) out[e] = acc;
 }
 
+__global__ __launch_bounds__(256) void k_poison(DevBatch B) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B.n_tracks) return;
+    B.found[t] = 0xFF;
+    B.nhits[t] = 0xFF;
+    for (int l = 0; l < NL; ++l) B.hit_idx[(size_t)t * NL + l] = -2;
+    const float nan = __uint_as_float(0x7FC00000u);
+    B.a[t] = nan; B.b[t] = nan; B.c[t] = nan; B.y0[t] = nan; B.ty[t] = nan; B.qop[t] = nan; B.Q[t] = nan;
+}
+
 }  // namespace
+
+hipError_t launch_poison(const DevBatch &b, hipStream_t s) {
+    if (b.n_tracks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_poison, dim3((b.n_tracks + 255) / 256), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
 
 hipError_t launch_digest(const DevBatch &b, const uint32_t *trk_off, uint32_t n_events, unsigned long long *out,
                          hipStream_t s) {

@@ -89,8 +89,9 @@ class lf_exec(ctypes.Structure):
 
 
 EXPORTS = ("lf_default_params", "lf_check_batch", "lf_create", "lf_upload_events", "lf_find_tracks",
-           "lf_work_counts", "lf_fetch_tracks", "lf_release_batch", "lf_set_exec", "lf_batch_info",
-           "lf_device_bytes_in_use", "lf_serve_run", "lf_destroy", "lf_last_error")
+           "lf_work_counts", "lf_fetch_tracks", "lf_copy_tracks", "lf_poison_tracks", "lf_release_batch", "lf_set_exec", "lf_batch_info",
+           "lf_device_bytes_in_use", "lf_serve_run", "lf_graph_create", "lf_graph_launch", "lf_graph_destroy",
+           "lf_destroy", "lf_last_error")
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -113,11 +114,17 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lf_find_tracks.argtypes = [vp, u64, i32, vp]
     lib.lf_fetch_tracks.argtypes = [vp, u64, P(lf_tracks_out), sz, vp]
     lib.lf_work_counts.argtypes = [vp, u64, vp, P(ctypes.c_int64), sz]
+    lib.lf_copy_tracks.argtypes = [vp, u64, P(lf_tracks_out), sz, vp]
+    lib.lf_poison_tracks.argtypes = [vp, u64, vp]
     lib.lf_release_batch.argtypes = [vp, u64]
     lib.lf_set_exec.argtypes = [vp, P(lf_exec)]
     lib.lf_batch_info.argtypes = [vp, u64, P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32), P(sz)]
     lib.lf_serve_run.argtypes = [vp, P(lf_batch), ctypes.c_uint32, vp, vp, P(lf_serve_config), vp, vp,
                                  P(lf_serve_stats)]
+    lib.lf_graph_create.argtypes = [vp, vp, ctypes.c_uint32, i32, P(vp)]
+    lib.lf_graph_launch.argtypes = [vp, vp, vp]
+    lib.lf_graph_destroy.argtypes = [vp]
+    lib.lf_graph_destroy.restype = None
     lib.lf_device_bytes_in_use.argtypes = [vp]
     lib.lf_device_bytes_in_use.restype = sz
     lib.lf_destroy.argtypes = [vp]
@@ -125,7 +132,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lf_last_error.argtypes = [vp]
     lib.lf_last_error.restype = ctypes.c_char_p
     for name in ("lf_check_batch", "lf_create", "lf_upload_events", "lf_find_tracks", "lf_work_counts",
-                 "lf_fetch_tracks", "lf_release_batch", "lf_set_exec", "lf_batch_info", "lf_serve_run"):
+                 "lf_fetch_tracks", "lf_release_batch", "lf_set_exec", "lf_batch_info", "lf_serve_run",
+                 "lf_graph_create", "lf_graph_launch", "lf_copy_tracks", "lf_poison_tracks"):
         getattr(lib, name).restype = i32
     return lib
 
@@ -258,7 +266,8 @@ def lf_work_counts(ctx, batch_id: int, stream=None) -> dict:
     return {k: int(arr[i]) for i, k in enumerate(WORK_COUNTERS)}
 
 
-def lf_fetch_tracks(ctx, batch_id: int, n_tracks: int | None = None, stream=None) -> dict:
+def lf_fetch_tracks(ctx, batch_id: int, n_tracks: int | None = None, stream=None, release: bool = True) -> dict:
+    """Results of a batch; the batch is freed unless release is False (lf_copy_tracks)."""
     if n_tracks is None:
         n_tracks = lf_batch_info(ctx, batch_id)["n_tracks"]
     T = int(n_tracks)
@@ -267,8 +276,17 @@ def lf_fetch_tracks(ctx, batch_id: int, n_tracks: int | None = None, stream=None
         out[k] = np.zeros(T, np.float32)
     o = lf_tracks_out(*[out[k].ctypes.data for k in ("found", "n_hits", "hit_idx", "a", "b", "c", "y0", "ty",
                                                       "qop", "Q")])
-    _check(lib().lf_fetch_tracks(ctx, ctypes.c_uint64(batch_id), ctypes.byref(o), T, _stream(stream)), ctx)
+    fn = lib().lf_fetch_tracks if release else lib().lf_copy_tracks
+    _check(fn(ctx, ctypes.c_uint64(batch_id), ctypes.byref(o), T, _stream(stream)), ctx)
     return out
+
+
+def lf_copy_tracks(ctx, batch_id: int, n_tracks: int | None = None, stream=None) -> dict:
+    return lf_fetch_tracks(ctx, batch_id, n_tracks, stream, release=False)
+
+
+def lf_poison_tracks(ctx, batch_id: int, stream=None) -> None:
+    _check(lib().lf_poison_tracks(ctx, ctypes.c_uint64(batch_id), _stream(stream)), ctx)
 
 
 def lf_release_batch(ctx, batch_id: int) -> None:
@@ -305,6 +323,24 @@ def lf_serve_run(ctx, pool, req_event, arrival_s, config: dict | None = None):
                               dig.ctypes.data, lat.ctypes.data, ctypes.byref(st)), ctx)
     stats = {n: getattr(st, n) for n, _ in lf_serve_stats._fields_}
     return dig, lat, stats
+
+
+def lf_graph_create(ctx, batch_ids, mode=LF_MODE_BATCHED) -> ctypes.c_void_p:
+    """Capture the hot path of resident batches (in order) into a HIP graph."""
+    if isinstance(mode, str):
+        mode = MODES[mode]
+    ids = np.ascontiguousarray(batch_ids, dtype=np.uint64)
+    g = ctypes.c_void_p()
+    _check(lib().lf_graph_create(ctx, ids.ctypes.data, len(ids), int(mode), ctypes.byref(g)), ctx)
+    return g
+
+
+def lf_graph_launch(ctx, graph, stream=None) -> None:
+    _check(lib().lf_graph_launch(ctx, graph, _stream(stream)), ctx)
+
+
+def lf_graph_destroy(graph) -> None:
+    lib().lf_graph_destroy(graph)
 
 
 def lf_device_bytes_in_use(ctx) -> int:

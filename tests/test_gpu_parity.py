@@ -218,3 +218,53 @@ def test_error_codes():
     with pytest.raises(lf.LFError) as e:
         lf.lf_create(W, {"n_triplets": 33})
     assert e.value.code == lf.LF_ERR_INVALID
+
+
+@pytest.mark.parametrize("mode", ["batched", "persistent", "plain"])
+def test_graph_replays(mode):
+    """A captured sequence of three batches replays identically: each replay
+    follows a poison of every result slot and eager work on another batch."""
+    from paper_2402_14670_amd import lf
+    parts = [lfgen.generate("uneven", n_events=30, first_event=30 * i) for i in range(3)]
+    other = lfgen.generate("nominal", n_events=5)
+    refs = [oracle.run(p, W) for p in parts]
+    ctx = lf.lf_create(W)
+    try:
+        ids = [lf.lf_upload_events(ctx, p) for p in parts]
+        oid = lf.lf_upload_events(ctx, other)
+        say(f"[gpu] graph capture mode={mode} of {len(ids)} uneven batches")
+        g = lf.lf_graph_create(ctx, ids, mode)
+        try:
+            for rep in range(3):
+                for i in ids:
+                    lf.lf_poison_tracks(ctx, i)
+                lf.lf_graph_launch(ctx, g)
+                lf.lf_find_tracks(ctx, oid, "batched")          # eager work between replays
+                for i, p, r in zip(ids, parts, refs):
+                    compare(r, lf.lf_copy_tracks(ctx, i, p.n_tracks), label=f"graph/{mode}/replay{rep}")
+        finally:
+            lf.lf_graph_destroy(g)
+    finally:
+        lf.lf_destroy(ctx)
+
+
+def test_autotuner_keeps_results():
+    import torch
+    from paper_2402_14670_amd import autotune, lf
+    ev = lfgen.generate("uneven", n_events=200)
+    ref = oracle.run(ev, W, events=(0, 40))
+    ctx = lf.lf_create(W)
+    try:
+        bid = lf.lf_upload_events(ctx, ev)
+        s = torch.cuda.Stream()
+        say("[gpu] autotune on uneven[200]")
+        res = autotune.autotune(ctx, bid, s, steps=2)
+        say(f"    best {res['best']}")
+        assert len(res["table"]) == 3 + 3 * 5 * 4
+        lf.lf_poison_tracks(ctx, bid)
+        lf.lf_find_tracks(ctx, bid, res["best"]["mode"])
+        got = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks)
+    finally:
+        lf.lf_destroy(ctx)
+    rows = np.arange(int(ev.trk_off[40]))
+    compare(ref, got, rows=rows, label="autotuned")
