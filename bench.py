@@ -272,7 +272,11 @@ def main():
         "found_tracks": int(out["found"].sum()),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": traffic,
-                     "kernel": KERNEL, "ops_per_launch": ops, "work_units": work,
+                     "kernel": KERNEL, "ops_per_launch": ops,
+                     "work_units": {k: v for k, v in work.items() if not k.startswith("cy_")},
+                     "phase_cycle_share": {k[3:]: round(v / max(1, sum(x for n, x in work.items()
+                                                                          if n.startswith("cy_"))), 4)
+                                           for k, v in work.items() if k.startswith("cy_")},
                      "hbm": {"algorithmic_bytes": nbytes, "achieved_GBs": round(nbytes / (ms * 1e-3) / 1e9, 1),
                              "peak_GBs": HBM_PEAK_GBS,
                              "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}},

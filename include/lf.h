@@ -75,7 +75,10 @@ enum {
     LF_WC_ACCEPTED = 8,      /* candidates with Q < T_Q */
     LF_WC_STAGED_HITS = 9,   /* window hits staged */
     LF_WC_FOUND = 10,        /* tracks found */
-    LF_WC_N = 11
+    /* shader-clock cycles per wavefront spent in each phase, summed over tracks */
+    LF_WC_CY_WINDOWS = 11, LF_WC_CY_STAGE = 12, LF_WC_CY_DOUBLETS = 13, LF_WC_CY_MODEL = 14,
+    LF_WC_CY_EXTEND = 15, LF_WC_CY_FIT = 16, LF_WC_CY_SELECT = 17,
+    LF_WC_N = 18
 };
 
 /* Detector and field description.  Layers 0..11 are three stations of

@@ -145,7 +145,7 @@ Layout layout(uint32_t E, uint32_t H, uint32_t T) {
     L.a = put((size_t)T * 4); L.b = put((size_t)T * 4); L.c = put((size_t)T * 4);
     L.y0 = put((size_t)T * 4); L.ty_o = put((size_t)T * 4); L.qop = put((size_t)T * 4); L.Q = put((size_t)T * 4);
     L.counter = put(1024);
-    L.stats = put(16 * 8);
+    L.stats = put(32 * 8);
     L.total = o;
     return L;
 }
@@ -409,13 +409,13 @@ int lf_work_counts(lf_ctx *c, uint64_t batch_id, void *hip_stream, int64_t *coun
     if (!counts) return fail(c, LF_ERR_INVALID, "lf_work_counts: NULL counts");
     Batch &bt = it->second;
     hipStream_t s = pick(c, hip_stream);
-    unsigned long long host[16] = {0};
+    unsigned long long host[32] = {0};
     hipError_t e = hipMemsetAsync(bt.dev.stats, 0, sizeof(host), s);
     if (e == hipSuccess) e = lfk::launch_count(bt.dev, c->d_params, c->params.n_hits_window, s);
     if (e == hipSuccess) e = hipMemcpyAsync(host, bt.dev.stats, sizeof(host), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "lf_work_counts");
-    for (size_t k = 0; k < n_counts; ++k) counts[k] = k < 16 ? (int64_t)host[k] : 0;
+    for (size_t k = 0; k < n_counts; ++k) counts[k] = k < 32 ? (int64_t)host[k] : 0;
     return LF_OK;
 }
 

@@ -34,7 +34,7 @@ struct DevBatch {
     int32_t *hit_idx;          // [12*T]
     float *a, *b, *c, *y0, *ty, *qop, *Q;  // [T]
     uint32_t *counter;         // [256] per-XCD queue heads and exited-wave count (batched mode), zero between launches
-    unsigned long long *stats; // [16] work counters (counting launch only)
+    unsigned long long *stats; // [32] work counters (counting launch only)
     uint32_t n_events, n_tracks;
 };
 

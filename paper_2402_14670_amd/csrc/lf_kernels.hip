@@ -136,7 +136,9 @@ struct WaveLds {
 
 // Work counters of one track (only in the counting build, CNT = true).
 enum { C_TRACKS, C_PAIRS_ALL, C_ITEMS, C_PAIRS_TESTED, C_DOUBLETS, C_TRIPLETS, C_KEPT, C_FITTED,
-       C_ACCEPTED, C_STAGED, C_FOUND, C_N };
+       C_ACCEPTED, C_STAGED, C_FOUND,
+       // shader-clock cycles spent per phase (counting build only)
+       C_CY_WINDOWS, C_CY_STAGE, C_CY_DOUBLETS, C_CY_MODEL, C_CY_EXTEND, C_CY_FIT, C_CY_SELECT, C_N };
 
 template <int NW, bool CNT = false>
 struct Track {
@@ -146,6 +148,16 @@ struct Track {
     int nL;    // kept triplets
     int buf;   // live half of the top-n double buffer
     uint32_t cnt[CNT ? C_N : 1];
+    uint64_t tphase;
+
+    // Adds the shader-clock cycles since the previous mark to counter k.
+    __device__ __forceinline__ void mark(int k) {
+        if constexpr (CNT) {
+            const uint64_t now = __builtin_readcyclecounter();
+            cnt[k] += (uint32_t)(now - tphase);
+            tphase = now;
+        }
+    }
 
     // Merge this pass's accepted triplets (one per lane) into the top-n list.
     __device__ void merge(bool valid, uint64_t key, int h1) {
@@ -217,6 +229,7 @@ struct Track {
         if constexpr (CNT) {
             for (int k = 0; k < C_N; ++k) cnt[k] = 0;
             cnt[C_TRACKS] = 1;
+            tphase = __builtin_readcyclecounter();
         }
         const float x_in = B.tx_[t], y_in = B.ty_[t], tx_in = B.ttx[t], ty_in = B.tty[t];
         const float qop = B.tqop[t];
@@ -285,6 +298,7 @@ struct Track {
             }
         }
         wave_sync();
+        mark(C_CY_WINDOWS);
 
         // ---- stage window hits into LDS ----
         for (int it = lane; it < NL * NW; it += WAVE) {
@@ -317,6 +331,7 @@ struct Track {
             cnt[C_PAIRS_ALL] = (uint32_t)(L.wlen[0] * L.wlen[8] + L.wlen[3] * L.wlen[11]);
         }
 
+        mark(C_CY_STAGE);
         // ---- doublets of both seed sets, filtered, queued; triplets by passes ----
         nL = 0;
         buf = 0;
@@ -426,6 +441,7 @@ struct Track {
             return;
         }
 
+        mark(C_CY_DOUBLETS);
         // ---- triplet x(z) models ----
         if (lane < nL) {
             const uint32_t lo = (uint32_t)L.tk[buf][lane];
@@ -453,6 +469,7 @@ struct Track {
         }
         wave_sync();
 
+        mark(C_CY_MODEL);
         // ---- extension: lanes = (candidate, missing layer) ----
         const float T_uv0 = P->T_uv_scale * (fabsf(tx_in) + fabsf(ty_in));
         const float T_uv = T_uv0 < P->T_uv_floor ? P->T_uv_floor : T_uv0;
@@ -483,6 +500,7 @@ struct Track {
         }
         wave_sync();
 
+        mark(C_CY_EXTEND);
         // ---- fits and quality, one lane per candidate ----
         bool acc = false, fit_lane = false;
         float Qb = 0.0f, fa = 0.0f, fb = 0.0f, fc = 0.0f, fy0 = 0.0f, fty = 0.0f;
@@ -593,6 +611,7 @@ struct Track {
             }
         }
 
+        mark(C_CY_FIT);
         // ---- best candidate: argmin (Q, rank) over the wave ----
         if constexpr (CNT) {
             cnt[C_FITTED] = (uint32_t)__popcll(__ballot(fit_lane));
@@ -628,6 +647,7 @@ struct Track {
             const int h = L.ch[br][lane];
             B.hit_idx[o12 + lane] = h >= 0 ? L.wfirst[lane] + h : -1;
         }
+        mark(C_CY_SELECT);
     }
 
     __device__ void write_none(uint32_t t, size_t o12) {
@@ -648,7 +668,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_plain(DevBatch B, const KParams 
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const uint32_t t = B.trk_off[ev] + blockIdx.x * WPB + w;
     if (t >= B.trk_off[ev + 1]) return;
-    Track<NW> tr{B, P, lds[w], 0, 0, {}};
+    Track<NW> tr{B, P, lds[w], 0, 0, {}, 0};
     tr.run(t, ev);
 }
 
@@ -665,7 +685,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_grid(DevBatch B, const KParams *
     const uint32_t lb = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
     const uint32_t t = lb * WPB + w;
     if (t >= B.n_tracks) return;
-    Track<NW, CNT> tr{B, P, lds[w], 0, 0, {}};
+    Track<NW, CNT> tr{B, P, lds[w], 0, 0, {}, 0};
     tr.run(t, B.trk_ev[t]);
     if constexpr (CNT) {
         if (lane_id() == 0)
@@ -709,7 +729,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_persistent(DevBatch B, const KPa
             // keep per-track loads inside the loop: hoisting them across tracks
             // costs ~30 VGPRs of loop-carried state and two waves per SIMD
             asm volatile("" ::: "memory");
-            Track<NW> tr{B, P, lds[w], 0, 0, {}};
+            Track<NW> tr{B, P, lds[w], 0, 0, {}, 0};
             tr.run(t, B.trk_ev[t]);
         }
     }

@@ -29,7 +29,8 @@ LF_MODE_BATCHED = 1
 LF_MODE_PERSISTENT = 2
 MODES = {"plain": LF_MODE_PLAIN, "batched": LF_MODE_BATCHED, "persistent": LF_MODE_PERSISTENT}
 WORK_COUNTERS = ("tracks", "pairs_all", "seed_items", "pairs_tested", "doublets", "triplets", "kept",
-                 "fitted", "accepted", "staged_hits", "found")
+                 "fitted", "accepted", "staged_hits", "found", "cy_windows", "cy_stage", "cy_doublets", "cy_model",
+                 "cy_extend", "cy_fit", "cy_select")
 
 
 class LFError(RuntimeError):
