@@ -48,6 +48,13 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Lane i's 64-bit value, broadcast (i uniform).
+__device__ __forceinline__ uint64_t bcast64(uint64_t v, int i) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, i);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), i);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ bool is_uv(int l) {
     const int k = l & 3;
     return k == 1 || k == 2;
@@ -117,21 +124,28 @@ __device__ __forceinline__ int closest_scan(Val val, int n, float xe, float &bd)
     return best;
 }
 
+// Index of stereo layer l (l % 4 in {1, 2}) among the six stereo layers.
+__device__ __forceinline__ int uv_index(int l) { return 2 * (l >> 2) + (l & 3) - 1; }
+
 template <int NW>
 struct WaveLds {
     float wx[NL][NW];          // window hits: x at y = 0
     float wz[NL][NW];          //              z
-    float wd[NL][NW];          //              stereo tangent
+    float wd[6][NW];           //              stereo tangent (stereo layers only)
     int32_t wfirst[NL];        // event-local index of each window's first hit
     int32_t wlen[NL];
-    uint32_t qkey[QCAP];       // queued doublets: set << 16 | i0 << 8 | i2
-    float qtx[QCAP];           //                  their slope
     uint64_t tk[2][MAX_TRIPLETS];   // top-n keys (double buffered), sorted
     uint8_t th1[2][MAX_TRIPLETS];   // middle hit of each kept triplet
-    uint64_t bk[WAVE];         // triplets of the current pass
-    uint8_t bh1[WAVE];
-    float ca[MAX_TRIPLETS], cb[MAX_TRIPLETS], cc[MAX_TRIPLETS];  // triplet x(z) models
-    int8_t ch[MAX_TRIPLETS][NL];    // candidate hits, window-relative, -1 = none
+    union {
+        struct {               // seeding
+            uint32_t qkey[QCAP];    // queued doublets: set << 16 | i0 << 8 | i2
+            float qtx[QCAP];        //                  their slope
+        };
+        struct {               // candidates (after seeding)
+            float ca[MAX_TRIPLETS], cb[MAX_TRIPLETS], cc[MAX_TRIPLETS];  // triplet x(z) models
+            int8_t ch[MAX_TRIPLETS][NL];    // candidate hits, window-relative, -1 = none
+        };
+    };
 };
 
 // Work counters of one track (only in the counting build, CNT = true).
@@ -160,33 +174,33 @@ struct Track {
     }
 
     // Merge this pass's accepted triplets (one per lane) into the top-n list.
+    // Every element's place in the merged order is its rank among the kept
+    // list (sorted, lane i < nL holds entry i) and this pass's keys, counted
+    // against broadcast keys; keys are distinct, so the ranks are too.
     __device__ void merge(bool valid, uint64_t key, int h1) {
         const int lane = lane_id();
         const uint64_t bal = __ballot(valid);
         const int nb = __popcll(bal);
         if (nb == 0) return;
-        if (valid) {
-            const int pos = lanes_below(bal);
-            L.bk[pos] = key;
-            L.bh1[pos] = (uint8_t)h1;
-        }
-        wave_sync();
         const int NT = P->n_triplets;
-        const int nu = nL + nb;
-        for (int j = lane; j < nu; j += WAVE) {
-            uint64_t kj;
-            uint8_t hj;
-            if (j < nL) { kj = L.tk[buf][j]; hj = L.th1[buf][j]; }
-            else { kj = L.bk[j - nL]; hj = L.bh1[j - nL]; }
-            int rank = 0;
-            for (int i = 0; i < nL; ++i) rank += L.tk[buf][i] < kj ? 1 : 0;
-            for (int i = 0; i < nb; ++i) rank += L.bk[i] < kj ? 1 : 0;
-            if (rank < NT) {
-                L.tk[buf ^ 1][rank] = kj;
-                L.th1[buf ^ 1][rank] = hj;
-            }
+        const uint64_t mine = lane < nL ? L.tk[buf][lane] : 0ull;
+        const int mh1 = lane < nL ? L.th1[buf][lane] : 0;
+        int r_new = 0, r_old = lane;
+        for (int i = 0; i < nL; ++i) r_new += bcast64(mine, i) < key ? 1 : 0;
+        for (uint64_t m = bal; m; m &= m - 1) {
+            const uint64_t k = bcast64(key, __builtin_ctzll(m));
+            r_new += k < key ? 1 : 0;
+            r_old += k < mine ? 1 : 0;
         }
-        nL = nu < NT ? nu : NT;
+        if (valid && r_new < NT) {
+            L.tk[buf ^ 1][r_new] = key;
+            L.th1[buf ^ 1][r_new] = (uint8_t)h1;
+        }
+        if (lane < nL && r_old < NT) {
+            L.tk[buf ^ 1][r_old] = mine;
+            L.th1[buf ^ 1][r_old] = (uint8_t)mh1;
+        }
+        nL = nL + nb < NT ? nL + nb : NT;
         buf ^= 1;
         wave_sync();
     }
@@ -231,6 +245,8 @@ struct Track {
             cnt[C_TRACKS] = 1;
             tphase = __builtin_readcyclecounter();
         }
+        // bucket offsets of this event (both zones), fetched with the track state
+        const uint32_t ho = lane <= 2 * NL ? B.hit_off[ev * 24u + (uint32_t)lane] : 0u;
         const float x_in = B.tx_[t], y_in = B.ty_[t], tx_in = B.ttx[t], ty_in = B.tty[t];
         const float qop = B.tqop[t];
         const float dR = P->dRatio;
@@ -243,42 +259,47 @@ struct Track {
         const float dtx = P->kick * qop;
         const float T = tx_in + dtx;
         const float kd = P->kappa * dtx;
-        const uint32_t ebase = B.hit_off[ev * 24u];
+        const uint32_t ebase = (uint32_t)__builtin_amdgcn_readlane((int)ho, 0);
 
         // ---- search windows: lane 3*l + k searches bound k of layer l ----
         int pos = 0;
-        if (lane < 3 * NL) {
-            const int l = lane / 3, k = lane - 3 * (lane / 3);
-            const float dz = P->z[l] - P->z_mag;
-            const float dzT = P->z[l] - P->z_T;
-            const float xe = x_mag + T * dz + kd * dzT * dzT;
-            const float ye = y_in + ty_in * (P->z[l] - P->z_in);
-            float xc, xmin, xmax;
-            if (is_uv(l)) {
-                xc = xe - P->dxdy[l] * ye;
-                xmin = xc - P->uv_halfwidth;
-                xmax = xc + P->uv_halfwidth;
-            } else {
-                const float xtol = P->xtol_const + P->xtol_pscale / p;
-                float asymL = 0.0f, asymR = 0.0f;
-                if (q * P->polarity > 0) asymR = P->xasym; else asymL = P->xasym;
-                xc = xe;
-                xmin = xc - xtol - asymL;
-                xmax = xc + xtol + asymR;
+        {
+            const int l = lane < 3 * NL ? lane / 3 : 0;
+            const uint32_t b0 = (uint32_t)__shfl((int)ho, 2 * l + zone);
+            const uint32_t b1 = (uint32_t)__shfl((int)ho, 2 * l + zone + 1);
+            if (lane < 3 * NL) {
+                const int k = lane - 3 * l;
+                const float dz = P->z[l] - P->z_mag;
+                const float dzT = P->z[l] - P->z_T;
+                const float xe = x_mag + T * dz + kd * dzT * dzT;
+                const float ye = y_in + ty_in * (P->z[l] - P->z_in);
+                float xc, xmin, xmax;
+                if (is_uv(l)) {
+                    xc = xe - P->dxdy[l] * ye;
+                    xmin = xc - P->uv_halfwidth;
+                    xmax = xc + P->uv_halfwidth;
+                } else {
+                    const float xtol = P->xtol_const + P->xtol_pscale / p;
+                    float asymL = 0.0f, asymR = 0.0f;
+                    if (q * P->polarity > 0) asymR = P->xasym; else asymL = P->xasym;
+                    xc = xe;
+                    xmin = xc - xtol - asymL;
+                    xmax = xc + xtol + asymR;
+                }
+                const float key = k == 0 ? xmin : (k == 1 ? xc : xmax);
+                uint32_t lo = b0;
+                uint32_t n = b1 - b0;
+                // lower bound (x < key) for x_min and the centre, upper bound (x <= key) for x_max
+                while (n > 0) {
+                    const uint32_t half = n >> 1;
+                    const float v = B.hx[lo + half];
+                    const bool right = k == 2 ? (v <= key) : (v < key);
+                    if (right) { lo += half + 1; n -= half + 1; } else { n = half; }
+                }
+                pos = (int)(lo - ebase);
             }
-            const float key = k == 0 ? xmin : (k == 1 ? xc : xmax);
-            const uint32_t b = ev * 24u + 2u * (uint32_t)l + (uint32_t)zone;
-            uint32_t lo = B.hit_off[b];
-            uint32_t n = B.hit_off[b + 1] - lo;
-            // lower bound (x < key) for x_min and the centre, upper bound (x <= key) for x_max
-            while (n > 0) {
-                const uint32_t half = n >> 1;
-                const float v = B.hx[lo + half];
-                const bool right = k == 2 ? (v <= key) : (v < key);
-                if (right) { lo += half + 1; n -= half + 1; } else { n = half; }
-            }
-            pos = (int)(lo - ebase);
         }
+        int wf = 0, wl = 0;   // lane l < 12: first hit (event-local) and length of layer l's window
         {
             const int src = lane < NL ? 3 * lane : 0;
             const int lo = __shfl(pos, src), c0 = __shfl(pos, src + 1), hi0 = __shfl(pos, src + 2);
@@ -293,39 +314,62 @@ struct Track {
                     if (first > hi - N) first = hi - N;
                     len = N;
                 }
+                wf = first;
+                wl = len;
                 L.wfirst[lane] = first;
                 L.wlen[lane] = len;
             }
         }
-        wave_sync();
         mark(C_CY_WINDOWS);
 
         // ---- stage window hits into LDS ----
-        for (int it = lane; it < NL * NW; it += WAVE) {
-            const int l = it / NW, j = it - NW * (it / NW);
-            if (j < L.wlen[l]) {
-                const uint32_t g = ebase + (uint32_t)(L.wfirst[l] + j);
-                L.wx[l][j] = B.hx[g];
-                L.wz[l][j] = B.hz[g];
-                L.wd[l][j] = B.hd[g];
+        // Round u covers slots lane + 64 u of the 12 x NW window slots (layer
+        // (lane + 64 u) / NW); every load is issued before the first LDS write.
+        // The same registers tell which layers have window hits that do not
+        // all share one z (resp. one stereo slope): those take the general
+        // paths below.
+        constexpr int SU = NL * NW / WAVE;
+        float sx[SU], sz[SU], sd[SU];
+        uint32_t smask = 0;
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int it = lane + WAVE * u, l = it / NW, j = it - NW * (it / NW);
+            const int la = WAVE * u / NW, lb = (WAVE * u + WAVE - 1) / NW;
+            const int f = l == la ? __builtin_amdgcn_readlane(wf, la) : __builtin_amdgcn_readlane(wf, lb);
+            const int n = l == la ? __builtin_amdgcn_readlane(wl, la) : __builtin_amdgcn_readlane(wl, lb);
+            sx[u] = sz[u] = sd[u] = 0.0f;
+            if (j < n) {
+                const uint32_t g = ebase + (uint32_t)(f + j);
+                sx[u] = B.hx[g];
+                sz[u] = B.hz[g];
+                if (is_uv(l)) sd[u] = B.hd[g];
+                smask |= 1u << u;
             }
+        }
+        uint32_t zvar = 0, dvar = 0;
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int it = lane + WAVE * u, l = it / NW, j = it - NW * (it / NW);
+            const int la = WAVE * u / NW, lb = (WAVE * u + WAVE - 1) / NW;
+            const bool in = (smask >> u) & 1u;
+            if (in) {
+                L.wx[l][j] = sx[u];
+                L.wz[l][j] = sz[u];
+                if (is_uv(l)) L.wd[uv_index(l)][j] = sd[u];
+            }
+            // slot 0 of layer la sits in lane la NW - 64 u, that of lb in lane lb NW - 64 u
+            const float za = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sz[u]), la * NW - WAVE * u));
+            const float zb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sz[u]), lb * NW - WAVE * u));
+            const float da = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sd[u]), la * NW - WAVE * u));
+            const float db = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sd[u]), lb * NW - WAVE * u));
+            const bool zd = in && sz[u] != (l == la ? za : zb);
+            const bool dd = in && sd[u] != (l == la ? da : db);
+            if (__ballot(zd && l == la)) zvar |= 1u << la;
+            if (__ballot(zd && l == lb)) zvar |= 1u << lb;
+            if (is_uv(la) && __ballot(dd && l == la)) dvar |= 1u << la;
+            if (is_uv(lb) && __ballot(dd && l == lb)) dvar |= 1u << lb;
         }
         wave_sync();
-        // layers whose window hits do not all share one z (resp. one stereo
-        // slope): those take the general paths below
-        uint32_t zvar = 0, dvar = 0;
-        for (int it = lane; it < NL * NW; it += WAVE) {
-            const int l = it / NW, j = it - NW * (it / NW);
-            if (j > 0 && j < L.wlen[l]) {
-                if (L.wz[l][j] != L.wz[l][0]) zvar |= 1u << l;
-                if (L.wd[l][j] != L.wd[l][0]) dvar |= 1u << l;
-            }
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            zvar |= __shfl_xor(zvar, off);
-            dvar |= __shfl_xor(dvar, off);
-        }
         if constexpr (CNT) {
             for (int l = 0; l < NL; ++l) cnt[C_STAGED] += (uint32_t)L.wlen[l];
             cnt[C_PAIRS_ALL] = (uint32_t)(L.wlen[0] * L.wlen[8] + L.wlen[3] * L.wlen[11]);
@@ -492,7 +536,7 @@ struct Track {
                 // the hit's x at y = 0 moved along its fibre to the predicted y; with a
                 // common stereo slope in the window these values stay sorted
                 const float yp = y_in + ty_in * (P->z[l] - P->z_in);
-                const float *wdl = L.wd[l];
+                const float *wdl = L.wd[uv_index(l)];
                 auto val = [wxl, wdl, yp](int j) { return wxl[j] + wdl[j] * yp; };
                 const int best = ((dvar >> l) & 1u) ? closest_scan(val, n, xe, bd) : closest_sorted(val, n, xe, bd);
                 if (best >= 0 && bd * bd < T_uv) L.ch[r][l] = (int8_t)best;
@@ -533,7 +577,7 @@ struct Track {
                     float xm;
                     if (is_uv(l)) {
                         const float yv = y_in + ty_in * (zh - P->z_in);
-                        xm = L.wx[l][j] + L.wd[l][j] * yv;
+                        xm = L.wx[l][j] + L.wd[uv_index(l)][j] * yv;
                     } else {
                         xm = L.wx[l][j];
                     }
@@ -574,7 +618,7 @@ struct Track {
                     for (int l = 0; l < NL; ++l) {
                         eta[l] = 0.0f;
                         if (hits[l] < 0 || !is_uv(l)) continue;
-                        eta[l] = -res[l] / L.wd[l][hits[l]];
+                        eta[l] = -res[l] / L.wd[uv_index(l)][hits[l]];
                         YS0 = YS0 + 1.0f;
                         YS1 = YS1 + su[l];
                         YS11 = YS11 + su[l] * su[l];
@@ -622,13 +666,13 @@ struct Track {
             write_none(t, o12);
             return;
         }
-        float bq = acc ? Qb : INFINITY;
-        int br = acc ? lane : (1 << 30);
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const float oq = __shfl_xor(bq, off);
-            const int orr = __shfl_xor(br, off);
-            if (oq < bq || (oq == bq && orr < br)) { bq = oq; br = orr; }
+        // accepted lanes in rank order; the first strict minimum wins ties
+        int br = -1;
+        float bq = 0.0f;
+        for (uint64_t m = __ballot(acc); m; m &= m - 1) {
+            const int r = __builtin_ctzll(m);
+            const float qr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Qb), r));
+            if (br < 0 || qr < bq) { bq = qr; br = r; }
         }
         if (lane == br) {
             const float uT = P->z_T - P->z_ref;

@@ -91,6 +91,31 @@ def test_geometry_variants():
             lf.lf_destroy(ctx)
 
 
+def _jitter(ev, z_mm, slope_rel, seed):
+    """Per-hit z (tilted or bowed layers) and per-hit stereo slope: the hits
+    of one window no longer share a z (or a slope), so the GPU takes its
+    general paths (every pair tested, stereo windows scanned)."""
+    rng = np.random.default_rng(seed)
+    hz = ev.hit_z + rng.uniform(-z_mm, z_mm, ev.n_hits).astype(np.float32)
+    hd = ev.hit_dxdy * (1.0 + rng.uniform(-slope_rel, slope_rel, ev.n_hits)).astype(np.float32)
+    return lfgen.Events(**{**ev.__dict__, "hit_z": hz.astype(np.float32), "hit_dxdy": hd.astype(np.float32)})
+
+
+@pytest.mark.parametrize("z_mm,slope_rel", [(1.5, 0.02), (0.0, 0.02), (3.0, 0.0)],
+                         ids=["z_and_slope", "slope_only", "z_only"])
+def test_per_hit_z_and_slope(z_mm, slope_rel):
+    ev = _jitter(lfgen.generate("nominal", n_events=5), z_mm, slope_rel, seed=11)
+    _check_all_modes(ev, f"nominal[5] z+-{z_mm} slope+-{slope_rel}")
+
+
+def test_inverted_windows():
+    """Negative tolerances: high-momentum x windows have x_max < x_min
+    (empty), the stereo windows have their centre outside the bounds."""
+    ev = lfgen.generate("nominal", n_events=4)
+    _check_all_modes(ev, "nominal[4] inverted", {"xtol_const": -120.0, "xasym": 300.0})
+    _check_all_modes(ev, "nominal[4] inverted uv", {"uv_halfwidth": -2.0, "n_hits_window": 7})
+
+
 @pytest.mark.parametrize("exec_cfg", [
     {"waves_per_block": 1}, {"waves_per_block": 4}, {"items_per_grab": 3}, {"items_per_grab": 16},
     {"blocks_per_cu": 1, "items_per_grab": 2},
