@@ -5,9 +5,11 @@ Workload: the nominal batch -- 1,000 synthetic events, each with 350
 particles (p 2-100 GeV, pt > 0.3 GeV), 200 upstream input tracks (170 true,
 30 fake) and ~5.4k SciFi hits -- resident in HBM.  One step is one pass of
 the whole hot path (windows, triplet seeding, extension, fits, selection,
-momentum) over the batch.  ``value`` is events/s of the batched persistent
-launch; the per-event-launch (plain) and one-wave-per-track (grid) modes are
-reported beside it, with identical output.
+momentum) over the batch.  ``value`` is events/s of the batched launch (one
+wavefront per input track, XCD-ordered); the persistent (resident waves
+pulling from per-XCD work queues) and per-event-launch (plain, eager and
+graph-captured) modes are reported beside it, with identical output, and so
+are the serving loop's rates and latencies.
 
 Roofline: the path is bound by plain VALU arithmetic (binary32 and integer,
 no FMA contraction, no packed math, no dense contraction), so the dominant
@@ -54,7 +56,8 @@ BYTES_PER_TRACK_OUT = 78
 # HBM traffic of the batched kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (per launch, scaled by the counters' reading of a known-size copy), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha256": None, "bytes_per_launch": None}
+TRAFFIC = {"kernel_sha256": "c8f1142d2ec4cba5c749675802319be427699b5a96c387891d74b1e3ada08f60",
+           "bytes_per_launch": 80125311}
 WORKLOADS = {
     "nominal": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",
     "uneven": "uneven: 20000 events, Poisson(7.6) x 50 particles, 0-13k hits and 0-600 tracks/event",
@@ -249,7 +252,7 @@ def main():
     traffic = TRAFFIC["bytes_per_launch"] if TRAFFIC["kernel_sha256"] == sha else None
     nbytes = algorithmic_bytes(ev)
     line = {
-        "metric": "events/s on 1 MI355X (batched persistent launch)",
+        "metric": "events/s on 1 MI355X (plain vs batched vs serving); p50/p99 event latency",
         "value": round(value, 1),
         "unit": "events/s",
         "n_gpus": 1,

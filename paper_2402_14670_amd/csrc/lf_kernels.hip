@@ -63,24 +63,23 @@ __device__ __forceinline__ bool is_uv(int l) {
 // x(z) model term g(u) = u^2 (1 + dRatio u), u = z - z_ref.
 __device__ __forceinline__ float g_of(float u, float dR) { return u * u * (1.0f + dR * u); }
 
-// Number of v[0..n) below key (lower bound) in a non-decreasing LDS array.
-__device__ __forceinline__ int count_below(const float *v, int n, float key) {
-    int lo = 0;
-    while (n > 0) {
-        const int half = n >> 1;
-        if (v[lo + half] < key) { lo += half + 1; n -= half + 1; } else { n = half; }
-    }
-    return lo;
-}
+// Binary searches over at most NMAX (a power of two) window entries, in a
+// fixed number of steps: p advances by s = NMAX, NMAX/2, .., 1 while the
+// entry before p + s still satisfies the (monotone) predicate, so p ends as
+// the number of leading entries that satisfy it.  Only entries < n are read.
 
-// Number of v[0..n) at or below key (upper bound).
-__device__ __forceinline__ int count_upto(const float *v, int n, float key) {
-    int lo = 0;
-    while (n > 0) {
-        const int half = n >> 1;
-        if (v[lo + half] <= key) { lo += half + 1; n -= half + 1; } else { n = half; }
+// Lower bound (v < klo) and upper bound (v <= khi) of one non-decreasing LDS
+// array, searched together.
+template <int NMAX>
+__device__ __forceinline__ void bounds_sorted(const float *v, int n, float klo, float khi, int &lo, int &hi) {
+    int p = 0, q = 0;
+#pragma unroll
+    for (int s = NMAX; s > 0; s >>= 1) {
+        if (p + s <= n && v[p + s - 1] < klo) p += s;
+        if (q + s <= n && v[q + s - 1] <= khi) q += s;
     }
-    return lo;
+    lo = p;
+    hi = q;
 }
 
 // Closest hit of a window: the first index j minimising d_j = |val(j) - xe|
@@ -89,13 +88,12 @@ __device__ __forceinline__ int count_upto(const float *v, int n, float key) {
 // RN(val(j) - xe) is non-decreasing too, so d falls up to the first j with
 // val(j) >= xe and rises after it: only that index, its left neighbour and
 // the plateau of equal d ending at the left neighbour can hold the answer.
-template <class Val>
+template <int NMAX, class Val>
 __device__ __forceinline__ int closest_sorted(Val val, int n, float xe, float &bd) {
     int p = 0;
-    for (int len = n; len > 0;) {
-        const int half = len >> 1;
-        if (val(p + half) < xe) { p += half + 1; len -= half + 1; } else { len = half; }
-    }
+#pragma unroll
+    for (int s = NMAX; s > 0; s >>= 1)
+        if (p + s <= n && val(p + s - 1) < xe) p += s;
     int best = p;
     float d = p < n ? fabsf(val(p) - xe) : INFINITY;
     if (p > 0) {
@@ -221,7 +219,7 @@ struct Track {
             const float x1e = P->z[l1] * txd + (x0 - txd * z0) * K;
             float bd = INFINITY;
             const float *wx1 = L.wx[l1];
-            best = closest_sorted([wx1](int j) { return wx1[j]; }, L.wlen[l1], x1e, bd);
+            best = closest_sorted<NW>([wx1](int j) { return wx1[j]; }, L.wlen[l1], x1e, bd);
             if (best >= 0) {
                 const float chi2 = bd * bd;
                 if (chi2 < P->T_triplet) {
@@ -388,8 +386,9 @@ struct Track {
         // <= tolb, so t lies within tolb/|z_mag - z0| of t_c = (x_mag - x0) /
         // (z_mag - z0), and x2 = x0 + t (z2 - z0).  The x2 interval is widened
         // by 0.5 mm + 1e-5 relative, orders of magnitude above the rounding
-        // of the filter itself, and every pair in it is tested with the exact
-        // filter below; pairs outside cannot pass.  Sets without a common z
+        // of the filter itself and of the approximate reciprocal used for the
+        // bracket, and every pair in it is tested with the exact filter
+        // below; pairs outside cannot pass.  Sets without a common z
         // per window (or a degenerate lever arm) test every pair.
         const int n00 = L.wlen[0], n01 = L.wlen[3];
         const int items_total = n00 + n01;
@@ -410,20 +409,21 @@ struct Track {
                     const float lev = P->z_mag - z0;
                     const float dz = L.wz[l2][0] - z0;
                     if (fabsf(lev) > 1.0f && fabsf(dz) > 1.0f) {
-                        const float tc = (x_mag - x0) / lev;
-                        const float dt0 = P->magtol_max / fabsf(lev);
+                        const float rl = __builtin_amdgcn_rcpf(lev);   // within 1 ulp: the bracket is padded
+                        const float arl = fabsf(rl);
+                        const float tc = (x_mag - x0) * rl;
+                        const float dt0 = P->magtol_max * arl;
                         float tolb = tolc + (P->magtol_txscale > 0.0f ? P->magtol_txscale : 0.0f) *
                                                 (fabsf(tc) + dt0);
                         if (tolb < P->magtol_min) tolb = P->magtol_min;
                         if (tolb > P->magtol_max) tolb = P->magtol_max;
-                        const float dt = tolb / fabsf(lev);
+                        const float dt = tolb * arl;
                         const float e1 = x0 + (tc - dt) * dz, e2 = x0 + (tc + dt) * dz;
                         const float margin = 0.5f + 1e-5f * (fabsf(e1) + fabsf(e2));
                         const float xlo = (e1 < e2 ? e1 : e2) - margin;
                         const float xhi = (e1 < e2 ? e2 : e1) + margin;
                         if (fabsf(xlo) < 1e30f && fabsf(xhi) < 1e30f) {
-                            jlo = count_below(L.wx[l2], n2, xlo);
-                            jhi = count_upto(L.wx[l2], n2, xhi);
+                            bounds_sorted<NW>(L.wx[l2], n2, xlo, xhi, jlo, jhi);
                         }
                     }
                 }
@@ -530,7 +530,7 @@ struct Track {
             const float *wxl = L.wx[l];
             float bd = INFINITY;
             if (slot < 3) {
-                const int best = closest_sorted([wxl](int j) { return wxl[j]; }, n, xe, bd);
+                const int best = closest_sorted<NW>([wxl](int j) { return wxl[j]; }, n, xe, bd);
                 if (best >= 0 && bd * bd < P->T_x) L.ch[r][l] = (int8_t)best;
             } else {
                 // the hit's x at y = 0 moved along its fibre to the predicted y; with a
@@ -538,7 +538,7 @@ struct Track {
                 const float yp = y_in + ty_in * (P->z[l] - P->z_in);
                 const float *wdl = L.wd[uv_index(l)];
                 auto val = [wxl, wdl, yp](int j) { return wxl[j] + wdl[j] * yp; };
-                const int best = ((dvar >> l) & 1u) ? closest_scan(val, n, xe, bd) : closest_sorted(val, n, xe, bd);
+                const int best = ((dvar >> l) & 1u) ? closest_scan(val, n, xe, bd) : closest_sorted<NW>(val, n, xe, bd);
                 if (best >= 0 && bd * bd < T_uv) L.ch[r][l] = (int8_t)best;
             }
         }
