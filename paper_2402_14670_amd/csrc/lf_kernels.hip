@@ -48,6 +48,23 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Pairwise sum over each aligned group of 16 lanes: lane j adds lane j^1,
+// then j^2, j^4, j^8 (the last two as mirrors, equal to the xor partner once
+// the quads, resp. halves, hold equal values).  Every lane of the group ends
+// with ((v0+v1)+(v2+v3)) + ... in the same association; float addition is
+// commutative, so both partners of a step compute the same bits.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float sum16(float v) {
+    v = v + dpp<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
+    v = v + dpp<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+    v = v + dpp<0x141>(v);   // row_half_mirror: lane 7 - j within 8
+    v = v + dpp<0x140>(v);   // row_mirror: lane 15 - j within 16
+    return v;
+}
+
 // Lane i's 64-bit value, broadcast (i uniform).
 __device__ __forceinline__ uint64_t bcast64(uint64_t v, int i) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, i);
@@ -132,12 +149,11 @@ struct WaveLds {
     float wd[6][NW];           //              stereo tangent (stereo layers only)
     int32_t wfirst[NL];        // event-local index of each window's first hit
     int32_t wlen[NL];
-    uint64_t tk[2][MAX_TRIPLETS];   // top-n keys (double buffered), sorted
-    uint8_t th1[2][MAX_TRIPLETS];   // middle hit of each kept triplet
+    uint64_t tk[MAX_TRIPLETS];      // top-n keys, sorted
+    uint8_t th1[MAX_TRIPLETS];      // middle hit of each kept triplet
     union {
         struct {               // seeding
             uint32_t qkey[QCAP];    // queued doublets: set << 16 | i0 << 8 | i2
-            float qtx[QCAP];        //                  their slope
         };
         struct {               // candidates (after seeding)
             float ca[MAX_TRIPLETS], cb[MAX_TRIPLETS], cc[MAX_TRIPLETS];  // triplet x(z) models
@@ -158,7 +174,6 @@ struct Track {
     const KParams *__restrict__ P;
     WaveLds<NW> &L;
     int nL;    // kept triplets
-    int buf;   // live half of the top-n double buffer
     uint32_t cnt[CNT ? C_N : 1];
     uint64_t tphase;
 
@@ -181,8 +196,8 @@ struct Track {
         const int nb = __popcll(bal);
         if (nb == 0) return;
         const int NT = P->n_triplets;
-        const uint64_t mine = lane < nL ? L.tk[buf][lane] : 0ull;
-        const int mh1 = lane < nL ? L.th1[buf][lane] : 0;
+        const uint64_t mine = lane < nL ? L.tk[lane] : 0ull;
+        const int mh1 = lane < nL ? L.th1[lane] : 0;
         int r_new = 0, r_old = lane;
         for (int i = 0; i < nL; ++i) r_new += bcast64(mine, i) < key ? 1 : 0;
         for (uint64_t m = bal; m; m &= m - 1) {
@@ -190,16 +205,16 @@ struct Track {
             r_new += k < key ? 1 : 0;
             r_old += k < mine ? 1 : 0;
         }
+        wave_sync();   // every lane has read the old list
         if (valid && r_new < NT) {
-            L.tk[buf ^ 1][r_new] = key;
-            L.th1[buf ^ 1][r_new] = (uint8_t)h1;
+            L.tk[r_new] = key;
+            L.th1[r_new] = (uint8_t)h1;
         }
         if (lane < nL && r_old < NT) {
-            L.tk[buf ^ 1][r_old] = mine;
-            L.th1[buf ^ 1][r_old] = (uint8_t)mh1;
+            L.tk[r_old] = mine;
+            L.th1[r_old] = (uint8_t)mh1;
         }
         nL = nL + nb < NT ? nL + nb : NT;
-        buf ^= 1;
         wave_sync();
     }
 
@@ -211,11 +226,11 @@ struct Track {
         int best = -1;
         if (lane < count) {
             const uint32_t e = L.qkey[lane];
-            const float txd = L.qtx[lane];
             const int s = (int)(e >> 16), i0 = (int)((e >> 8) & 0xffu), i2 = (int)(e & 0xffu);
-            const int l0 = s ? 3 : 0, l1 = s ? 7 : 4;
+            const int l0 = s ? 3 : 0, l1 = s ? 7 : 4, l2 = s ? 11 : 8;
             const float K = s ? P->K_last : P->K_first;
             const float x0 = L.wx[l0][i0], z0 = L.wz[l0][i0];
+            const float txd = (L.wx[l2][i2] - x0) / (L.wz[l2][i2] - z0);   // the doublet's slope, as queued
             const float x1e = P->z[l1] * txd + (x0 - txd * z0) * K;
             float bd = INFINITY;
             const float *wx1 = L.wx[l1];
@@ -228,7 +243,7 @@ struct Track {
                           (uint64_t)(uint32_t)((s << 12) | (i0 << 6) | i2);
                     // a full list only admits keys below its last one (exactly what the
                     // rank count of merge() would keep)
-                    valid = nL < P->n_triplets || key < L.tk[buf][nL - 1];
+                    valid = nL < P->n_triplets || key < L.tk[nL - 1];
                 }
             }
         }
@@ -376,7 +391,6 @@ struct Track {
         mark(C_CY_STAGE);
         // ---- doublets of both seed sets, filtered, queued; triplets by passes ----
         nL = 0;
-        buf = 0;
         const float tolc = P->magtol_const + P->magtol_pscale / p;
         const bool low_p = p < P->p_charge_cut;
         int qn = 0;
@@ -456,7 +470,6 @@ struct Track {
                 if (pass) {
                     const int at = qn + lanes_below(bal);
                     L.qkey[at] = ((uint32_t)s << 16) | ((uint32_t)i0 << 8) | (uint32_t)i2;
-                    L.qtx[at] = txd;
                 }
                 qn += __popcll(bal);
                 if (qn >= WAVE) {
@@ -464,10 +477,9 @@ struct Track {
                     flush(WAVE);
                     const int rest = qn - WAVE;
                     uint32_t k2 = 0;
-                    float t2 = 0.0f;
-                    if (lane < rest) { k2 = L.qkey[WAVE + lane]; t2 = L.qtx[WAVE + lane]; }
+                    if (lane < rest) k2 = L.qkey[WAVE + lane];
                     wave_sync();
-                    if (lane < rest) { L.qkey[lane] = k2; L.qtx[lane] = t2; }
+                    if (lane < rest) L.qkey[lane] = k2;
                     qn = rest;
                     wave_sync();
                 }
@@ -488,9 +500,9 @@ struct Track {
         mark(C_CY_DOUBLETS);
         // ---- triplet x(z) models ----
         if (lane < nL) {
-            const uint32_t lo = (uint32_t)L.tk[buf][lane];
+            const uint32_t lo = (uint32_t)L.tk[lane];
             const int s = (int)((lo >> 12) & 1u), i0 = (int)((lo >> 6) & 63u), i2 = (int)(lo & 63u);
-            const int i1 = L.th1[buf][lane];
+            const int i1 = L.th1[lane];
             const int l0 = s ? 3 : 0, l1 = s ? 7 : 4, l2 = s ? 11 : 8;
             const float u0 = L.wz[l0][i0] - P->z_ref, u1 = L.wz[l1][i1] - P->z_ref, u2 = L.wz[l2][i2] - P->z_ref;
             const float X0 = L.wx[l0][i0], X1 = L.wx[l1][i1], X2 = L.wx[l2][i2];
@@ -519,7 +531,7 @@ struct Track {
         const float T_uv = T_uv0 < P->T_uv_floor ? P->T_uv_floor : T_uv0;
         for (int it = lane; it < nL * NSLOT; it += WAVE) {
             const int r = it / NSLOT, slot = it - NSLOT * (it / NSLOT);
-            const int s = (int)(((uint32_t)L.tk[buf][r] >> 12) & 1u);
+            const int s = (int)(((uint32_t)L.tk[r] >> 12) & 1u);
             int l;
             if (slot < 3) l = s ? 4 * slot : 4 * slot + 3;
             else l = 4 * ((slot - 3) >> 1) + 1 + ((slot - 3) & 1);
@@ -545,150 +557,135 @@ struct Track {
         wave_sync();
 
         mark(C_CY_EXTEND);
-        // ---- fits and quality, one lane per candidate ----
-        bool acc = false, fit_lane = false;
-        float Qb = 0.0f, fa = 0.0f, fb = 0.0f, fc = 0.0f, fy0 = 0.0f, fty = 0.0f;
-        int nb = 0;
-        if (lane < nL) {
-            int hits[NL];
-            int n = 0, n_uv = 0;
+        // ---- fits and quality: 16 lanes per candidate, 4 candidates per pass ----
+        // Lane (g, j) = (lane / 16, lane % 16) holds layer j of the g-th
+        // candidate of the pass; each fit sum is the pairwise sum over the 16
+        // slots (absent hits and slots 12..15 add +0), formed by four DPP
+        // exchange steps, so every lane of the group ends with the same sums
+        // and solves the normal equations itself.
+        uint64_t fitm = 0;   // candidates passing the candidate rule, in rank order
+        {
+            bool rule = false;
+            if (lane < nL) {
+                int n = 0;
+                bool st_ok = true;
 #pragma unroll
-            for (int l = 0; l < NL; ++l) {
-                hits[l] = L.ch[lane][l];
-                if (hits[l] >= 0) { ++n; if (is_uv(l)) ++n_uv; }
+                for (int l = 0; l < NL; ++l) n += L.ch[lane][l] >= 0 ? 1 : 0;
+#pragma unroll
+                for (int st = 0; st < 3; ++st)
+                    if (L.ch[lane][4 * st + 1] < 0 && L.ch[lane][4 * st + 2] < 0) st_ok = false;
+                rule = n >= 9 && st_ok;
             }
-            bool st_ok = true;
+            fitm = __ballot(rule);
+        }
+        if constexpr (CNT) cnt[C_FITTED] = (uint32_t)__popcll(fitm);
+        int best_r = -1, best_n = 0;
+        float best_Q = 0.0f, bfa = 0.0f, bfb = 0.0f, bfc = 0.0f, bfy0 = 0.0f, bfty = 0.0f;
+        const int g = lane >> 4, j = lane & 15;
+        const bool uvj = j < NL && is_uv(j);
+        const float Tj = uvj ? T_uv : P->T_x;
+        while (fitm) {
+            int r = -1;
+            int rq[4];
 #pragma unroll
-            for (int st = 0; st < 3; ++st)
-                if (hits[4 * st + 1] < 0 && hits[4 * st + 2] < 0) st_ok = false;
-            if constexpr (CNT) fit_lane = n >= 9 && st_ok;
-            if (n >= 9 && st_ok) {
-                const float a = L.ca[lane], b = L.cb[lane], c = L.cc[lane];
-                float su[NL], sh[NL], rho[NL];
-                float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, S11 = 0.0f, S12 = 0.0f, S22 = 0.0f;
-                float R0 = 0.0f, R1 = 0.0f, R2 = 0.0f;
-#pragma unroll
-                for (int l = 0; l < NL; ++l) {
-                    su[l] = 0.0f; sh[l] = 0.0f; rho[l] = 0.0f;
-                    const int j = hits[l];
-                    if (j < 0) continue;
-                    const float zh = L.wz[l][j];
-                    const float u = zh - P->z_ref;
-                    float xm;
-                    if (is_uv(l)) {
-                        const float yv = y_in + ty_in * (zh - P->z_in);
-                        xm = L.wx[l][j] + L.wd[uv_index(l)][j] * yv;
-                    } else {
-                        xm = L.wx[l][j];
-                    }
-                    const float sv = u * INV1024;
-                    const float h = sv * sv * (1.0f + dR * u);
-                    const float r = xm - (a + b * u + c * g_of(u, dR));
-                    su[l] = sv; sh[l] = h; rho[l] = r;
-                    S0 = S0 + 1.0f;
-                    S1 = S1 + sv;
-                    S2 = S2 + h;
-                    S11 = S11 + sv * sv;
-                    S12 = S12 + sv * h;
-                    S22 = S22 + h * h;
-                    R0 = R0 + r;
-                    R1 = R1 + sv * r;
-                    R2 = R2 + h * r;
+            for (int k = 0; k < 4; ++k) {
+                rq[k] = fitm ? (int)__builtin_ctzll(fitm) : -1;
+                if (fitm) fitm &= fitm - 1;
+                if (k == g) r = rq[k];
+            }
+            int hit = -1;
+            if (r >= 0 && j < NL) hit = L.ch[r][j];
+            const bool pres = hit >= 0;
+            const bool pres_uv = pres && uvj;
+            float a = 0.0f, b = 0.0f, c = 0.0f;
+            if (r >= 0) { a = L.ca[r]; b = L.cb[r]; c = L.cc[r]; }
+            float sv = 0.0f, h = 0.0f, rr = 0.0f, dxy = 1.0f;
+            if (pres) {
+                const float zh = L.wz[j][hit];
+                const float u = zh - P->z_ref;
+                float xm;
+                if (uvj) {
+                    dxy = L.wd[uv_index(j)][hit];
+                    const float yv = y_in + ty_in * (zh - P->z_in);
+                    xm = L.wx[j][hit] + dxy * yv;
+                } else {
+                    xm = L.wx[j][hit];
                 }
-                const float m00 = S11 * S22 - S12 * S12;
-                const float m01 = S1 * S22 - S12 * S2;
-                const float m02 = S1 * S12 - S11 * S2;
-                const float det = S0 * m00 - S1 * m01 + S2 * m02;
-                if (fabsf(det) > 0.0f) {
-                    const float da = (R0 * m00 - S1 * (R1 * S22 - S12 * R2) + S2 * (R1 * S12 - S11 * R2)) / det;
-                    const float db = (S0 * (R1 * S22 - S12 * R2) - R0 * m01 + S2 * (S1 * R2 - R1 * S2)) / det;
-                    const float dc = (S0 * (S11 * R2 - R1 * S12) - S1 * (S1 * R2 - R1 * S2) + R0 * m02) / det;
-                    float res[NL];
-                    float Qx = 0.0f;
+                sv = u * INV1024;
+                h = sv * sv * (1.0f + dR * u);
+                rr = xm - (a + b * u + c * g_of(u, dR));
+            }
+            const float S0 = sum16(pres ? 1.0f : 0.0f), S1 = sum16(sv), S2 = sum16(h);
+            const float S11 = sum16(sv * sv), S12 = sum16(sv * h), S22 = sum16(h * h);
+            const float R0 = sum16(rr), R1 = sum16(sv * rr), R2 = sum16(h * rr);
+            const float m00 = S11 * S22 - S12 * S12;
+            const float m01 = S1 * S22 - S12 * S2;
+            const float m02 = S1 * S12 - S11 * S2;
+            const float det = S0 * m00 - S1 * m01 + S2 * m02;
+            const bool ok_x = fabsf(det) > 0.0f;
+            const float det_s = ok_x ? det : 1.0f;
+            const float da = (R0 * m00 - S1 * (R1 * S22 - S12 * R2) + S2 * (R1 * S12 - S11 * R2)) / det_s;
+            const float db = (S0 * (R1 * S22 - S12 * R2) - R0 * m01 + S2 * (S1 * R2 - R1 * S2)) / det_s;
+            const float dc = (S0 * (S11 * R2 - R1 * S12) - S1 * (S1 * R2 - R1 * S2) + R0 * m02) / det_s;
+            const float res = pres ? rr - (da + db * sv + dc * h) : 0.0f;
+            const float Qx = sum16(pres ? res * res / Tj : 0.0f);
+            const float eta = pres_uv ? -res / dxy : 0.0f;
+            const float YS0 = sum16(pres_uv ? 1.0f : 0.0f), YS1 = sum16(pres_uv ? sv : 0.0f);
+            const float YS11 = sum16(pres_uv ? sv * sv : 0.0f);
+            const float Y0 = sum16(eta), Y1 = sum16(pres_uv ? sv * eta : 0.0f);
+            const float D = YS0 * YS11 - YS1 * YS1;
+            const bool ok_y = fabsf(D) > 0.0f;
+            const float D_s = ok_y ? D : 1.0f;
+            const float dy0 = (Y0 * YS11 - YS1 * Y1) / D_s;
+            const float dty = (YS0 * Y1 - YS1 * Y0) / D_s;
+            const float dslope = dty * INV1024;
+            const float ry = pres_uv ? eta - (dy0 + dty * sv) : 0.0f;
+            const float Qy = sum16(pres_uv ? ry * ry / P->T_y : 0.0f);
+            const int n = (int)S0, n_uv = (int)YS0;   // exact counts
+            const float Q = (Qx / (float)(n - 3) + Qy / (float)(n_uv - 2)) * P->C_nhits[n - 9 < 0 ? 0 : (n - 9 > 3 ? 3 : n - 9)];
+            const bool acc = r >= 0 && ok_x && ok_y && fabsf(dslope) < P->T_ty && Q < P->T_Q;
+            // candidates of this pass in rank order: the first strict minimum wins ties
+            const uint64_t accm = __ballot(acc && j == 0);
+            if constexpr (CNT) cnt[C_ACCEPTED] += (uint32_t)__popcll(accm);
 #pragma unroll
-                    for (int l = 0; l < NL; ++l) {
-                        res[l] = 0.0f;
-                        if (hits[l] < 0) continue;
-                        res[l] = rho[l] - (da + db * su[l] + dc * sh[l]);
-                        Qx = Qx + res[l] * res[l] / (is_uv(l) ? T_uv : P->T_x);
-                    }
-                    float YS0 = 0.0f, YS1 = 0.0f, YS11 = 0.0f, Y0 = 0.0f, Y1 = 0.0f;
-                    float eta[NL];
-#pragma unroll
-                    for (int l = 0; l < NL; ++l) {
-                        eta[l] = 0.0f;
-                        if (hits[l] < 0 || !is_uv(l)) continue;
-                        eta[l] = -res[l] / L.wd[uv_index(l)][hits[l]];
-                        YS0 = YS0 + 1.0f;
-                        YS1 = YS1 + su[l];
-                        YS11 = YS11 + su[l] * su[l];
-                        Y0 = Y0 + eta[l];
-                        Y1 = Y1 + su[l] * eta[l];
-                    }
-                    const float D = YS0 * YS11 - YS1 * YS1;
-                    if (fabsf(D) > 0.0f) {
-                        const float dy0 = (Y0 * YS11 - YS1 * Y1) / D;
-                        const float dty = (YS0 * Y1 - YS1 * Y0) / D;
-                        const float dslope = dty * INV1024;
-                        if (fabsf(dslope) < P->T_ty) {
-                            float Qy = 0.0f;
-#pragma unroll
-                            for (int l = 0; l < NL; ++l) {
-                                if (hits[l] < 0 || !is_uv(l)) continue;
-                                const float ry = eta[l] - (dy0 + dty * su[l]);
-                                Qy = Qy + ry * ry / P->T_y;
-                            }
-                            const float Q = (Qx / (float)(n - 3) + Qy / (float)(n_uv - 2)) * P->C_nhits[n - 9];
-                            if (Q < P->T_Q) {
-                                acc = true;
-                                Qb = Q;
-                                nb = n;
-                                fa = a + da;
-                                fb = b + db * INV1024;
-                                fc = c + dc * INV1024SQ;
-                                fy0 = (y_in + ty_in * (P->z_ref - P->z_in)) + dy0;
-                                fty = ty_in + dslope;
-                            }
-                        }
-                    }
-                }
+            for (int k = 0; k < 4; ++k) {
+                if (!((accm >> (16 * k)) & 1ull)) continue;
+                const float qk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Q), 16 * k));
+                if (best_r >= 0 && !(qk < best_Q)) continue;
+                best_r = rq[k];
+                best_Q = qk;
+                best_n = __builtin_amdgcn_readlane(n, 16 * k);
+                bfa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a + da), 16 * k));
+                bfb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b + db * INV1024), 16 * k));
+                bfc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c + dc * INV1024SQ), 16 * k));
+                bfy0 = __int_as_float(__builtin_amdgcn_readlane(
+                    __float_as_int((y_in + ty_in * (P->z_ref - P->z_in)) + dy0), 16 * k));
+                bfty = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ty_in + dslope), 16 * k));
             }
         }
 
         mark(C_CY_FIT);
-        // ---- best candidate: argmin (Q, rank) over the wave ----
-        if constexpr (CNT) {
-            cnt[C_FITTED] = (uint32_t)__popcll(__ballot(fit_lane));
-            cnt[C_ACCEPTED] = (uint32_t)__popcll(__ballot(acc));
-            cnt[C_FOUND] = __ballot(acc) != 0;
-        }
-        if (__ballot(acc) == 0) {
+        // ---- best candidate: output ----
+        if constexpr (CNT) cnt[C_FOUND] = best_r >= 0 ? 1u : 0u;
+        if (best_r < 0) {
             write_none(t, o12);
             return;
         }
-        // accepted lanes in rank order; the first strict minimum wins ties
-        int br = -1;
-        float bq = 0.0f;
-        for (uint64_t m = __ballot(acc); m; m &= m - 1) {
-            const int r = __builtin_ctzll(m);
-            const float qr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Qb), r));
-            if (br < 0 || qr < bq) { bq = qr; br = r; }
-        }
-        if (lane == br) {
+        if (lane == 0) {
             const float uT = P->z_T - P->z_ref;
-            const float txT = fb + 2.0f * fc * uT + 3.0f * fc * dR * uT * uT;
+            const float txT = bfb + 2.0f * bfc * uT + 3.0f * bfc * dR * uT * uT;
             B.found[t] = 1;
-            B.nhits[t] = (uint8_t)nb;
-            B.a[t] = fa;
-            B.b[t] = fb;
-            B.c[t] = fc;
-            B.y0[t] = fy0;
-            B.ty[t] = fty;
+            B.nhits[t] = (uint8_t)best_n;
+            B.a[t] = bfa;
+            B.b[t] = bfb;
+            B.c[t] = bfc;
+            B.y0[t] = bfy0;
+            B.ty[t] = bfty;
             B.qop[t] = (txT - tx_in) / P->kick;
-            B.Q[t] = Qb;
+            B.Q[t] = best_Q;
         }
         if (lane < NL) {
-            const int h = L.ch[br][lane];
+            const int h = L.ch[best_r][lane];
             B.hit_idx[o12 + lane] = h >= 0 ? L.wfirst[lane] + h : -1;
         }
         mark(C_CY_SELECT);
@@ -712,7 +709,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_plain(DevBatch B, const KParams 
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const uint32_t t = B.trk_off[ev] + blockIdx.x * WPB + w;
     if (t >= B.trk_off[ev + 1]) return;
-    Track<NW> tr{B, P, lds[w], 0, 0, {}, 0};
+    Track<NW> tr{B, P, lds[w], 0, {}, 0};
     tr.run(t, ev);
 }
 
@@ -729,7 +726,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_grid(DevBatch B, const KParams *
     const uint32_t lb = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
     const uint32_t t = lb * WPB + w;
     if (t >= B.n_tracks) return;
-    Track<NW, CNT> tr{B, P, lds[w], 0, 0, {}, 0};
+    Track<NW, CNT> tr{B, P, lds[w], 0, {}, 0};
     tr.run(t, B.trk_ev[t]);
     if constexpr (CNT) {
         if (lane_id() == 0)
@@ -773,7 +770,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_persistent(DevBatch B, const KPa
             // keep per-track loads inside the loop: hoisting them across tracks
             // costs ~30 VGPRs of loop-carried state and two waves per SIMD
             asm volatile("" ::: "memory");
-            Track<NW> tr{B, P, lds[w], 0, 0, {}, 0};
+            Track<NW> tr{B, P, lds[w], 0, {}, 0};
             tr.run(t, B.trk_ev[t]);
         }
     }

@@ -54,7 +54,7 @@ MUTANTS = [
     ("uv_x_uncorrected", "xm = ev->x[i] + ev->dxdy[i] * yv;", "xm = ev->x[i];"),
     ("ndof_x", "(Qx / (float)(n - 3)", "(Qx / (float)(n - 2)"),
     ("C_index", "P->C_nhits[n - 9]", "P->C_nhits[n > 9 ? n - 10 : 0]"),
-    ("Qy_tolerance", "Qy = Qy + ry * ry / P->T_y;", "Qy = Qy + ry * ry / P->T_x;"),
+    ("Qy_tolerance", "tqy[l] = ry * ry / P->T_y;", "tqy[l] = ry * ry / P->T_x;"),
     ("T_uv_floor_ignored", "if (T_uv < P->T_uv_floor) T_uv = P->T_uv_floor;", ""),
     ("ty_cut_scale", "float dslope = dty * 0.0009765625f;", "float dslope = dty;"),
     ("qop_curvature_term", "float txT = bb + 2.0f * cc * uT", "float txT = bb + cc * uT"),
