@@ -175,8 +175,11 @@ int lf_create(const lf_geometry *geom, const lf_params *params, size_t device_bu
               lf_ctx **out);
 
 /* Validates a host batch without touching the device: LF_OK, or
- * LF_ERR_INVALID with the reason in lf_last_error(NULL).  lf_upload_events
- * runs the same checks. */
+ * LF_ERR_INVALID with the reason in lf_last_error(NULL).  Checked: offsets
+ * start at 0 and never decrease; fewer than 2^26 events, 2^30 hits and 2^26
+ * tracks (device arrays stay below 4 GiB); no NULL array that has elements;
+ * finite hits and track states; q/p != 0; x sorted inside every bucket.
+ * lf_upload_events runs the same checks. */
 int lf_check_batch(const lf_batch *batch);
 
 /* Validates a host batch, copies it to device memory (on hip_stream) and
@@ -253,7 +256,7 @@ typedef struct {
     uint32_t min_batch_events;   /* arrived events to wait for before launching [1] ... */
     uint32_t max_wait_us;        /* ... unless the oldest has waited this long [0] */
     uint32_t n_slots;            /* batches in flight, one stream each, 1..16 [4] */
-    uint32_t n_pack_threads;     /* host threads packing a batch, 1..32 [4] */
+    uint32_t n_pack_threads;     /* unused (0..64): batches are assembled on the device */
     uint32_t reserved;
     size_t device_budget_bytes;  /* admission budget for resident events [8 GiB] */
 } lf_serve_config;
@@ -277,8 +280,10 @@ typedef struct {
  * device ring of device_budget_bytes in arrival order (a request that does
  * not fit waits: backpressure, nothing is dropped).  Whenever one of
  * n_slots in-flight slots is free, every admitted request (up to
- * max_batch_events) is packed into one batch and runs upload -> hot path
- * (LF_MODE_BATCHED) -> digest -> download on the slot's stream.
+ * max_batch_events) forms one batch: the host writes one descriptor per
+ * event, and on the slot's stream a gather kernel reads the events straight
+ * from the pinned pool into the batch's device arrays, then the hot path
+ * (LF_MODE_BATCHED), a digest kernel and the download of the results run.
  * req_digest[i] (optional) receives a 64-bit digest of request i's results
  * (FNV-1a over each track slot's 20 words -- found | n_hits << 8, 12 hit
  * indices, bits of a b c y0 ty qop Q -- summed as splitmix64(h ^ index *

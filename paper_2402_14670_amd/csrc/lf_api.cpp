@@ -103,7 +103,8 @@ int validate(const lf_batch *b, std::string &why) {
     for (size_t e = 0; e < E; ++e)
         if (b->trk_off[e + 1] < b->trk_off[e]) { why = "batch: trk_off decreases at event " + std::to_string(e); return 0; }
     const uint64_t H = b->hit_off[nb], T = b->trk_off[E];
-    if (H >= 0x7fffffffull || T >= 0x7fffffffull) { why = "batch: more than 2^31-1 hits or tracks"; return 0; }
+    if (E >= (1u << 26)) { why = "batch: 2^26 or more events"; return 0; }
+    if (H >= (1ull << 30) || T >= (1ull << 26)) { why = "batch: 2^30 or more hits, or 2^26 or more tracks"; return 0; }
     if (H && (!b->hit_x || !b->hit_z || !b->hit_dxdy)) { why = "batch: NULL hit array"; return 0; }
     if (T && (!b->trk_x || !b->trk_y || !b->trk_tx || !b->trk_ty || !b->trk_qop)) { why = "batch: NULL track array"; return 0; }
     for (size_t i = 0; i < H; ++i)

@@ -45,6 +45,27 @@ struct ExecCfg {
     int n_cu;
 };
 
+// One event of a serving batch: its blob in pinned host memory (device
+// address) -- [bucket offsets, event-local: u32 x 25][x H][z H][dxdy H]
+// [track x, y, tx, ty, q/p: 5 x T] -- and where it goes in the batch.
+struct GatherDesc {
+    uint64_t src;
+    uint32_t hit_base, trk_base, n_hits, n_tracks;
+};
+
+// Writable view of a batch's input arrays (the serving gather fills them).
+struct BatchIn {
+    uint32_t *hit_off;
+    float *hx, *hz, *hd;
+    uint32_t *trk_off, *trk_ev;
+    float *tx, *ty, *ttx, *tty, *tqop;
+};
+
+// Assembles a batch of E events on the device from their host blobs
+// (zero-copy reads over the host link): offsets rebased, hits and track
+// states copied, trk_ev filled.  desc is in device memory.
+hipError_t launch_gather(const GatherDesc *desc, uint32_t n_events, const BatchIn &out, hipStream_t s);
+
 // Fills trk_ev from trk_off (one thread per track).
 hipError_t launch_track_event(const DevBatch &b, hipStream_t s);
 // The hot path.  P points to a KParams in device memory.  mode: 0 plain

@@ -43,6 +43,14 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// Element i of a device array of less than 4 GiB (the host checks the batch
+// sizes): a 32-bit byte offset from a wave-uniform base, so the load takes
+// the scalar-base form with one 32-bit address register.
+template <class T>
+__device__ __forceinline__ T ld32(const T *base, uint32_t i) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+
 __device__ __forceinline__ int lanes_below(uint64_t mask) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -259,7 +267,7 @@ struct Track {
             tphase = __builtin_readcyclecounter();
         }
         // bucket offsets of this event (both zones), fetched with the track state
-        const uint32_t ho = lane <= 2 * NL ? B.hit_off[ev * 24u + (uint32_t)lane] : 0u;
+        const uint32_t ho = lane <= 2 * NL ? ld32(B.hit_off, ev * 24u + (uint32_t)lane) : 0u;
         const float x_in = B.tx_[t], y_in = B.ty_[t], tx_in = B.ttx[t], ty_in = B.tty[t];
         const float qop = B.tqop[t];
         const float dR = P->dRatio;
@@ -305,7 +313,7 @@ struct Track {
                 // lower bound (x < key) for x_min and the centre, upper bound (x <= key) for x_max
                 while (n > 0) {
                     const uint32_t half = n >> 1;
-                    const float v = B.hx[lo + half];
+                    const float v = ld32(B.hx, lo + half);
                     const bool right = k == 2 ? (v <= key) : (v < key);
                     if (right) { lo += half + 1; n -= half + 1; } else { n = half; }
                 }
@@ -348,14 +356,16 @@ struct Track {
         for (int u = 0; u < SU; ++u) {
             const int it = lane + WAVE * u, l = it / NW, j = it - NW * (it / NW);
             const int la = WAVE * u / NW, lb = (WAVE * u + WAVE - 1) / NW;
-            const int f = l == la ? __builtin_amdgcn_readlane(wf, la) : __builtin_amdgcn_readlane(wf, lb);
-            const int n = l == la ? __builtin_amdgcn_readlane(wl, la) : __builtin_amdgcn_readlane(wl, lb);
+            const int fa = __builtin_amdgcn_readlane(wf, la), fb = __builtin_amdgcn_readlane(wf, lb);
+            const int na = __builtin_amdgcn_readlane(wl, la), nb = __builtin_amdgcn_readlane(wl, lb);
+            const int f = l == la ? fa : fb;
+            const int n = l == la ? na : nb;
             sx[u] = sz[u] = sd[u] = 0.0f;
             if (j < n) {
                 const uint32_t g = ebase + (uint32_t)(f + j);
-                sx[u] = B.hx[g];
-                sz[u] = B.hz[g];
-                if (is_uv(l)) sd[u] = B.hd[g];
+                sx[u] = ld32(B.hx, g);
+                sz[u] = ld32(B.hz, g);
+                if (is_uv(l)) sd[u] = ld32(B.hd, g);
                 smask |= 1u << u;
             }
         }
@@ -784,6 +794,46 @@ __global__ __launch_bounds__(WPB * WAVE) void k_persistent(DevBatch B, const KPa
     }
 }
 
+// Serving gather: block (k, c) copies chunk c of GATHER_CHUNKS of event k's
+// hits and track states from its host blob into the batch.
+constexpr uint32_t GATHER_CHUNKS = 8;
+
+__global__ __launch_bounds__(256) void k_gather(const GatherDesc *__restrict__ desc, uint32_t n_events,
+                                                 BatchIn out) {
+    const uint32_t k = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+    const GatherDesc d = desc[k];
+    const char *src = reinterpret_cast<const char *>(d.src);
+    const uint32_t *loc = reinterpret_cast<const uint32_t *>(src);
+    if (c == 0) {
+        if (tid < 24) out.hit_off[24 * k + tid] = d.hit_base + loc[tid];
+        if (tid == 24) out.trk_off[k] = d.trk_base;
+        if (k + 1 == n_events) {
+            if (tid == 25) out.hit_off[24 * n_events] = d.hit_base + d.n_hits;
+            if (tid == 26) out.trk_off[n_events] = d.trk_base + d.n_tracks;
+        }
+    }
+    const uint32_t H = d.n_hits, T = d.n_tracks;
+    const float *sx = reinterpret_cast<const float *>(src + 100);
+    const float *sz = sx + H, *sd = sz + H, *st = sd + H;
+    const uint32_t h0 = (uint32_t)((uint64_t)H * c / GATHER_CHUNKS), h1 = (uint32_t)((uint64_t)H * (c + 1) / GATHER_CHUNKS);
+    for (uint32_t i = h0 + tid; i < h1; i += 256) {
+        const uint32_t g = d.hit_base + i;
+        out.hx[g] = sx[i];
+        out.hz[g] = sz[i];
+        out.hd[g] = sd[i];
+    }
+    const uint32_t t0 = (uint32_t)((uint64_t)T * c / GATHER_CHUNKS), t1 = (uint32_t)((uint64_t)T * (c + 1) / GATHER_CHUNKS);
+    for (uint32_t i = t0 + tid; i < t1; i += 256) {
+        const uint32_t g = d.trk_base + i;
+        out.tx[g] = st[i];
+        out.ty[g] = st[T + i];
+        out.ttx[g] = st[2 * T + i];
+        out.tty[g] = st[3 * T + i];
+        out.tqop[g] = st[4 * T + i];
+        out.trk_ev[g] = k;
+    }
+}
+
 __global__ void k_track_event(const uint32_t *__restrict__ trk_off, uint32_t n_events, uint32_t n_tracks,
                               uint32_t *__restrict__ trk_ev) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -894,6 +944,12 @@ hipError_t launch_count(const DevBatch &b, const KParams *P, int n_hits_window, 
     const uint32_t grid = (need + NXCD - 1) / NXCD * NXCD;
     if (n_hits_window <= 32) hipLaunchKernelGGL((k_grid<32, 2, true>), dim3(grid), dim3(2 * WAVE), 0, s, b, P);
     else hipLaunchKernelGGL((k_grid<64, 2, true>), dim3(grid), dim3(2 * WAVE), 0, s, b, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const GatherDesc *desc, uint32_t n_events, const BatchIn &out, hipStream_t s) {
+    if (n_events == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3(n_events, GATHER_CHUNKS), dim3(256), 0, s, desc, n_events, out);
     return hipGetLastError();
 }
 

@@ -7,17 +7,18 @@
 // free (continuous batching: requests arriving while others run on the GPU
 // join the next batch), and runs upload -> hot path -> digest -> download on
 // that slot's stream, so copies and kernels of consecutive batches overlap.
-// A request completes when its results are in host memory.
+// A request completes when its results are in host memory.  Batches are
+// assembled on the device: the host writes one 24-byte descriptor per event,
+// and a gather kernel reads the events' blobs from pinned host memory over
+// the host link straight into the batch's device arrays, so no host thread
+// copies event data on the request path.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
 #include <chrono>
-#include <condition_variable>
 #include <cstring>
 #include <deque>
-#include <functional>
-#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -56,7 +57,7 @@ struct Pool {
 
 // Byte layout of one batch region (device ring and pinned staging share it).
 struct BatchLayout {
-    size_t hit_off, hx, hz, hd, trk_off, trk_ev, tx, ty, ttx, tty, tqop, in_bytes;
+    size_t desc, hit_off, hx, hz, hd, trk_off, trk_ev, tx, ty, ttx, tty, tqop, in_bytes;
     size_t dig, found, nhits, hit_idx, fl, out_bytes, total;
     uint32_t E, H, T;
 };
@@ -66,6 +67,7 @@ BatchLayout batch_layout(uint32_t E, uint32_t H, uint32_t T) {
     L.E = E; L.H = H; L.T = T;
     size_t o = 0;
     auto put = [&](size_t n) { size_t at = o; o += a256(n ? n : 1); return at; };
+    L.desc = put((size_t)E * sizeof(lfk::GatherDesc));
     L.hit_off = put(((size_t)E * 24 + 1) * 4);
     L.hx = put((size_t)H * 4); L.hz = put((size_t)H * 4); L.hd = put((size_t)H * 4);
     L.trk_off = put(((size_t)E + 1) * 4); L.trk_ev = put((size_t)T * 4);
@@ -82,68 +84,10 @@ BatchLayout batch_layout(uint32_t E, uint32_t H, uint32_t T) {
     return L;
 }
 
-// Fixed set of worker threads splitting a range of work.
-class Workers {
-  public:
-    explicit Workers(int n) : n_(n < 1 ? 1 : n) {
-        for (int i = 1; i < n_; ++i) th_.emplace_back([this, i] { loop(i); });
-    }
-    ~Workers() {
-        {
-            std::lock_guard<std::mutex> g(m_);
-            stop_ = true;
-            ++gen_;
-        }
-        cv_.notify_all();
-        for (auto &t : th_) t.join();
-    }
-    // Runs f(i, n) on every worker i of n (the caller is worker 0) and waits.
-    void run(const std::function<void(int, int)> &f) {
-        {
-            std::lock_guard<std::mutex> g(m_);
-            f_ = &f;
-            left_ = n_ - 1;
-            ++gen_;
-        }
-        cv_.notify_all();
-        f(0, n_);
-        std::unique_lock<std::mutex> g(m_);
-        done_.wait(g, [this] { return left_ == 0; });
-    }
-
-  private:
-    void loop(int i) {
-        uint64_t seen = 0;
-        for (;;) {
-            const std::function<void(int, int)> *f;
-            {
-                std::unique_lock<std::mutex> g(m_);
-                cv_.wait(g, [&] { return gen_ != seen; });
-                seen = gen_;
-                if (stop_) return;
-                f = f_;
-            }
-            (*f)(i, n_);
-            {
-                std::lock_guard<std::mutex> g(m_);
-                if (--left_ == 0) done_.notify_one();
-            }
-        }
-    }
-    int n_;
-    std::vector<std::thread> th_;
-    std::mutex m_;
-    std::condition_variable cv_, done_;
-    const std::function<void(int, int)> *f_ = nullptr;
-    int left_ = 0;
-    uint64_t gen_ = 0;
-    bool stop_ = false;
-};
-
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    char *stage = nullptr;   // pinned, inputs of one batch
+    lfk::GatherDesc *stage = nullptr;   // pinned, event descriptors of one batch
     char *out = nullptr;     // pinned, outputs of one batch
     size_t stage_cap = 0, out_cap = 0;
     bool busy = false;
@@ -189,9 +133,8 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
     lf_serve_config cfg = *cfg_in;
     if (cfg.max_batch_events == 0) cfg.max_batch_events = 1024;
     if (cfg.n_slots == 0) cfg.n_slots = 4;
-    if (cfg.n_pack_threads == 0) cfg.n_pack_threads = 4;
     if (cfg.device_budget_bytes == 0) cfg.device_budget_bytes = size_t(8) << 30;
-    if (cfg.n_slots > 16 || cfg.n_pack_threads > 32 || cfg.max_batch_events > (1u << 20))
+    if (cfg.n_slots > 16 || cfg.n_pack_threads > 64 || cfg.max_batch_events > (1u << 20))
         return lfapi::ctx_fail(ctx, LF_ERR_INVALID, "lf_serve_run: configuration out of range");
     const uint32_t PE = pool_b->n_events;
     for (uint32_t i = 0; i < n_requests; ++i) {
@@ -271,94 +214,90 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
             big_t += (uint64_t)ts[0] * (cfg.max_batch_events - PE);
         }
     }
-    if (big_h >= 0x7fffffffull || big_t >= 0x7fffffffull) {
+    if (big_h >= (1ull << 30) || big_t >= (1ull << 26)) {
         cleanup();
-        return lfapi::ctx_fail(ctx, LF_ERR_INVALID, "lf_serve_run: max_batch_events too large for 32-bit indices");
+        return lfapi::ctx_fail(ctx, LF_ERR_INVALID, "lf_serve_run: max_batch_events allows batches over 2^30 hits or 2^26 tracks");
     }
     const BatchLayout biggest = batch_layout(cfg.max_batch_events, (uint32_t)big_h, (uint32_t)big_t);
     for (auto &s : slots) {
         err = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
         if (err == hipSuccess) err = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
-        if (err == hipSuccess) err = hipHostMalloc(reinterpret_cast<void **>(&s.stage), biggest.in_bytes, hipHostMallocDefault);
+        if (err == hipSuccess)
+            err = hipHostMalloc(reinterpret_cast<void **>(&s.stage), (size_t)cfg.max_batch_events * sizeof(lfk::GatherDesc),
+                                hipHostMallocDefault);
         if (err == hipSuccess) err = hipHostMalloc(reinterpret_cast<void **>(&s.out), biggest.out_bytes, hipHostMallocDefault);
         if (err != hipSuccess) {
             cleanup();
             return lfapi::ctx_fail(ctx, LF_ERR_NOMEM, "lf_serve_run: slot allocation failed");
         }
-        s.stage_cap = biggest.in_bytes;
+        s.stage_cap = cfg.max_batch_events;
         s.out_cap = biggest.out_bytes;
     }
-    Workers workers((int)cfg.n_pack_threads);
+    // device address of the pinned pool (the gather kernel reads it directly)
+    char *pool_dev = nullptr;
+    err = hipHostGetDevicePointer(reinterpret_cast<void **>(&pool_dev), pool.blob, 0);
+    if (err != hipSuccess) {
+        cleanup();
+        return lfapi::ctx_fail(ctx, LF_ERR_DEVICE, std::string("lf_serve_run: ") + hipGetErrorString(err));
+    }
     const lfk::KParams *P = lfapi::ctx_dparams(ctx);
     const int nhw = lfapi::ctx_nhits_window(ctx);
     const lfk::ExecCfg exec = lfapi::ctx_exec(ctx);
 
-    // Packs pool events evs[0..E) into slot s's staging buffer (host worker
-    // threads) and enqueues upload -> hot path -> digest -> download on the
+    // Writes the descriptors of pool events evs[0..E) and enqueues
+    // descriptors up -> gather -> hot path -> digest -> download on the
     // slot's stream into device region `at` of the ring.
     auto launch_batch = [&](Slot &s, const std::vector<uint32_t> &evs, const BatchLayout &lay,
                             size_t at) -> hipError_t {
         const uint32_t E = (uint32_t)evs.size();
-        std::vector<uint64_t> hb(E + 1), tb(E + 1);
-        hb[0] = tb[0] = 0;
+        if (E > s.stage_cap) return hipErrorInvalidValue;   // descriptors must fit the slot
+        uint32_t H = 0, T = 0;
         for (uint32_t k = 0; k < E; ++k) {
-            hb[k + 1] = hb[k] + pool.nh[evs[k]];
-            tb[k + 1] = tb[k] + pool.nt[evs[k]];
+            const uint32_t ev = evs[k];
+            s.stage[k] = lfk::GatherDesc{reinterpret_cast<uint64_t>(pool_dev + pool.off[ev]), H, T, pool.nh[ev],
+                                         pool.nt[ev]};
+            H += pool.nh[ev];
+            T += pool.nt[ev];
         }
-        const uint64_t H = hb[E], T = tb[E];
-        char *st = s.stage;
-        uint32_t *ho = reinterpret_cast<uint32_t *>(st + lay.hit_off);
-        uint32_t *to = reinterpret_cast<uint32_t *>(st + lay.trk_off);
-        uint32_t *tev = reinterpret_cast<uint32_t *>(st + lay.trk_ev);
-        float *tr[5] = {reinterpret_cast<float *>(st + lay.tx), reinterpret_cast<float *>(st + lay.ty),
-                        reinterpret_cast<float *>(st + lay.ttx), reinterpret_cast<float *>(st + lay.tty),
-                        reinterpret_cast<float *>(st + lay.tqop)};
-        float *hx = reinterpret_cast<float *>(st + lay.hx);
-        float *hz = reinterpret_cast<float *>(st + lay.hz);
-        float *hd = reinterpret_cast<float *>(st + lay.hd);
-        workers.run([&](int w, int nw) {
-            const uint32_t e0 = (uint32_t)((uint64_t)E * w / nw), e1 = (uint32_t)((uint64_t)E * (w + 1) / nw);
-            for (uint32_t k = e0; k < e1; ++k) {
-                const uint32_t ev = evs[k];
-                const char *p = pool.blob + pool.off[ev];
-                const uint32_t *lo = reinterpret_cast<const uint32_t *>(p);
-                for (int b = 0; b < 24; ++b) ho[24 * (size_t)k + b] = (uint32_t)hb[k] + lo[b];
-                const size_t nh = pool.nh[ev], nt = pool.nt[ev];
-                const char *q = p + 100;
-                std::memcpy(hx + hb[k], q, nh * 4); q += nh * 4;
-                std::memcpy(hz + hb[k], q, nh * 4); q += nh * 4;
-                std::memcpy(hd + hb[k], q, nh * 4); q += nh * 4;
-                for (int j = 0; j < 5; ++j) { std::memcpy(tr[j] + tb[k], q, nt * 4); q += nt * 4; }
-                to[k] = (uint32_t)tb[k];
-                for (size_t i = 0; i < nt; ++i) tev[tb[k] + i] = k;
-            }
-        });
-        ho[24 * (size_t)E] = (uint32_t)H;
-        to[E] = (uint32_t)T;
         char *dr = static_cast<char *>(ring_mem) + at;
+        lfk::BatchIn in{};
+        in.hit_off = reinterpret_cast<uint32_t *>(dr + lay.hit_off);
+        in.hx = reinterpret_cast<float *>(dr + lay.hx);
+        in.hz = reinterpret_cast<float *>(dr + lay.hz);
+        in.hd = reinterpret_cast<float *>(dr + lay.hd);
+        in.trk_off = reinterpret_cast<uint32_t *>(dr + lay.trk_off);
+        in.trk_ev = reinterpret_cast<uint32_t *>(dr + lay.trk_ev);
+        in.tx = reinterpret_cast<float *>(dr + lay.tx);
+        in.ty = reinterpret_cast<float *>(dr + lay.ty);
+        in.ttx = reinterpret_cast<float *>(dr + lay.ttx);
+        in.tty = reinterpret_cast<float *>(dr + lay.tty);
+        in.tqop = reinterpret_cast<float *>(dr + lay.tqop);
         lfk::DevBatch d{};
-        d.hit_off = reinterpret_cast<const uint32_t *>(dr + lay.hit_off);
-        d.hx = reinterpret_cast<const float *>(dr + lay.hx);
-        d.hz = reinterpret_cast<const float *>(dr + lay.hz);
-        d.hd = reinterpret_cast<const float *>(dr + lay.hd);
-        d.trk_off = reinterpret_cast<const uint32_t *>(dr + lay.trk_off);
-        d.trk_ev = reinterpret_cast<const uint32_t *>(dr + lay.trk_ev);
-        d.tx_ = reinterpret_cast<const float *>(dr + lay.tx);
-        d.ty_ = reinterpret_cast<const float *>(dr + lay.ty);
-        d.ttx = reinterpret_cast<const float *>(dr + lay.ttx);
-        d.tty = reinterpret_cast<const float *>(dr + lay.tty);
-        d.tqop = reinterpret_cast<const float *>(dr + lay.tqop);
+        d.hit_off = in.hit_off;
+        d.hx = in.hx;
+        d.hz = in.hz;
+        d.hd = in.hd;
+        d.trk_off = in.trk_off;
+        d.trk_ev = in.trk_ev;
+        d.tx_ = in.tx;
+        d.ty_ = in.ty;
+        d.ttx = in.ttx;
+        d.tty = in.tty;
+        d.tqop = in.tqop;
         d.found = reinterpret_cast<uint8_t *>(dr + lay.found);
         d.nhits = reinterpret_cast<uint8_t *>(dr + lay.nhits);
         d.hit_idx = reinterpret_cast<int32_t *>(dr + lay.hit_idx);
         float *fl = reinterpret_cast<float *>(dr + lay.fl);
-        d.a = fl; d.b = fl + T; d.c = fl + 2 * T; d.y0 = fl + 3 * T;
-        d.ty = fl + 4 * T; d.qop = fl + 5 * T; d.Q = fl + 6 * T;
+        d.a = fl; d.b = fl + T; d.c = fl + 2 * (size_t)T; d.y0 = fl + 3 * (size_t)T;
+        d.ty = fl + 4 * (size_t)T; d.qop = fl + 5 * (size_t)T; d.Q = fl + 6 * (size_t)T;
         d.counter = nullptr;
         d.stats = nullptr;
         d.n_events = E;
-        d.n_tracks = (uint32_t)T;
-        hipError_t e = hipMemcpyAsync(dr, st, lay.in_bytes, hipMemcpyHostToDevice, s.stream);
+        d.n_tracks = T;
+        const lfk::GatherDesc *ddesc = reinterpret_cast<const lfk::GatherDesc *>(dr + lay.desc);
+        hipError_t e = hipMemcpyAsync(dr + lay.desc, s.stage, (size_t)E * sizeof(lfk::GatherDesc),
+                                      hipMemcpyHostToDevice, s.stream);
+        if (e == hipSuccess) e = lfk::launch_gather(ddesc, E, in, s.stream);
         if (e == hipSuccess) e = lfk::launch_find(d, P, nhw, 1, exec, nullptr, s.stream);
         if (e == hipSuccess)
             e = lfk::launch_digest(d, d.trk_off, E, reinterpret_cast<unsigned long long *>(dr + lay.dig), s.stream);
@@ -371,10 +310,10 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
     {
         std::vector<uint32_t> evs;
         uint64_t H = 0, T = 0;
-        for (uint32_t e = 0; e < PE && evs.size() < 16; ++e) {
+        for (uint32_t e = 0; e < PE && evs.size() < std::min<uint32_t>(16, cfg.max_batch_events); ++e) {
             const BatchLayout trial = batch_layout((uint32_t)evs.size() + 1, (uint32_t)(H + pool.nh[e]),
                                                    (uint32_t)(T + pool.nt[e]));
-            if (trial.total > ring.cap || trial.in_bytes > slots[0].stage_cap || trial.out_bytes > slots[0].out_cap)
+            if (trial.total > ring.cap || trial.out_bytes > slots[0].out_cap)
                 break;
             evs.push_back(e);
             H += pool.nh[e];
@@ -451,7 +390,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
                 while (E < queue.size() && E < cfg.max_batch_events) {
                     const uint32_t ev = req_event[queue[E]];
                     const BatchLayout trial = batch_layout(E + 1, (uint32_t)(H + pool.nh[ev]), (uint32_t)(T + pool.nt[ev]));
-                    if (trial.in_bytes > s.stage_cap || trial.out_bytes > s.out_cap) break;
+                    if (trial.out_bytes > s.out_cap) break;
                     if (ring.used + trial.total > ring.cap) break;   // admission: the budget is full
                     H += pool.nh[ev];
                     T += pool.nt[ev];
