@@ -74,8 +74,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--plain-steps", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="minimum CPU time of the oracle baseline sample (0 disables it)")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0,
+                    help="wall time of the oracle baseline, half single-threaded, half on all cores (0 disables it)")
     ap.add_argument("--workload", default="nominal", choices=sorted(WORKLOADS))
     ap.add_argument("--events", type=int, default=0, help="events of the workload (0: its full size)")
     ap.add_argument("--no-autotune", action="store_true")
@@ -83,6 +83,9 @@ def parse():
                     help="comma-separated subset of batched,persistent,plain to time (batched is always timed)")
     ap.add_argument("--serve-requests", type=int, default=200000,
                     help="requests per serving run (0 skips the serving runs)")
+    ap.add_argument("--scan-window", action="store_true",
+                    help="instead of the throughput line: events/s and physics efficiency of the batched mode "
+                         "for n_hits_window = 16, 32, 48, 64 (one JSON line)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a known-size reference for HBM "
                          "byte counters under a profiler)")
@@ -120,7 +123,7 @@ def serving(lf, ctx, ev, batched_out, n_requests, seed=40):
     ref = lf.result_digests(batched_out, ev.trk_off)
     rng = np.random.default_rng(seed)
     req = rng.integers(0, ev.n_events, size=n_requests).astype(np.uint32)
-    cfg = {"max_batch_events": 256, "n_slots": 4, "n_pack_threads": 8, "device_budget_bytes": 8 << 30}
+    cfg = {"max_batch_events": 256, "n_slots": 2, "device_budget_bytes": 8 << 30}
     dig, lat, st = lf.lf_serve_run(ctx, ev, req, np.zeros(n_requests), cfg)
     ok = bool(np.array_equal(dig, ref[req]))
     sat = st["events_per_s"]
@@ -144,26 +147,112 @@ def serving(lf, ctx, ev, batched_out, n_requests, seed=40):
             "latency": "arrival to results in host memory; uploads and downloads included"}
 
 
-def cpu_baseline(ev, world, min_seconds):
-    """The oracle, as it stands, on the host: repeated passes over a sample
-    of the same workload until min_seconds of CPU time have elapsed."""
+def host_cores() -> int:
+    """Cores this process may use (capped at 16, the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(ev, world, min_seconds, gpu_out):
+    """The oracle, as it stands, on the host: single-threaded over a sample,
+    then over the whole workload with the events split into one contiguous
+    slice per core (threads; the oracle call releases the GIL), repeated
+    until min_seconds have elapsed.  The first whole pass is also compared,
+    event by event, with the GPU's batched results (digests)."""
+    import concurrent.futures as cf
+    import numpy as np
     import lfgen
     import oracle
+    from paper_2402_14670_amd import lf
     oracle.build(force=False)
-    n_sample = min(ev.n_events, 250)
-    import lfgen
-    sub = lfgen.select_events(ev, range(n_sample))
-    done = 0
-    t0 = time.perf_counter()
+    n1 = min(ev.n_events, 250)
+    sub = lfgen.select_events(ev, range(n1))
+    done, t0 = 0, time.perf_counter()
     while True:
         oracle.run(sub, world)
-        done += n_sample
-        el = time.perf_counter() - t0
-        if el >= min_seconds:
+        done += n1
+        el1 = time.perf_counter() - t0
+        if el1 >= min_seconds / 2:
             break
-    return dict(value=done / el, unit="events/s", cores=1, kind="oracle",
-                sample=f"first {n_sample} events of the batch, {done} events processed "
-                       f"single-threaded in {el:.1f} s")
+    single = done / el1
+    W = host_cores()
+    bounds = [(ev.n_events * k // W, ev.n_events * (k + 1) // W) for k in range(W)]
+    parts = [lfgen.select_events(ev, range(a, b)) for a, b in bounds]
+    with cf.ThreadPoolExecutor(max_workers=W) as pool:
+        first = None
+        passes, t0 = 0, time.perf_counter()
+        while True:
+            outs = list(pool.map(lambda part: oracle.run(part, world), parts))
+            if first is None:
+                first = outs
+            passes += 1
+            el = time.perf_counter() - t0
+            if el >= min_seconds / 2:
+                break
+    multi = passes * ev.n_events / el
+    ref = {k: np.concatenate([o[k] for o in first]) for k in first[0]}
+    ok = lf.result_digests(ref, ev.trk_off) == lf.result_digests(gpu_out, ev.trk_off)
+    return dict(value=round(multi, 1), unit="events/s", cores=W, kind="oracle",
+                sample=f"whole workload ({ev.n_events} events) split over {W} threads, {passes} passes in "
+                       f"{el:.1f} s; single-threaded on its first {n1} events: {single:.1f} events/s "
+                       f"({done} events in {el1:.1f} s)",
+                single_core_events_per_s=round(single, 1), cpu_model=cpu_model(),
+                events_equal_gpu=int(ok.sum()), events_checked=int(ok.size))
+
+
+def end_to_end(lf, ctx, ev, stream, reps=3):
+    """The whole batch from host buffers: validation and upload, the hot path,
+    and the download of the results (host link included)."""
+    import torch
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bid = lf.lf_upload_events(ctx, ev, stream.cuda_stream)
+        lf.lf_find_tracks(ctx, bid, lf.LF_MODE_BATCHED, stream.cuda_stream)
+        lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
+        el = time.perf_counter() - t0
+        best = el if best is None else min(best, el)
+    return {"ms_per_batch": round(best * 1e3, 3), "events_per_s": round(ev.n_events / best, 1),
+            "includes": "host validation, upload, hot path, download (best of %d)" % reps}
+
+
+def scan_window(lf, world, ev, stream, steps, warmup, workload):
+    """The paper's tuning experiment on the window cap: throughput and
+    efficiency (reconstructible particles with p > 5 GeV, truth matching of
+    the generator) for each n_hits_window."""
+    from lfgen import truth
+    rows = []
+    for n in (16, 32, 48, 64):
+        ctx = lf.lf_create(world, {"n_hits_window": n})
+        try:
+            bid = lf.lf_upload_events(ctx, ev, stream.cuda_stream)
+            ms, _ = time_mode(lf, ctx, bid, lf.LF_MODE_BATCHED, steps, warmup, stream)
+            out = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
+        finally:
+            lf.lf_destroy(ctx)
+        ph = truth.physics(ev, out, p_min=5.0)
+        rows.append({"n_hits_window": n, "ms_per_step": round(ms, 4), "events_per_s": round(ev.n_events / ms * 1e3, 1),
+                     "efficiency_p_gt_5GeV": round(ph["efficiency"], 5), "ghost_rate": round(ph["ghost_rate"], 5),
+                     "found_tracks": ph["n_found"], "qop_resolution": round(ph["qop_resolution"], 6)})
+        print(f"bench: n_hits_window {n:3d}  {ms:8.3f} ms/step  efficiency {ph['efficiency']:.4f}  "
+              f"ghosts {ph['ghost_rate']:.4f}", file=sys.stderr, flush=True)
+    return {"metric": "n_hits_window scan: events/s and efficiency (batched mode)", "n_gpus": 1,
+            "config": {"workload": WORKLOADS[workload], "events": ev.n_events, "input_tracks": ev.n_tracks},
+            "steps": steps, "warmup": warmup, "data": "synthetic", "scan": rows}
 
 
 def main():
@@ -195,6 +284,10 @@ def main():
             torch.mul(src, 2.0, out=dst)   # reads and writes exactly n*4 bytes
         torch.cuda.synchronize()
         del src, dst
+
+    if args.scan_window:
+        print(json.dumps(scan_window(lf, world, ev, stream, args.steps, args.warmup, args.workload)), flush=True)
+        return
 
     ctx = lf.lf_create(world)
     bid = lf.lf_upload_events(ctx, ev, stream.cuda_stream)
@@ -240,6 +333,9 @@ def main():
         lf.lf_set_exec(ctx, waves_per_block=c["waves_per_block"])
     work = lf.lf_work_counts(ctx, bid, stream.cuda_stream)
     out = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
+    e2e = end_to_end(lf, ctx, ev, stream)
+    print(f"bench: end to end {e2e['ms_per_batch']:8.3f} ms/batch  {e2e['events_per_s']:12.0f} events/s",
+          file=sys.stderr, flush=True)
     serve = serving(lf, ctx, ev, out, args.serve_requests) if args.serve_requests else None
     lf.lf_destroy(ctx)
 
@@ -287,9 +383,14 @@ def main():
                         "p999": serve["rates"][1]["p999_ms"], "at": "serving, 80% of saturated throughput"}
                        if serve else None),
         "serving": serve,
+        "end_to_end": e2e,
     }
     if args.cpu_seconds > 0:
-        line["cpu_baseline"] = cpu_baseline(ev, world, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(ev, world, args.cpu_seconds, out)
+        print(f"bench: cpu oracle {line['cpu_baseline']['value']:.0f} events/s on "
+              f"{line['cpu_baseline']['cores']} cores; equal to the GPU on "
+              f"{line['cpu_baseline']['events_equal_gpu']}/{line['cpu_baseline']['events_checked']} events",
+              file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 

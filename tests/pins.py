@@ -16,7 +16,7 @@ import numpy as np
 
 import lfgen
 import oracle
-import truth
+from lfgen import truth
 
 NL = 12
 X_LAYERS = (0, 3, 4, 7, 8, 11)
