@@ -56,8 +56,8 @@ BYTES_PER_TRACK_OUT = 78
 # HBM traffic of the batched kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (per launch, scaled by the counters' reading of a known-size copy), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha256": "c8f1142d2ec4cba5c749675802319be427699b5a96c387891d74b1e3ada08f60",
-           "bytes_per_launch": 80125311}
+TRAFFIC = {"kernel_sha256": "6b83b0807dead0e2cc486b2484f7f5439937199d1be5a7aecd18ea0c850fa9f4",
+           "bytes_per_launch": 80056610}
 WORKLOADS = {
     "nominal": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",
     "uneven": "uneven: 20000 events, Poisson(7.6) x 50 particles, 0-13k hits and 0-600 tracks/event",
