@@ -43,7 +43,10 @@ class Params(ctypes.Structure):
         "xtol_const", "xtol_pscale", "xasym", "uv_halfwidth", "K_first", "K_last",
         "magtol_const", "magtol_pscale", "magtol_txscale", "magtol_min", "magtol_max",
         "p_charge_cut")] + [("C_nhits", ctypes.c_float * 4), ("n_hits_window", ctypes.c_int32),
-                            ("n_triplets", ctypes.c_int32)]
+                            ("n_triplets", ctypes.c_int32), ("velo_only", ctypes.c_int32),
+                            ("noUT_c", ctypes.c_float * 8), ("noUT_p_min", ctypes.c_float),
+                            ("noUT_pt_min", ctypes.c_float), ("noUT_overlap", ctypes.c_float)]
+_ARRAYS = ("C_nhits", "noUT_c")
 
 
 class _Out(ctypes.Structure):
@@ -53,7 +56,7 @@ class _Out(ctypes.Structure):
 
 class _Dbg(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("win", "wx", "counts", "trip", "trip_chi2", "cand_Q",
-                                                "cand_hits")]
+                                                "cand_hits", "win1", "wx1")]
 
 
 def build(force: bool = False) -> str:
@@ -71,6 +74,7 @@ _lib = None
 
 def _bind(lib):
     lib.lfo_default_params.argtypes = [ctypes.POINTER(Params)]
+    lib.lfo_default_params_no_ut.argtypes = [ctypes.POINTER(Params)]
     lib.lfo_find_tracks.restype = ctypes.c_int
     lib.lfo_find_tracks.argtypes = (
         [ctypes.POINTER(Geometry), ctypes.POINTER(Params), ctypes.c_uint32] + [ctypes.c_void_p] * 10
@@ -92,14 +96,16 @@ def _load():
     return _lib
 
 
-def default_params() -> dict:
-    """The oracle's own defaults (paper's Forward tuning plus readings)."""
+def default_params(no_ut: bool = False) -> dict:
+    """The oracle's own defaults: the paper's Forward tuning plus readings, or
+    (no_ut) its Forward no-UT tuning for VELO-only input."""
     p = Params()
-    _load().lfo_default_params(ctypes.byref(p))
+    lib = _load()
+    (lib.lfo_default_params_no_ut if no_ut else lib.lfo_default_params)(ctypes.byref(p))
     d = {}
     for name, _ in Params._fields_:
         v = getattr(p, name)
-        d[name] = list(v) if name == "C_nhits" else v
+        d[name] = list(v) if name in _ARRAYS else v
     return d
 
 
@@ -120,12 +126,16 @@ def make_geometry(world: dict) -> Geometry:
 
 
 def make_params(params: dict | None, lib=None) -> Params:
+    """Defaults (the no-UT column when params has velo_only set) overridden by params."""
     p = Params()
-    (lib or _load()).lfo_default_params(ctypes.byref(p))
+    lib = lib or _load()
+    no_ut = bool((params or {}).get("velo_only", 0))
+    (lib.lfo_default_params_no_ut if no_ut else lib.lfo_default_params)(ctypes.byref(p))
     for k, v in (params or {}).items():
-        if k == "C_nhits":
-            for i in range(4):
-                p.C_nhits[i] = v[i]
+        if k in _ARRAYS:
+            arr = getattr(p, k)
+            for i in range(len(arr)):
+                arr[i] = v[i]
         else:
             setattr(p, k, v)
     return p
@@ -166,8 +176,10 @@ def run(ev, world: dict, params: dict | None = None, events: tuple[int, int] | N
         out["trip_chi2"] = np.full((T, NT), np.nan, np.float32)
         out["cand_Q"] = np.full((T, NT), np.nan, np.float32)
         out["cand_hits"] = np.full((T, NT, NL), -1, np.int32)
+        out["win1"] = np.zeros((T, NL, 2), np.int32)
+        out["wx1"] = np.zeros((T, NL, 3), np.float32)
         d = _Dbg(*[_ptr(out[k]) for k in ("win", "wx", "counts", "trip", "trip_chi2", "cand_Q",
-                                          "cand_hits")])
+                                          "cand_hits", "win1", "wx1")])
     arrs = [np.ascontiguousarray(a) for a in (
         ev.hit_off.astype(np.uint32), ev.hit_x.astype(np.float32), ev.hit_z.astype(np.float32),
         ev.hit_dxdy.astype(np.float32), ev.trk_off.astype(np.uint32), ev.trk_x.astype(np.float32),

@@ -58,6 +58,35 @@ void lfo_default_params(lfo_params *p) {
     p->C_nhits[3] = 0.5f;
 }
 
+void lfo_default_params_no_ut(lfo_params *p) {
+    lfo_default_params(p);
+    /* Table of parameters and tolerances, "Forward no-UT" column. */
+    p->T_triplet = 2.0f;
+    p->T_x = 0.5f;
+    p->T_uv_scale = 15.0f;       /* T_uv = 15 (tx + ty), same floor [R17] */
+    p->T_ty = 0.003f;
+    p->T_y = 800.0f;
+    p->T_Q = 0.5f;
+    p->n_hits_window = 64;
+    p->n_triplets = 20;
+    /* No-UT tuning section: u/v tolerance 1200 mm, magnet x tolerance fixed
+     * at 10 mm, no bend-direction filter (no q/p). */
+    p->uv_halfwidth = 1200.0f;
+    p->magtol_const = 10.0f;
+    p->magtol_pscale = 0.0f;
+    p->magtol_txscale = 0.0f;
+    p->magtol_min = 10.0f;
+    p->magtol_max = 10.0f;
+    p->p_charge_cut = 0.0f;
+    p->velo_only = 1;
+    /* Polynomial coefficients of the curvature tolerance (Tab.Poly). */
+    const float c[8] = {4824.3f, 426.3f, 7071.1f, 12080.4f, 14077.8f, 13909.3f, 9315.3f, 3209.5f};
+    for (int i = 0; i < 8; ++i) p->noUT_c[i] = c[i];
+    p->noUT_p_min = 5.0f;        /* 5 GeV or pt 1 GeV, whichever is tighter [N2] */
+    p->noUT_pt_min = 1.0f;
+    p->noUT_overlap = 5.0f;      /* the text's 5 mm (the figure caption says 1 cm) [N4] */
+}
+
 /* ---------------------------------------------------------------- */
 typedef struct {
     const float *x, *z, *dxdy;     /* event-local hit arrays */
@@ -65,13 +94,15 @@ typedef struct {
     uint32_t end[2 * LFO_NL];
 } event_view;
 
-typedef struct { float chi2; int set, h0, h1, h2; } triplet;
+typedef struct { float chi2; int side, set, h0, h1, h2; } triplet;
 
 static int triplet_cmp(const void *pa, const void *pb) {
     const triplet *a = (const triplet *)pa, *b = (const triplet *)pb;
-    /* [R13] ascending (chi2, set, h0, h2) */
+    /* [R13] ascending (chi2, side, set, h0, h2); side is 0 except with
+     * VELO-only input [N7] */
     if (a->chi2 < b->chi2) return -1;
     if (a->chi2 > b->chi2) return 1;
+    if (a->side != b->side) return a->side < b->side ? -1 : 1;
     if (a->set != b->set) return a->set < b->set ? -1 : 1;
     if (a->h0 != b->h0) return a->h0 < b->h0 ? -1 : 1;
     if (a->h2 != b->h2) return a->h2 < b->h2 ? -1 : 1;
@@ -124,74 +155,116 @@ static void track_one(const lfo_geometry *G, const lfo_params *P, const event_vi
                       float x_in, float y_in, float tx_in, float ty_in, float qop,
                       uint8_t *found, uint8_t *n_out, int32_t *hit_out, float *par_out,
                       int32_t *dbg_win, float *dbg_wx, int64_t *dbg_counts, int32_t *dbg_trip,
-                      float *dbg_trip_chi2, float *dbg_candQ, int32_t *dbg_cand_hits) {
+                      float *dbg_trip_chi2, float *dbg_candQ, int32_t *dbg_cand_hits,
+                      int32_t *dbg_win1, float *dbg_wx1) {
     const int NT = P->n_triplets;
     *found = 0;
     *n_out = 0;
     for (int l = 0; l < LFO_NL; ++l) hit_out[l] = -1;
     for (int k = 0; k < 7; ++k) par_out[k] = 0.0f;
 
-    /* ---- Kinematics [R2][R3]: the y-slope picks the detector half. ---- */
-    float p = 1.0f / fabsf(qop);
-    int q = qop > 0.0f ? 1 : -1;
+    /* ---- Kinematics [R2][R3]: the y-slope picks the detector half.  With
+     *      VELO-only input the momentum is the assumed minimum: the tighter
+     *      (larger) of noUT_p_min and the momentum at which the track's
+     *      transverse momentum is noUT_pt_min [N2]. ---- */
+    const int velo = P->velo_only != 0;
+    float p;
+    int q = 0;
+    if (velo) {
+        float t2 = tx_in * tx_in + ty_in * ty_in;
+        float sin_t = sqrtf(t2 / (1.0f + t2));
+        float p_pt = sin_t > 0.0f ? P->noUT_pt_min / sin_t : 0.0f;
+        p = p_pt > P->noUT_p_min ? p_pt : P->noUT_p_min;
+    } else {
+        p = 1.0f / fabsf(qop);
+        q = qop > 0.0f ? 1 : -1;
+    }
     int zone = ty_in >= 0.0f ? 1 : 0;
 
-    /* ---- pt-kick extrapolation to every layer [R1]: straight to the
-     *      bending plane, kick dtx = kick*q/p, then the post-magnet model. ---- */
+    /* ---- Extrapolation to every layer.  VELO-UT input: the pt-kick model
+     *      [R1], straight to the bending plane, kick dtx = kick*q/p, then the
+     *      post-magnet model.  VELO input: a straight line [N1]. ---- */
     float x_mag = x_in + tx_in * (G->z_mag - G->z_in);
-    float dtx = G->kick * qop;
-    float T = tx_in + dtx;
-    float kd = G->kappa * dtx;
     float x_ext[LFO_NL], y_ext[LFO_NL];
-    for (int l = 0; l < LFO_NL; ++l) {
-        float dz = G->z[l] - G->z_mag;
-        float dzT = G->z[l] - G->z_T;
-        x_ext[l] = x_mag + T * dz + kd * dzT * dzT;
-        y_ext[l] = y_in + ty_in * (G->z[l] - G->z_in);
+    if (velo) {
+        for (int l = 0; l < LFO_NL; ++l) x_ext[l] = x_in + tx_in * (G->z[l] - G->z_in);
+    } else {
+        float dtx = G->kick * qop;
+        float T = tx_in + dtx;
+        float kd = G->kappa * dtx;
+        for (int l = 0; l < LFO_NL; ++l) {
+            float dz = G->z[l] - G->z_mag;
+            float dzT = G->z[l] - G->z_T;
+            x_ext[l] = x_mag + T * dz + kd * dzT * dzT;
+        }
     }
+    for (int l = 0; l < LFO_NL; ++l) y_ext[l] = y_in + ty_in * (G->z[l] - G->z_in);
 
     /* ---- Step 1: search windows (x_min/x_max; u/v straight line +-800 mm;
-     *      at most n_hits_window hits, symmetric around the centre). ---- */
+     *      at most n_hits_window hits, symmetric around the centre).  With
+     *      VELO-only input every layer has two windows, side 0 for bending
+     *      towards -x and side 1 towards +x: [x_ext - tol, x_ext + overlap]
+     *      and [x_ext - overlap, x_ext + tol], tol the momentum polynomial on
+     *      x layers and uv_halfwidth on u/v layers, centred for the cap on
+     *      the middle of each window [N3]-[N6]. ---- */
+    const int NS = velo ? 2 : 1;
     float xtol = P->xtol_const + P->xtol_pscale / p;          /* [R4] */
+    if (velo) {                                                /* [N3] */
+        const float *c8 = P->noUT_c;
+        float ip = 1.0f / p;
+        float ty2 = ty_in * ty_in;
+        xtol = ip * (c8[0] + tx_in * (c8[1] + c8[2] * tx_in) + ty2 * (c8[3] + tx_in * (c8[4] + c8[5] * tx_in)) +
+                     ip * (c8[6] * tx_in + c8[7] * ip));
+    }
     float asymL = 0.0f, asymR = 0.0f;                          /* [R5] */
     if (q * G->polarity > 0) asymR = P->xasym; else asymL = P->xasym;
-    int wfirst[LFO_NL], wlast[LFO_NL];
-    for (int l = 0; l < LFO_NL; ++l) {
-        float xc, xmin, xmax;
-        if (is_uv(l)) {                                         /* [R6] */
-            xc = x_ext[l] - G->dxdy[l] * y_ext[l];
-            xmin = xc - P->uv_halfwidth;
-            xmax = xc + P->uv_halfwidth;
-        } else {
-            xc = x_ext[l];
-            xmin = xc - xtol - asymL;
-            xmax = xc + xtol + asymR;
+    int wfirst[2][LFO_NL], wlast[2][LFO_NL];
+    for (int sd = 0; sd < NS; ++sd) {
+        for (int l = 0; l < LFO_NL; ++l) {
+            float xc, xmin, xmax;
+            if (velo) {
+                float x0 = is_uv(l) ? x_ext[l] - G->dxdy[l] * y_ext[l] : x_ext[l];
+                float tol = is_uv(l) ? P->uv_halfwidth : xtol;
+                if (sd == 0) { xmin = x0 - tol; xmax = x0 + P->noUT_overlap; }
+                else { xmin = x0 - P->noUT_overlap; xmax = x0 + tol; }
+                xc = 0.5f * (xmin + xmax);
+            } else if (is_uv(l)) {                              /* [R6] */
+                xc = x_ext[l] - G->dxdy[l] * y_ext[l];
+                xmin = xc - P->uv_halfwidth;
+                xmax = xc + P->uv_halfwidth;
+            } else {
+                xc = x_ext[l];
+                xmin = xc - xtol - asymL;
+                xmax = xc + xtol + asymR;
+            }
+            int b = 2 * l + zone;
+            int begin = (int)ev->begin[b], end = (int)ev->end[b];
+            /* [R7] closed interval by counting over the sorted bucket */
+            int lo = begin, hi = begin, c = begin;
+            for (int i = begin; i < end; ++i) {
+                if (ev->x[i] < xmin) ++lo;
+                if (ev->x[i] <= xmax) ++hi;
+                if (ev->x[i] < xc) ++c;
+            }
+            if (hi < lo) hi = lo;
+            if (c < lo) c = lo;
+            if (c > hi) c = hi;
+            int N = P->n_hits_window;
+            if (hi - lo > N) {                                 /* [R8] */
+                int first = c - N / 2;
+                if (first < lo) first = lo;
+                if (first > hi - N) first = hi - N;
+                wfirst[sd][l] = first;
+                wlast[sd][l] = first + N;
+            } else {
+                wfirst[sd][l] = lo;
+                wlast[sd][l] = hi;
+            }
+            int32_t *dw = sd == 0 ? dbg_win : dbg_win1;
+            float *dx = sd == 0 ? dbg_wx : dbg_wx1;
+            if (dw) { dw[2 * l] = wfirst[sd][l]; dw[2 * l + 1] = wlast[sd][l]; }
+            if (dx) { dx[3 * l] = xmin; dx[3 * l + 1] = xc; dx[3 * l + 2] = xmax; }
         }
-        int b = 2 * l + zone;
-        int begin = (int)ev->begin[b], end = (int)ev->end[b];
-        /* [R7] closed interval by counting over the sorted bucket */
-        int lo = begin, hi = begin, c = begin;
-        for (int i = begin; i < end; ++i) {
-            if (ev->x[i] < xmin) ++lo;
-            if (ev->x[i] <= xmax) ++hi;
-            if (ev->x[i] < xc) ++c;
-        }
-        if (hi < lo) hi = lo;
-        if (c < lo) c = lo;
-        if (c > hi) c = hi;
-        int N = P->n_hits_window;
-        if (hi - lo > N) {                                     /* [R8] */
-            int first = c - N / 2;
-            if (first < lo) first = lo;
-            if (first > hi - N) first = hi - N;
-            wfirst[l] = first;
-            wlast[l] = first + N;
-        } else {
-            wfirst[l] = lo;
-            wlast[l] = hi;
-        }
-        if (dbg_win) { dbg_win[2 * l] = wfirst[l]; dbg_win[2 * l + 1] = wlast[l]; }
-        if (dbg_wx) { dbg_wx[3 * l] = xmin; dbg_wx[3 * l + 1] = xc; dbg_wx[3 * l + 2] = xmax; }
     }
 
     /* ---- Step 2: triplet seeding. ---- */
@@ -199,18 +272,19 @@ static void track_one(const lfo_geometry *G, const lfo_params *P, const event_vi
     size_t cap = 64, ntrip = 0;
     triplet *trips = (triplet *)malloc(cap * sizeof(triplet));
     if (!trips) return;
+    for (int sd = 0; sd < NS; ++sd)   /* VELO input: each charge assumption on its own [N7] */
     for (int s = 0; s < 2; ++s) {
         int l0 = SEED_SETS[s][0], l1 = SEED_SETS[s][1], l2 = SEED_SETS[s][2];
         float K = s == 0 ? P->K_first : P->K_last;
-        for (int i0 = wfirst[l0]; i0 < wlast[l0]; ++i0) {
-            for (int i2 = wfirst[l2]; i2 < wlast[l2]; ++i2) {
+        for (int i0 = wfirst[sd][l0]; i0 < wlast[sd][l0]; ++i0) {
+            for (int i2 = wfirst[sd][l2]; i2 < wlast[sd][l2]; ++i2) {
                 ++n_pairs;
                 float x0 = ev->x[i0], z0 = ev->z[i0];
                 float x2 = ev->x[i2], z2 = ev->z[i2];
                 float txd = (x2 - x0) / (z2 - z0);
                 /* doublet filter 1: below p_charge_cut the bending from the
                  * upstream track to the doublet must follow the charge [R9] */
-                if (p < P->p_charge_cut && !((txd - tx_in) * qop > 0.0f)) continue;
+                if (!velo && p < P->p_charge_cut && !((txd - tx_in) * qop > 0.0f)) continue;
                 /* doublet filter 2: x opening at the bending plane [R10] */
                 float xm = x0 + txd * (G->z_mag - z0);
                 float tol = P->magtol_const + P->magtol_pscale / p + P->magtol_txscale * fabsf(txd);
@@ -221,7 +295,7 @@ static void track_one(const lfo_geometry *G, const lfo_params *P, const event_vi
                 /* middle hit: straight line corrected by K [R11] */
                 float x1e = G->z[l1] * txd + (x0 - txd * z0) * K;
                 float d;
-                int i1 = closest_x(ev, wfirst[l1], wlast[l1], x1e, &d);
+                int i1 = closest_x(ev, wfirst[sd][l1], wlast[sd][l1], x1e, &d);
                 if (i1 < 0 || !(d * d < P->T_triplet)) continue;
                 if (ntrip == cap) {
                     cap *= 2;
@@ -229,7 +303,7 @@ static void track_one(const lfo_geometry *G, const lfo_params *P, const event_vi
                     if (!nt) { free(trips); return; }
                     trips = nt;
                 }
-                triplet t = {d * d, s, i0, i1, i2};
+                triplet t = {d * d, sd, s, i0, i1, i2};
                 trips[ntrip++] = t;
             }
         }
@@ -239,7 +313,10 @@ static void track_one(const lfo_geometry *G, const lfo_params *P, const event_vi
     for (int r = 0; r < NT; ++r) {
         if (dbg_trip) {
             int32_t *o = dbg_trip + 4 * r;
-            if (r < nkeep) { o[0] = trips[r].set; o[1] = trips[r].h0; o[2] = trips[r].h1; o[3] = trips[r].h2; }
+            if (r < nkeep) {
+                o[0] = trips[r].set + 2 * trips[r].side;
+                o[1] = trips[r].h0; o[2] = trips[r].h1; o[3] = trips[r].h2;
+            }
             else { o[0] = o[1] = o[2] = o[3] = -1; }
         }
         if (dbg_trip_chi2) dbg_trip_chi2[r] = r < nkeep ? trips[r].chi2 : NAN;
@@ -282,7 +359,7 @@ static void track_one(const lfo_geometry *G, const lfo_params *P, const event_vi
             float u = G->z[l] - G->z_ref;
             float xe = a + b * u + c * g_of(u, G->dRatio);
             float d;
-            int i = closest_x(ev, wfirst[l], wlast[l], xe, &d);
+            int i = closest_x(ev, wfirst[t->side][l], wlast[t->side][l], xe, &d);
             if (i >= 0 && d * d < P->T_x) hits[l] = i;
         }
         /* extension to the u/v layers, slope-dependent tolerance [R16][R17] */
@@ -291,7 +368,7 @@ static void track_one(const lfo_geometry *G, const lfo_params *P, const event_vi
             float u = G->z[l] - G->z_ref;
             float xp = a + b * u + c * g_of(u, G->dRatio);
             float d;
-            int i = closest_uv(ev, wfirst[l], wlast[l], xp, y_ext[l], &d);
+            int i = closest_uv(ev, wfirst[t->side][l], wlast[t->side][l], xp, y_ext[l], &d);
             if (i >= 0 && d * d < T_uv) hits[l] = i;
         }
         if (dbg_cand_hits) memcpy(dbg_cand_hits + r * LFO_NL, hits, sizeof(hits));
@@ -463,7 +540,9 @@ int lfo_find_tracks(const lfo_geometry *g, const lfo_params *P, uint32_t n_event
                       dbg && dbg->trip ? dbg->trip + (size_t)t * NT * 4 : NULL,
                       dbg && dbg->trip_chi2 ? dbg->trip_chi2 + (size_t)t * NT : NULL,
                       dbg && dbg->cand_Q ? dbg->cand_Q + (size_t)t * NT : NULL,
-                      dbg && dbg->cand_hits ? dbg->cand_hits + (size_t)t * NT * LFO_NL : NULL);
+                      dbg && dbg->cand_hits ? dbg->cand_hits + (size_t)t * NT * LFO_NL : NULL,
+                      dbg && dbg->win1 ? dbg->win1 + (size_t)t * 24 : NULL,
+                      dbg && dbg->wx1 ? dbg->wx1 + (size_t)t * 36 : NULL);
             out->a[t] = par[0];
             out->b[t] = par[1];
             out->c[t] = par[2];

@@ -47,6 +47,15 @@ typedef struct {
     float C_nhits[4];     /* C(9), C(10), C(11), C(12) */
     int32_t n_hits_window;
     int32_t n_triplets;   /* <= LFO_MAX_TRIPLETS */
+    /* No-UT tuning: VELO input tracks without q/p, extrapolated as straight
+     * lines, an assumed minimum momentum, double-sided windows (one per
+     * charge assumption) and seeding per side.  uv_halfwidth is then the
+     * stereo-window tolerance and the Tab.Tol no-UT column applies. */
+    int32_t velo_only;    /* 0: VELO-UT input (q/p used); 1: VELO input (q/p ignored) */
+    float noUT_c[8];      /* x_tol polynomial coefficients c0..c7 (Tab.Poly) */
+    float noUT_p_min;     /* assumed minimum momentum, GeV */
+    float noUT_pt_min;    /* assumed minimum transverse momentum, GeV */
+    float noUT_overlap;   /* overlap of the two windows of a layer, mm */
 } lfo_params;
 
 /* One result slot per input track.  hit_idx is event-local (index into the
@@ -59,16 +68,20 @@ typedef struct {
 
 /* Optional intermediate dumps (any pointer may be NULL). */
 typedef struct {
-    int32_t *win;          /* [n_tracks * 24]: event-local [first, last) per layer */
-    float *wx;             /* [n_tracks * 36]: x_min, centre, x_max per layer */
+    int32_t *win;          /* [n_tracks * 24]: event-local [first, last) per layer (side 0 when velo_only) */
+    float *wx;             /* [n_tracks * 36]: x_min, centre, x_max per layer (side 0 when velo_only) */
     int64_t *counts;       /* [n_tracks * 4]: doublet pairs, filtered doublets, triplets, valid candidates */
-    int32_t *trip;         /* [n_tracks * n_triplets * 4]: set, h0, h1, h2 (rank order; -1 padded) */
+    int32_t *trip;         /* [n_tracks * n_triplets * 4]: set + 2*side, h0, h1, h2 (rank order; -1 padded) */
     float *trip_chi2;      /* [n_tracks * n_triplets] */
     float *cand_Q;         /* [n_tracks * n_triplets]: Q of each candidate, NaN if rejected earlier */
     int32_t *cand_hits;    /* [n_tracks * n_triplets * 12]: hits after extension, -1 = none */
+    int32_t *win1;         /* [n_tracks * 24]: side 1 windows (velo_only) */
+    float *wx1;            /* [n_tracks * 36]: side 1 x_min, centre, x_max (velo_only) */
 } lfo_debug;
 
 void lfo_default_params(lfo_params *p);
+/* The "Forward no-UT" tuning: VELO-only input and its tolerances. */
+void lfo_default_params_no_ut(lfo_params *p);
 
 /* Runs events [ev_begin, ev_end) of the batch.  Arrays are the whole batch:
  * hit_off[24*n_events+1] (bucket = 24*event + 2*layer + zone), hits sorted

@@ -662,8 +662,228 @@ def pin_nine_hit_tracks(lib=None):
     assert n >= 3, n
 
 
+# ------------------------------------------------------------------ no-UT tuning
+NU = {"velo_only": 1}   # the Forward no-UT column (oracle.make_params picks its defaults)
+GOLDEN_NO_UT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_constants_no_ut.txt")
+
+
+@functools.lru_cache(maxsize=None)
+def ev_noise_free_wide(seed: int = 21):
+    """Noise-free single-event geometry over a wide momentum range (1-60 GeV)."""
+    return lfgen.generate("single", seed=seed, sigma_x=0.0, qop_sigma=0.0, hit_eff=1.0, n_noise=0,
+                          p_min=1.0, p_max=60.0, n_particles=120)
+
+
+def _bend(p: float, q: float, z: float) -> float:
+    """x displacement of the toy-field trajectory from its upstream straight line (float64)."""
+    dtx = W["kick"] * q / p
+    return dtx * (z - W["z_mag"]) + W["kappa"] * dtx * (z - W["z_T"]) ** 2
+
+
+def _pt(p: float, tx: float, ty: float) -> float:
+    t2 = tx * tx + ty * ty
+    return p * math.sqrt(t2 / (1.0 + t2))
+
+
+def pin_no_ut_constants(lib=None):
+    """The no-UT defaults equal the values the paper prints (Tab.Tol no-UT
+    column, the polynomial coefficients, the No-UT tuning text)."""
+    gold = {}
+    with open(GOLDEN_NO_UT) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                head = line.split("|")[0].split()
+                gold[head[0]] = float(head[1])
+    p = oracle.make_params(NU, lib)
+    for k, v in gold.items():
+        got = p.noUT_c[int(k[6:])] if k.startswith("noUT_c") else getattr(p, k)
+        assert got == f32(v), f"{k}: oracle no-UT default {got} != paper {v}"
+
+
+def pin_no_ut_containment(lib=None):
+    """VELO-only input on noise-free tracks: above both momentum thresholds
+    (p > 5.5 GeV, pt > 1.1 GeV) the true hit of every layer up to z = 9200 mm
+    lies inside the window of the track's own charge side, and a hit bent by
+    more than the 5 mm overlap never lies inside the other side's window."""
+    ev = ev_noise_free_wide()
+    o = oracle.run(ev, W, NU, debug=True, lib=lib)
+    base = ev.event_hit_base()
+    n_in = n_out = 0
+    for t in range(ev.n_tracks):
+        p, q, tx, ty = particle(ev, t)
+        own = 1 if q * W["polarity"] > 0 else 0
+        wx_own = o["wx1"] if own else o["wx"]
+        wx_other = o["wx"] if own else o["wx1"]
+        for l in range(NL):
+            h = truth_hit(ev, t, l)
+            if h < 0:
+                continue
+            x = float(ev.hit_x[base[0] + h])
+            if p > 5.5 and _pt(p, tx, ty) > 1.1 and W["z"][l] < 9200.0:
+                assert wx_own[t, l, 0] <= x <= wx_own[t, l, 2], (t, l, p, x, wx_own[t, l])
+                n_in += 1
+            if abs(_bend(p, q, W["z"][l])) > 5.0 + 1.0:
+                assert not (wx_other[t, l, 0] <= x <= wx_other[t, l, 2]), (t, l, p, x, wx_other[t, l])
+                n_out += 1
+    assert n_in > 200 and n_out > 500, (n_in, n_out)
+
+
+def pin_no_ut_low_pt_excluded(lib=None):
+    """The window assumes the tighter momentum threshold: a track with p < 30
+    GeV and pt < 0.55 GeV bends at the first layer (1.2 GeV x 2626 mm / p)
+    beyond the widest tolerance its slopes allow (below 5,100 mm GeV x pt / p),
+    so none of its true hits is in a window and it is never found."""
+    ev = ev_noise_free_wide()
+    o = oracle.run(ev, W, NU, lib=lib)
+    m = truth.match(ev, o)
+    n = 0
+    for t in range(ev.n_tracks):
+        p, q, tx, ty = particle(ev, t)
+        if p < 30.0 and _pt(p, tx, ty) < 0.55:
+            assert not (m[t] >= 0 and m[t] == int(ev.trk_pid[t])), (t, p, _pt(p, tx, ty))
+            n += 1
+    assert n >= 3, n
+
+
+def pin_no_ut_physics(lib=None):
+    """VELO-only input: noise-free tracks above the thresholds (p > 5.5 GeV,
+    pt > 1.1 GeV) are found (>= 90%) with the right charge and q/p within
+    1e-4 from the pt-kick of the fit; on the single-event workload the same
+    tracks are found with q/p resolution below 1%."""
+    for ev, tol in ((ev_noise_free_wide(), 1e-4), (ev_single(), 0.01)):
+        o = oracle.run(ev, W, NU, lib=lib)
+        m = truth.match(ev, o)
+        sel = found = 0
+        rel = []
+        for t in range(ev.n_tracks):
+            if int(ev.trk_pid[t]) < 0:
+                continue
+            p, q, tx, ty = particle(ev, t)
+            if not (p > 5.5 and _pt(p, tx, ty) > 1.1):
+                continue
+            sel += 1
+            if m[t] == int(ev.trk_pid[t]):
+                found += 1
+                assert np.sign(o["qop"][t]) == np.sign(q), t
+                rel.append(float(o["qop"][t]) * p / q - 1.0)
+        assert sel >= 10 and found >= 0.9 * sel, (sel, found)
+        assert math.sqrt(np.mean(np.square(rel))) < tol, (tol, rel)
+
+
+def _bruteforce_no_ut(ev, t, P, NT):
+    """Exhaustive triplets for VELO input when both windows of every layer
+    span the whole bucket: each side's enumeration is the same list, so the
+    kept triplets come in (side 0, side 1) copies of equal chi2."""
+    e = int(ev.track_event()[t])
+    base = int(ev.hit_off[24 * e])
+    X, Z = ev.hit_x, ev.hit_z
+    x_in, tx_in, ty_in = f32(ev.trk_x[t]), f32(ev.trk_tx[t]), f32(ev.trk_ty[t])
+    zone = 1 if ty_in >= 0 else 0
+    x_mag = x_in + tx_in * (f32(W["z_mag"]) - f32(W["z_in"]))
+    one = []
+    for s, (l0, l1, l2) in enumerate(SEED_SETS):
+        K = f32(P["K_first"] if s == 0 else P["K_last"])
+        b = [24 * e + 2 * l + zone for l in (l0, l1, l2)]
+        r0 = range(int(ev.hit_off[b[0]]), int(ev.hit_off[b[0] + 1]))
+        r1 = range(int(ev.hit_off[b[1]]), int(ev.hit_off[b[1] + 1]))
+        r2 = range(int(ev.hit_off[b[2]]), int(ev.hit_off[b[2] + 1]))
+        for i0 in r0:
+            for i2 in r2:
+                x0, z0, x2, z2 = X[i0], Z[i0], X[i2], Z[i2]
+                txd = (x2 - x0) / (z2 - z0)
+                xm = x0 + txd * (f32(W["z_mag"]) - z0)
+                if not abs(xm - x_mag) < f32(P["magtol_max"]):
+                    continue
+                x1e = f32(W["z"][l1]) * txd + (x0 - txd * z0) * K
+                d = [abs(X[i1] - x1e) for i1 in r1]
+                if not d:
+                    continue
+                k = int(np.argmin(d))
+                if d[k] * d[k] < f32(P["T_triplet"]):
+                    one.append((float(d[k] * d[k]), s, i0 - base, r1[k] - base, i2 - base))
+    out = [(c, sd, s, h0, h1, h2) for sd in (0, 1) for (c, s, h0, h1, h2) in one]
+    out.sort(key=lambda r: (r[0], r[1], r[2], r[3], r[5]))
+    return out[:NT], len(out)
+
+
+def pin_no_ut_bruteforce(lib=None):
+    """VELO input with both windows of every layer spanning the whole bucket:
+    the windowed, per-side search keeps exactly the top-n of an exhaustive
+    enumeration ordered by (chi2, side, set, h0, h2)."""
+    ev = ev_tiny()
+    NT = 3
+    big = dict(NU, noUT_c=[1e9] * 8, noUT_overlap=1e7, uv_halfwidth=1e7, n_hits_window=64, n_triplets=NT,
+               T_triplet=40.0, magtol_const=40.0, magtol_min=40.0, magtol_max=40.0)
+    P = oracle.default_params(no_ut=True)
+    P.update(big)
+    o = oracle.run(ev, W, params=big, debug=True, lib=lib)
+    n_cut = 0
+    for t in range(ev.n_tracks):
+        ref, n_all = _bruteforce_no_ut(ev, t, P, NT)
+        got = []
+        for r in range(NT):
+            tr = o["trip"][t, r]
+            if tr[0] >= 0:
+                got.append((float(o["trip_chi2"][t, r]), int(tr[0]) // 2, int(tr[0]) % 2, int(tr[1]), int(tr[2]),
+                            int(tr[3])))
+        assert len(got) == len(ref), (t, got, ref)
+        for g, r in zip(got, ref):
+            assert g[1:] == r[1:] and f32(g[0]) == f32(r[0]), (t, g, r)
+        assert int(o["counts"][t, 2]) == n_all
+        n_cut += n_all > NT
+    assert n_cut > 0
+
+
+def pin_no_ut_window_formula(lib=None):
+    """Consistency check (a float64 re-evaluation of the no-UT window
+    equations, not an independent pin): assumed momentum, polynomial
+    tolerance, both windows and their centres, every layer and track."""
+    ev = ev_single()
+    o = oracle.run(ev, W, NU, debug=True, lib=lib)
+    c = [4824.3, 426.3, 7071.1, 12080.4, 14077.8, 13909.3, 9315.3, 3209.5]
+    for t in range(ev.n_tracks):
+        x_in, y_in, tx, ty = (float(v[t]) for v in (ev.trk_x, ev.trk_y, ev.trk_tx, ev.trk_ty))
+        t2 = tx * tx + ty * ty
+        s = math.sqrt(t2 / (1 + t2))
+        p = max(5.0, 1.0 / s if s > 0 else 0.0)
+        ip = 1.0 / p
+        xtol = ip * (c[0] + tx * (c[1] + c[2] * tx) + ty * ty * (c[3] + tx * (c[4] + c[5] * tx))
+                     + ip * (c[6] * tx + c[7] * ip))
+        for l in range(NL):
+            xe = x_in + tx * (W["z"][l] - W["z_in"])
+            ye = y_in + ty * (W["z"][l] - W["z_in"])
+            x0 = xe - W["dxdy"][l] * ye if l in UV_LAYERS else xe
+            tol = 1200.0 if l in UV_LAYERS else xtol
+            for wx, (lo, hi) in ((o["wx"], (x0 - tol, x0 + 5.0)), (o["wx1"], (x0 - 5.0, x0 + tol))):
+                for k, v in enumerate((lo, 0.5 * (lo + hi), hi)):
+                    assert abs(float(wx[t, l, k]) - v) < 2e-3 + 1e-6 * abs(v), (t, l, k, wx[t, l], v)
+
+
+def pin_no_ut_invariants(lib=None):
+    """VELO-only outputs: every found track's hits lie in one side's windows,
+    9..12 hits with a u/v hit per station, Q < T_Q and |ty - ty_in| < 0.003."""
+    for ev in (ev_nominal(1), ev_single()):
+        o = oracle.run(ev, W, NU, debug=True, lib=lib)
+        assert o["found"].sum() > 0
+        for t in np.nonzero(o["found"])[0]:
+            hits = o["hit_idx"][t]
+            n = int((hits >= 0).sum())
+            assert n == int(o["n_hits"][t]) and 9 <= n <= 12
+            for st in range(3):
+                assert hits[4 * st + 1] >= 0 or hits[4 * st + 2] >= 0
+            sides = [all(w[t, l, 0] <= hits[l] < w[t, l, 1] for l in range(NL) if hits[l] >= 0)
+                     for w in (o["win"], o["win1"])]
+            assert any(sides), t
+            assert o["Q"][t] < 0.5
+            assert abs(float(o["ty"][t]) - float(ev.trk_ty[t])) < 0.003 + 1e-7
+
+
+NO_UT_PINS = [pin_no_ut_constants, pin_no_ut_containment, pin_no_ut_low_pt_excluded, pin_no_ut_physics,
+              pin_no_ut_bruteforce, pin_no_ut_window_formula, pin_no_ut_invariants]
+
 ALL_PINS = [pin_constants, pin_extrapolation_noise_free, pin_window_bounds, pin_window_search,
             pin_window_edges_closed, pin_triplet_closed_form, pin_magnet_threshold,
             pin_charge_filter, pin_bruteforce_triplets, pin_fit_noise_free, pin_fit_lstsq,
             pin_y_fit_recovers_slope, pin_physics_single, pin_invariants, pin_batch_independence,
-            pin_tie_breaks, pin_extension_rule, pin_nine_hit_tracks]
+            pin_tie_breaks, pin_extension_rule, pin_nine_hit_tracks] + NO_UT_PINS

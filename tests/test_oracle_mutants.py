@@ -62,6 +62,17 @@ MUTANTS = [
      "if (hits[4 * st + 1] < 0 || hits[4 * st + 2] < 0) st_ok = 0;"),
     ("min_hits_10", "if (n < 9 || !st_ok) continue;", "if (n < 10 || !st_ok) continue;"),
     ("best_highest_Q", "if (best_rank < 0 || Q < best_Q) {", "if (best_rank < 0 || Q > best_Q) {"),
+    # no-UT tuning (VELO-only input)
+    ("noUT_side_swap", "if (sd == 0) { xmin = x0 - tol; xmax = x0 + P->noUT_overlap; }",
+     "if (sd == 1) { xmin = x0 - tol; xmax = x0 + P->noUT_overlap; }"),
+    ("noUT_pt_threshold_ignored", "p = p_pt > P->noUT_p_min ? p_pt : P->noUT_p_min;", "p = P->noUT_p_min;"),
+    ("noUT_extrapolation_origin", "x_ext[l] = x_in + tx_in * (G->z[l] - G->z_in);",
+     "x_ext[l] = x_in + tx_in * (G->z[l] - G->z_mag);"),
+    ("noUT_overlap_sign", "else { xmin = x0 - P->noUT_overlap; xmax = x0 + tol; }",
+     "else { xmin = x0 + P->noUT_overlap; xmax = x0 + tol; }"),
+    ("noUT_poly_c7", "ip * (c8[6] * tx_in + c8[7] * ip)", "ip * (c8[6] * tx_in + c8[7])"),
+    ("noUT_centre_edge", "xc = 0.5f * (xmin + xmax);", "xc = xmin;"),
+    ("noUT_uv_tol_as_x", "float tol = is_uv(l) ? P->uv_halfwidth : xtol;", "float tol = xtol;"),
 ]
 
 
