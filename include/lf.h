@@ -126,6 +126,21 @@ typedef struct {
     float C_nhits[4];      /* C(9), C(10), C(11), C(12): 5.0, 1.0, 0.8, 0.5 */
     int32_t n_hits_window; /* hits kept per window (1..64), 32 */
     int32_t n_triplets;    /* triplets kept per input track (1..32), 12 */
+    /* No-UT tuning (arXiv 2402.14670, "No-UT tuning" subsection): VELO input
+     * tracks without a momentum.  velo_only = 1 ignores trk_qop, extrapolates
+     * each track as a straight line, assumes the momentum
+     * p = max(noUT_p_min, noUT_pt_min / sin(theta)), and gives every layer
+     * two windows, [x - tol, x + overlap] and [x - overlap, x + tol], one per
+     * charge, with tol the polynomial below on x layers (the paper's window
+     * tolerance equation, coefficients c0..c7 of its table) and uv_halfwidth
+     * on u/v layers; each charge side seeds its own triplets and the n_triplets
+     * best of both go on.  lf_default_params_no_ut() fills the paper's
+     * "Forward no-UT" column. */
+    int32_t velo_only;     /* 0: VELO-UT input (default); 1: VELO-only input */
+    float noUT_c[8];       /* x_tol polynomial coefficients, mm GeV^k */
+    float noUT_p_min;      /* assumed minimum momentum, GeV: 5 */
+    float noUT_pt_min;     /* assumed minimum transverse momentum, GeV: 1 */
+    float noUT_overlap;    /* overlap of the two windows of a layer, mm: 5 */
 } lf_params;
 
 /* A batch of events in host memory, ragged structure-of-arrays.  Hits are
@@ -166,6 +181,15 @@ typedef struct {
 
 /* Fills *p with the default parameters. */
 void lf_default_params(lf_params *p);
+
+/* Fills *p with the "Forward no-UT" parameters (velo_only = 1): T_triplet 2,
+ * T_x 0.5, T_uv 15 (|tx| + |ty|) with the same floor, T_ty 0.003, T_y 800,
+ * T_Q 0.5, 64 hits per window, 20 triplets, u/v tolerance 1200 mm, magnet
+ * tolerance fixed at 10 mm, no bend-direction filter, the polynomial
+ * coefficients 4824.3, 426.3, 7071.1, 12080.4, 14077.8, 13909.3, 9315.3,
+ * 3209.5, p_min 5 GeV, pt_min 1 GeV, overlap 5 mm.  For the callers that
+ * run VELO-only input, as the paper's 2022 trigger did. */
+void lf_default_params_no_ut(lf_params *p);
 
 /* Creates a context on the current HIP device.  Geometry and parameters are
  * copied.  device_budget_bytes bounds the device memory of all resident

@@ -73,6 +73,14 @@ int check_params(const lf_geometry *g, const lf_params *p, std::string &why) {
                         p->magtol_const, p->magtol_pscale, p->magtol_txscale, p->magtol_min, p->magtol_max,
                         p->p_charge_cut, p->C_nhits[0], p->C_nhits[1], p->C_nhits[2], p->C_nhits[3]};
     for (float v : ps) if (std::isnan(v)) { why = "params: NaN value"; return 0; }
+    if (p->velo_only != 0 && p->velo_only != 1) { why = "params: velo_only must be 0 or 1"; return 0; }
+    for (int i = 0; i < 8; ++i)
+        if (!finitef(p->noUT_c[i])) { why = "params: non-finite no-UT polynomial coefficient"; return 0; }
+    if (!finitef(p->noUT_p_min) || !finitef(p->noUT_pt_min) || !finitef(p->noUT_overlap)) {
+        why = "params: non-finite no-UT momentum threshold or overlap";
+        return 0;
+    }
+    if (p->velo_only && !(p->noUT_p_min > 0.0f)) { why = "params: velo_only needs noUT_p_min > 0"; return 0; }
     return 1;
 }
 
@@ -89,6 +97,9 @@ lfk::KParams to_kparams(const lf_geometry &g, const lf_params &p) {
     k.magtol_min = p.magtol_min; k.magtol_max = p.magtol_max; k.p_charge_cut = p.p_charge_cut;
     for (int i = 0; i < 4; ++i) k.C_nhits[i] = p.C_nhits[i];
     k.n_hits_window = p.n_hits_window; k.n_triplets = p.n_triplets;
+    k.velo_only = p.velo_only;
+    for (int i = 0; i < 8; ++i) k.noUT_c[i] = p.noUT_c[i];
+    k.noUT_p_min = p.noUT_p_min; k.noUT_pt_min = p.noUT_pt_min; k.noUT_overlap = p.noUT_overlap;
     return k;
 }
 
@@ -157,6 +168,7 @@ namespace lfapi {
 int ctx_fail(lf_ctx *c, int code, const std::string &msg) { return fail(c, code, msg); }
 const lfk::KParams *ctx_dparams(const lf_ctx *c) { return c->d_params; }
 int ctx_nhits_window(const lf_ctx *c) { return c->params.n_hits_window; }
+int ctx_sides(const lf_ctx *c) { return c->params.velo_only ? 2 : 1; }
 const lfk::ExecCfg &ctx_exec(const lf_ctx *c) { return c->exec; }
 int check_batch(const lf_batch *b, std::string &why) { return validate(b, why); }
 }  // namespace lfapi
@@ -198,6 +210,35 @@ void lf_default_params(lf_params *p) {
     p->C_nhits[3] = 0.5f;
 }
 
+void lf_default_params_no_ut(lf_params *p) {
+    if (!p) return;
+    lf_default_params(p);
+    // Table of parameters and tolerances, "Forward no-UT" column.
+    p->T_triplet = 2.0f;
+    p->T_x = 0.5f;
+    p->T_uv_scale = 15.0f;
+    p->T_ty = 0.003f;
+    p->T_y = 800.0f;
+    p->T_Q = 0.5f;
+    p->n_hits_window = 64;
+    p->n_triplets = 20;
+    // No-UT tuning: u/v tolerance 1200 mm, magnet tolerance fixed at 10 mm,
+    // no q/p for the bend-direction filter.
+    p->uv_halfwidth = 1200.0f;
+    p->magtol_const = 10.0f;
+    p->magtol_pscale = 0.0f;
+    p->magtol_txscale = 0.0f;
+    p->magtol_min = 10.0f;
+    p->magtol_max = 10.0f;
+    p->p_charge_cut = 0.0f;
+    p->velo_only = 1;
+    const float c[8] = {4824.3f, 426.3f, 7071.1f, 12080.4f, 14077.8f, 13909.3f, 9315.3f, 3209.5f};
+    for (int i = 0; i < 8; ++i) p->noUT_c[i] = c[i];
+    p->noUT_p_min = 5.0f;
+    p->noUT_pt_min = 1.0f;
+    p->noUT_overlap = 5.0f;
+}
+
 int lf_check_batch(const lf_batch *b) {
     if (!b) return fail(nullptr, LF_ERR_INVALID, "lf_check_batch: NULL batch");
     std::string why;
@@ -231,7 +272,8 @@ int lf_create(const lf_geometry *geom, const lf_params *params, size_t device_bu
         return fail(nullptr, LF_ERR_DEVICE, msg);
     }
     c->exec.n_cu = ncu;
-    c->exec.blocks_per_cu = lfk::persistent_blocks_per_cu(params->n_hits_window, c->exec.waves_per_block);
+    c->exec.blocks_per_cu = lfk::persistent_blocks_per_cu(params->n_hits_window, params->velo_only ? 2 : 1,
+                                                          c->exec.waves_per_block);
     if (c->exec.blocks_per_cu < 1) c->exec.blocks_per_cu = 1;
     *out = c;
     return LF_OK;
@@ -244,7 +286,8 @@ int lf_set_exec(lf_ctx *c, const lf_exec *x) {
         if (x->waves_per_block != 1 && x->waves_per_block != 2 && x->waves_per_block != 4)
             return fail(c, LF_ERR_INVALID, "lf_set_exec: waves_per_block must be 1, 2 or 4");
         n.waves_per_block = x->waves_per_block;
-        n.blocks_per_cu = lfk::persistent_blocks_per_cu(c->params.n_hits_window, n.waves_per_block);
+        n.blocks_per_cu = lfk::persistent_blocks_per_cu(c->params.n_hits_window, c->params.velo_only ? 2 : 1,
+                                                        n.waves_per_block);
         if (n.blocks_per_cu < 1) n.blocks_per_cu = 1;
     }
     if (x->items_per_grab) {
@@ -341,7 +384,8 @@ int lf_find_tracks(lf_ctx *c, uint64_t batch_id, int mode, void *hip_stream) {
     if (mode != LF_MODE_PLAIN && mode != LF_MODE_BATCHED && mode != LF_MODE_PERSISTENT)
         return fail(c, LF_ERR_INVALID, "lf_find_tracks: unknown mode");
     Batch &bt = it->second;
-    const hipError_t e = lfk::launch_find(bt.dev, c->d_params, c->params.n_hits_window, mode, c->exec,
+    const hipError_t e = lfk::launch_find(bt.dev, c->d_params, c->params.n_hits_window, c->params.velo_only ? 2 : 1,
+                                          mode, c->exec,
                                           bt.trk_off.data(), pick(c, hip_stream));
     if (e != hipSuccess) return hip_fail(c, e, "lf_find_tracks");
     return LF_OK;
@@ -372,7 +416,8 @@ int lf_graph_create(lf_ctx *c, const uint64_t *ids, uint32_t n, int mode, lf_gra
     if (e == hipSuccess) {
         hipError_t le = hipSuccess;
         for (Batch *b : bs) {
-            le = lfk::launch_find(b->dev, c->d_params, c->params.n_hits_window, mode, c->exec, b->trk_off.data(), cs);
+            le = lfk::launch_find(b->dev, c->d_params, c->params.n_hits_window, c->params.velo_only ? 2 : 1, mode,
+                                  c->exec, b->trk_off.data(), cs);
             if (le != hipSuccess) break;
         }
         e = hipStreamEndCapture(cs, &g->graph);
@@ -412,7 +457,8 @@ int lf_work_counts(lf_ctx *c, uint64_t batch_id, void *hip_stream, int64_t *coun
     hipStream_t s = pick(c, hip_stream);
     unsigned long long host[32] = {0};
     hipError_t e = hipMemsetAsync(bt.dev.stats, 0, sizeof(host), s);
-    if (e == hipSuccess) e = lfk::launch_count(bt.dev, c->d_params, c->params.n_hits_window, s);
+    if (e == hipSuccess)
+        e = lfk::launch_count(bt.dev, c->d_params, c->params.n_hits_window, c->params.velo_only ? 2 : 1, s);
     if (e == hipSuccess) e = hipMemcpyAsync(host, bt.dev.stats, sizeof(host), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "lf_work_counts");

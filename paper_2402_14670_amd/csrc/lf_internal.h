@@ -21,6 +21,10 @@ struct KParams {
     float magtol_const, magtol_pscale, magtol_txscale, magtol_min, magtol_max, p_charge_cut;
     float C_nhits[4];
     int32_t n_hits_window, n_triplets;
+    // No-UT tuning (VELO-only input): straight-line extrapolation, assumed
+    // minimum momentum, two windows per layer
+    int32_t velo_only;
+    float noUT_c[8], noUT_p_min, noUT_pt_min, noUT_overlap;
 };
 
 // Device view of one resident batch (SoA, all in HBM).
@@ -72,14 +76,15 @@ hipError_t launch_track_event(const DevBatch &b, hipStream_t s);
 // (per-event launches), 1 batched (one wavefront per track), 2 persistent
 // (resident wavefronts pulling from per-XCD work queues).
 // trk_off_host is read by mode 0 only.
-hipError_t launch_find(const DevBatch &b, const KParams *P, int n_hits_window, int mode,
+// n_sides: 1 for VELO-UT input, 2 for VELO-only input (two windows per layer).
+hipError_t launch_find(const DevBatch &b, const KParams *P, int n_hits_window, int n_sides, int mode,
                        const ExecCfg &cfg, const uint32_t *trk_off_host, hipStream_t s);
 // Counting launch: one wavefront per track, adds the work counters of every
 // track into b.stats (which must be zeroed first).
-hipError_t launch_count(const DevBatch &b, const KParams *P, int n_hits_window, hipStream_t s);
+hipError_t launch_count(const DevBatch &b, const KParams *P, int n_hits_window, int n_sides, hipStream_t s);
 // Fills the result slots with a poison pattern (kernel, no memset).
 hipError_t launch_poison(const DevBatch &b, hipStream_t s);
 // Resident blocks per compute unit of the persistent kernel (0 on error).
-int persistent_blocks_per_cu(int n_hits_window, int waves_per_block);
+int persistent_blocks_per_cu(int n_hits_window, int n_sides, int waves_per_block);
 
 }  // namespace lfk

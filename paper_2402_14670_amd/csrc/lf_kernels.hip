@@ -73,6 +73,11 @@ __device__ __forceinline__ float sum16(float v) {
     return v;
 }
 
+// Lane i's float, broadcast (i uniform).
+__device__ __forceinline__ float bcast_f(float v, int i) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
+}
+
 // Lane i's 64-bit value, broadcast (i uniform).
 __device__ __forceinline__ uint64_t bcast64(uint64_t v, int i) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, i);
@@ -150,18 +155,20 @@ __device__ __forceinline__ int closest_scan(Val val, int n, float xe, float &bd)
 // Index of stereo layer l (l % 4 in {1, 2}) among the six stereo layers.
 __device__ __forceinline__ int uv_index(int l) { return 2 * (l >> 2) + (l & 3) - 1; }
 
-template <int NW>
+// NS = 1: one window per layer; NS = 2 (VELO-only input): two windows per
+// layer, side 0 for bending towards -x, side 1 towards +x.
+template <int NW, int NS>
 struct WaveLds {
-    float wx[NL][NW];          // window hits: x at y = 0
-    float wz[NL][NW];          //              z
-    float wd[6][NW];           //              stereo tangent (stereo layers only)
-    int32_t wfirst[NL];        // event-local index of each window's first hit
-    int32_t wlen[NL];
+    float wx[NS][NL][NW];      // window hits: x at y = 0
+    float wz[NS][NL][NW];      //              z
+    float wd[NS][6][NW];       //              stereo tangent (stereo layers only)
+    int32_t wfirst[NS][NL];    // event-local index of each window's first hit
+    int32_t wlen[NS][NL];
     uint64_t tk[MAX_TRIPLETS];      // top-n keys, sorted
     uint8_t th1[MAX_TRIPLETS];      // middle hit of each kept triplet
     union {
         struct {               // seeding
-            uint32_t qkey[QCAP];    // queued doublets: set << 16 | i0 << 8 | i2
+            uint32_t qkey[QCAP];    // queued doublets: side << 17 | set << 16 | i0 << 8 | i2
         };
         struct {               // candidates (after seeding)
             float ca[MAX_TRIPLETS], cb[MAX_TRIPLETS], cc[MAX_TRIPLETS];  // triplet x(z) models
@@ -176,11 +183,11 @@ enum { C_TRACKS, C_PAIRS_ALL, C_ITEMS, C_PAIRS_TESTED, C_DOUBLETS, C_TRIPLETS, C
        // shader-clock cycles spent per phase (counting build only)
        C_CY_WINDOWS, C_CY_STAGE, C_CY_DOUBLETS, C_CY_MODEL, C_CY_EXTEND, C_CY_FIT, C_CY_SELECT, C_N };
 
-template <int NW, bool CNT = false>
+template <int NW, int NS, bool CNT = false>
 struct Track {
     const DevBatch &B;
     const KParams *__restrict__ P;
-    WaveLds<NW> &L;
+    WaveLds<NW, NS> &L;
     int nL;    // kept triplets
     uint32_t cnt[CNT ? C_N : 1];
     uint64_t tphase;
@@ -234,21 +241,22 @@ struct Track {
         int best = -1;
         if (lane < count) {
             const uint32_t e = L.qkey[lane];
-            const int s = (int)(e >> 16), i0 = (int)((e >> 8) & 0xffu), i2 = (int)(e & 0xffu);
+            const int sd = NS > 1 ? (int)((e >> 17) & 1u) : 0;
+            const int s = (int)((e >> 16) & 1u), i0 = (int)((e >> 8) & 0xffu), i2 = (int)(e & 0xffu);
             const int l0 = s ? 3 : 0, l1 = s ? 7 : 4, l2 = s ? 11 : 8;
             const float K = s ? P->K_last : P->K_first;
-            const float x0 = L.wx[l0][i0], z0 = L.wz[l0][i0];
-            const float txd = (L.wx[l2][i2] - x0) / (L.wz[l2][i2] - z0);   // the doublet's slope, as queued
+            const float x0 = L.wx[sd][l0][i0], z0 = L.wz[sd][l0][i0];
+            const float txd = (L.wx[sd][l2][i2] - x0) / (L.wz[sd][l2][i2] - z0);   // the doublet's slope, as queued
             const float x1e = P->z[l1] * txd + (x0 - txd * z0) * K;
             float bd = INFINITY;
-            const float *wx1 = L.wx[l1];
-            best = closest_sorted<NW>([wx1](int j) { return wx1[j]; }, L.wlen[l1], x1e, bd);
+            const float *wx1 = L.wx[sd][l1];
+            best = closest_sorted<NW>([wx1](int j) { return wx1[j]; }, L.wlen[sd][l1], x1e, bd);
             if (best >= 0) {
                 const float chi2 = bd * bd;
                 if (chi2 < P->T_triplet) {
                     tri = true;
                     key = ((uint64_t)__float_as_uint(chi2) << 32) |
-                          (uint64_t)(uint32_t)((s << 12) | (i0 << 6) | i2);
+                          (uint64_t)(uint32_t)((sd << 13) | (s << 12) | (i0 << 6) | i2);
                     // a full list only admits keys below its last one (exactly what the
                     // rank count of merge() would keep)
                     valid = nL < P->n_triplets || key < L.tk[nL - 1];
@@ -272,139 +280,179 @@ struct Track {
         const float qop = B.tqop[t];
         const float dR = P->dRatio;
 
-        // ---- kinematics, pt-kick extrapolation ----
-        const float p = 1.0f / fabsf(qop);
-        const int q = qop > 0.0f ? 1 : -1;
+        // ---- kinematics ----
+        // VELO-UT input: p and q from q/p.  VELO-only input: the assumed
+        // minimum momentum, the tighter (larger) of p_min and the momentum
+        // at which the track's transverse momentum is pt_min.
+        float p;
+        int q = 0;
+        if constexpr (NS == 2) {
+            const float t2 = tx_in * tx_in + ty_in * ty_in;
+            const float sin_t = sqrtf(t2 / (1.0f + t2));
+            const float p_pt = sin_t > 0.0f ? P->noUT_pt_min / sin_t : 0.0f;
+            p = p_pt > P->noUT_p_min ? p_pt : P->noUT_p_min;
+        } else {
+            p = 1.0f / fabsf(qop);
+            q = qop > 0.0f ? 1 : -1;
+        }
         const int zone = ty_in >= 0.0f ? 1 : 0;
         const float x_mag = x_in + tx_in * (P->z_mag - P->z_in);
         const float dtx = P->kick * qop;
         const float T = tx_in + dtx;
         const float kd = P->kappa * dtx;
         const uint32_t ebase = (uint32_t)__builtin_amdgcn_readlane((int)ho, 0);
-
-        // ---- search windows: lane 3*l + k searches bound k of layer l ----
-        int pos = 0;
-        {
-            const int l = lane < 3 * NL ? lane / 3 : 0;
-            const uint32_t b0 = (uint32_t)__shfl((int)ho, 2 * l + zone);
-            const uint32_t b1 = (uint32_t)__shfl((int)ho, 2 * l + zone + 1);
-            if (lane < 3 * NL) {
-                const int k = lane - 3 * l;
-                const float dz = P->z[l] - P->z_mag;
-                const float dzT = P->z[l] - P->z_T;
-                const float xe = x_mag + T * dz + kd * dzT * dzT;
-                const float ye = y_in + ty_in * (P->z[l] - P->z_in);
-                float xc, xmin, xmax;
-                if (is_uv(l)) {
-                    xc = xe - P->dxdy[l] * ye;
-                    xmin = xc - P->uv_halfwidth;
-                    xmax = xc + P->uv_halfwidth;
-                } else {
-                    const float xtol = P->xtol_const + P->xtol_pscale / p;
-                    float asymL = 0.0f, asymR = 0.0f;
-                    if (q * P->polarity > 0) asymR = P->xasym; else asymL = P->xasym;
-                    xc = xe;
-                    xmin = xc - xtol - asymL;
-                    xmax = xc + xtol + asymR;
-                }
-                const float key = k == 0 ? xmin : (k == 1 ? xc : xmax);
-                uint32_t lo = b0;
-                uint32_t n = b1 - b0;
-                // lower bound (x < key) for x_min and the centre, upper bound (x <= key) for x_max
-                while (n > 0) {
-                    const uint32_t half = n >> 1;
-                    const float v = ld32(B.hx, lo + half);
-                    const bool right = k == 2 ? (v <= key) : (v < key);
-                    if (right) { lo += half + 1; n -= half + 1; } else { n = half; }
-                }
-                pos = (int)(lo - ebase);
-            }
+        // x tolerance of the x-layer windows
+        float xtol;
+        if constexpr (NS == 2) {
+            const float ip = 1.0f / p;
+            const float ty2 = ty_in * ty_in;
+            const float *c8 = P->noUT_c;
+            xtol = ip * (c8[0] + tx_in * (c8[1] + c8[2] * tx_in) + ty2 * (c8[3] + tx_in * (c8[4] + c8[5] * tx_in)) +
+                         ip * (c8[6] * tx_in + c8[7] * ip));
+        } else {
+            xtol = P->xtol_const + P->xtol_pscale / p;
         }
-        int wf = 0, wl = 0;   // lane l < 12: first hit (event-local) and length of layer l's window
-        {
-            const int src = lane < NL ? 3 * lane : 0;
-            const int lo = __shfl(pos, src), c0 = __shfl(pos, src + 1), hi0 = __shfl(pos, src + 2);
-            if (lane < NL) {
-                int hi = hi0 < lo ? lo : hi0;
-                int c = c0 < lo ? lo : (c0 > hi ? hi : c0);
-                const int N = P->n_hits_window;
-                int first = lo, len = hi - lo;
-                if (hi - lo > N) {
-                    first = c - N / 2;
-                    if (first < lo) first = lo;
-                    if (first > hi - N) first = hi - N;
-                    len = N;
+
+        // ---- search windows: lane 3*l + k searches bound k of layer l, side by side ----
+        int wf[NS], wl[NS];   // lane l < 12: first hit (event-local) and length of layer l's window
+#pragma unroll
+        for (int sd = 0; sd < NS; ++sd) {
+            int pos = 0;
+            {
+                const int l = lane < 3 * NL ? lane / 3 : 0;
+                const uint32_t b0 = (uint32_t)__shfl((int)ho, 2 * l + zone);
+                const uint32_t b1 = (uint32_t)__shfl((int)ho, 2 * l + zone + 1);
+                if (lane < 3 * NL) {
+                    const int k = lane - 3 * l;
+                    const float ye = y_in + ty_in * (P->z[l] - P->z_in);
+                    float xc, xmin, xmax;
+                    if constexpr (NS == 2) {
+                        // straight line; two windows per layer sharing an overlap
+                        const float xe = x_in + tx_in * (P->z[l] - P->z_in);
+                        const float x0 = is_uv(l) ? xe - P->dxdy[l] * ye : xe;
+                        const float tol = is_uv(l) ? P->uv_halfwidth : xtol;
+                        if (sd == 0) { xmin = x0 - tol; xmax = x0 + P->noUT_overlap; }
+                        else { xmin = x0 - P->noUT_overlap; xmax = x0 + tol; }
+                        xc = 0.5f * (xmin + xmax);
+                    } else {
+                        const float dz = P->z[l] - P->z_mag;
+                        const float dzT = P->z[l] - P->z_T;
+                        const float xe = x_mag + T * dz + kd * dzT * dzT;
+                        if (is_uv(l)) {
+                            xc = xe - P->dxdy[l] * ye;
+                            xmin = xc - P->uv_halfwidth;
+                            xmax = xc + P->uv_halfwidth;
+                        } else {
+                            float asymL = 0.0f, asymR = 0.0f;
+                            if (q * P->polarity > 0) asymR = P->xasym; else asymL = P->xasym;
+                            xc = xe;
+                            xmin = xc - xtol - asymL;
+                            xmax = xc + xtol + asymR;
+                        }
+                    }
+                    const float key = k == 0 ? xmin : (k == 1 ? xc : xmax);
+                    uint32_t lo = b0;
+                    uint32_t n = b1 - b0;
+                    // lower bound (x < key) for x_min and the centre, upper bound (x <= key) for x_max
+                    while (n > 0) {
+                        const uint32_t half = n >> 1;
+                        const float v = ld32(B.hx, lo + half);
+                        const bool right = k == 2 ? (v <= key) : (v < key);
+                        if (right) { lo += half + 1; n -= half + 1; } else { n = half; }
+                    }
+                    pos = (int)(lo - ebase);
                 }
-                wf = first;
-                wl = len;
-                L.wfirst[lane] = first;
-                L.wlen[lane] = len;
+            }
+            wf[sd] = 0;
+            wl[sd] = 0;
+            {
+                const int src = lane < NL ? 3 * lane : 0;
+                const int lo = __shfl(pos, src), c0 = __shfl(pos, src + 1), hi0 = __shfl(pos, src + 2);
+                if (lane < NL) {
+                    int hi = hi0 < lo ? lo : hi0;
+                    int c = c0 < lo ? lo : (c0 > hi ? hi : c0);
+                    const int N = P->n_hits_window;
+                    int first = lo, len = hi - lo;
+                    if (hi - lo > N) {
+                        first = c - N / 2;
+                        if (first < lo) first = lo;
+                        if (first > hi - N) first = hi - N;
+                        len = N;
+                    }
+                    wf[sd] = first;
+                    wl[sd] = len;
+                    L.wfirst[sd][lane] = first;
+                    L.wlen[sd][lane] = len;
+                }
             }
         }
         mark(C_CY_WINDOWS);
 
         // ---- stage window hits into LDS ----
         // Round u covers slots lane + 64 u of the 12 x NW window slots (layer
-        // (lane + 64 u) / NW); every load is issued before the first LDS write.
-        // The same registers tell which layers have window hits that do not
-        // all share one z (resp. one stereo slope): those take the general
-        // paths below.
+        // (lane + 64 u) / NW); every load of a side is issued before its first
+        // LDS write.  The same registers tell which windows have hits that do
+        // not all share one z (resp. one stereo slope): bit NL * side + layer
+        // of zvar (dvar); those take the general paths below.
         constexpr int SU = NL * NW / WAVE;
-        float sx[SU], sz[SU], sd[SU];
-        uint32_t smask = 0;
-#pragma unroll
-        for (int u = 0; u < SU; ++u) {
-            const int it = lane + WAVE * u, l = it / NW, j = it - NW * (it / NW);
-            const int la = WAVE * u / NW, lb = (WAVE * u + WAVE - 1) / NW;
-            const int fa = __builtin_amdgcn_readlane(wf, la), fb = __builtin_amdgcn_readlane(wf, lb);
-            const int na = __builtin_amdgcn_readlane(wl, la), nb = __builtin_amdgcn_readlane(wl, lb);
-            const int f = l == la ? fa : fb;
-            const int n = l == la ? na : nb;
-            sx[u] = sz[u] = sd[u] = 0.0f;
-            if (j < n) {
-                const uint32_t g = ebase + (uint32_t)(f + j);
-                sx[u] = ld32(B.hx, g);
-                sz[u] = ld32(B.hz, g);
-                if (is_uv(l)) sd[u] = ld32(B.hd, g);
-                smask |= 1u << u;
-            }
-        }
         uint32_t zvar = 0, dvar = 0;
 #pragma unroll
-        for (int u = 0; u < SU; ++u) {
-            const int it = lane + WAVE * u, l = it / NW, j = it - NW * (it / NW);
-            const int la = WAVE * u / NW, lb = (WAVE * u + WAVE - 1) / NW;
-            const bool in = (smask >> u) & 1u;
-            if (in) {
-                L.wx[l][j] = sx[u];
-                L.wz[l][j] = sz[u];
-                if (is_uv(l)) L.wd[uv_index(l)][j] = sd[u];
+        for (int sd = 0; sd < NS; ++sd) {
+            float sx[SU], sz[SU], sd_[SU];
+            uint32_t smask = 0;
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int it = lane + WAVE * u, l = it / NW, j = it - NW * (it / NW);
+                const int la = WAVE * u / NW, lb = (WAVE * u + WAVE - 1) / NW;
+                const int fa = __builtin_amdgcn_readlane(wf[sd], la), fb = __builtin_amdgcn_readlane(wf[sd], lb);
+                const int na = __builtin_amdgcn_readlane(wl[sd], la), nb = __builtin_amdgcn_readlane(wl[sd], lb);
+                const int f = l == la ? fa : fb;
+                const int n = l == la ? na : nb;
+                sx[u] = sz[u] = sd_[u] = 0.0f;
+                if (j < n) {
+                    const uint32_t g = ebase + (uint32_t)(f + j);
+                    sx[u] = ld32(B.hx, g);
+                    sz[u] = ld32(B.hz, g);
+                    if (is_uv(l)) sd_[u] = ld32(B.hd, g);
+                    smask |= 1u << u;
+                }
             }
-            // slot 0 of layer la sits in lane la NW - 64 u, that of lb in lane lb NW - 64 u
-            const float za = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sz[u]), la * NW - WAVE * u));
-            const float zb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sz[u]), lb * NW - WAVE * u));
-            const float da = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sd[u]), la * NW - WAVE * u));
-            const float db = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sd[u]), lb * NW - WAVE * u));
-            const bool zd = in && sz[u] != (l == la ? za : zb);
-            const bool dd = in && sd[u] != (l == la ? da : db);
-            if (__ballot(zd && l == la)) zvar |= 1u << la;
-            if (__ballot(zd && l == lb)) zvar |= 1u << lb;
-            if (is_uv(la) && __ballot(dd && l == la)) dvar |= 1u << la;
-            if (is_uv(lb) && __ballot(dd && l == lb)) dvar |= 1u << lb;
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int it = lane + WAVE * u, l = it / NW, j = it - NW * (it / NW);
+                const int la = WAVE * u / NW, lb = (WAVE * u + WAVE - 1) / NW;
+                const bool in = (smask >> u) & 1u;
+                if (in) {
+                    L.wx[sd][l][j] = sx[u];
+                    L.wz[sd][l][j] = sz[u];
+                    if (is_uv(l)) L.wd[sd][uv_index(l)][j] = sd_[u];
+                }
+                // slot 0 of layer la sits in lane la NW - 64 u, that of lb in lane lb NW - 64 u
+                const float za = bcast_f(sz[u], la * NW - WAVE * u), zb = bcast_f(sz[u], lb * NW - WAVE * u);
+                const float da = bcast_f(sd_[u], la * NW - WAVE * u), db = bcast_f(sd_[u], lb * NW - WAVE * u);
+                const bool zd = in && sz[u] != (l == la ? za : zb);
+                const bool dd = in && sd_[u] != (l == la ? da : db);
+                if (__ballot(zd && l == la)) zvar |= 1u << (NL * sd + la);
+                if (__ballot(zd && l == lb)) zvar |= 1u << (NL * sd + lb);
+                if (is_uv(la) && __ballot(dd && l == la)) dvar |= 1u << (NL * sd + la);
+                if (is_uv(lb) && __ballot(dd && l == lb)) dvar |= 1u << (NL * sd + lb);
+            }
         }
         wave_sync();
         if constexpr (CNT) {
-            for (int l = 0; l < NL; ++l) cnt[C_STAGED] += (uint32_t)L.wlen[l];
-            cnt[C_PAIRS_ALL] = (uint32_t)(L.wlen[0] * L.wlen[8] + L.wlen[3] * L.wlen[11]);
+            for (int sd = 0; sd < NS; ++sd) {
+                for (int l = 0; l < NL; ++l) cnt[C_STAGED] += (uint32_t)L.wlen[sd][l];
+                cnt[C_PAIRS_ALL] += (uint32_t)(L.wlen[sd][0] * L.wlen[sd][8] + L.wlen[sd][3] * L.wlen[sd][11]);
+            }
         }
 
         mark(C_CY_STAGE);
         // ---- doublets of both seed sets, filtered, queued; triplets by passes ----
         nL = 0;
         const float tolc = P->magtol_const + P->magtol_pscale / p;
-        const bool low_p = p < P->p_charge_cut;
+        const bool low_p = NS == 1 && p < P->p_charge_cut;   // no bend-direction filter without q/p
         int qn = 0;
-        // One item per (set, h0).  Each item gets the range of h2 in its third
+        // One item per (side, set, h0).  Each item gets the range of h2 in its third
         // window that can pass the magnet filter: with a common z per window,
         // a passing slope t satisfies |x0 - x_mag + (z_mag - z0) t| < tol(t)
         // <= tolb, so t lies within tolb/|z_mag - z0| of t_c = (x_mag - x0) /
@@ -414,24 +462,27 @@ struct Track {
         // bracket, and every pair in it is tested with the exact filter
         // below; pairs outside cannot pass.  Sets without a common z
         // per window (or a degenerate lever arm) test every pair.
-        const int n00 = L.wlen[0], n01 = L.wlen[3];
-        const int items_total = n00 + n01;
+        // items in (side, set) order: group g = 2 side + set starts at c[g]
+        const int c1 = L.wlen[0][0], c2 = c1 + L.wlen[0][3];
+        const int c3 = NS > 1 ? c2 + L.wlen[NS - 1][0] : c2;
+        const int items_total = NS > 1 ? c3 + L.wlen[NS - 1][3] : c2;
         if constexpr (CNT) cnt[C_ITEMS] = (uint32_t)items_total;
         for (int base = 0; base < items_total; base += WAVE) {
             const int item = base + lane;
-            const int s = item < n00 ? 0 : 1;
-            const int i0 = item - (s ? n00 : 0);
+            const int grp = item < c1 ? 0 : (item < c2 ? 1 : (item < c3 ? 2 : 3));
+            const int sd = NS > 1 ? grp >> 1 : 0, s = grp & 1;
+            const int i0 = item - (grp == 0 ? 0 : (grp == 1 ? c1 : (grp == 2 ? c2 : c3)));
             const int l0 = s ? 3 : 0, l2 = s ? 11 : 8;
-            const int n2 = L.wlen[l2];
+            const int n2 = L.wlen[sd][l2];
             int jlo = 0, jhi = 0;
             float x0 = 0.0f, z0 = 0.0f;
             if (item < items_total) {
-                x0 = L.wx[l0][i0];
-                z0 = L.wz[l0][i0];
+                x0 = L.wx[sd][l0][i0];
+                z0 = L.wz[sd][l0][i0];
                 jhi = n2;
-                if (n2 > 0 && !((zvar >> l0) & 1u) && !((zvar >> l2) & 1u)) {
+                if (n2 > 0 && !((zvar >> (NL * sd + l0)) & 1u) && !((zvar >> (NL * sd + l2)) & 1u)) {
                     const float lev = P->z_mag - z0;
-                    const float dz = L.wz[l2][0] - z0;
+                    const float dz = L.wz[sd][l2][0] - z0;
                     if (fabsf(lev) > 1.0f && fabsf(dz) > 1.0f) {
                         const float rl = __builtin_amdgcn_rcpf(lev);   // within 1 ulp: the bracket is padded
                         const float arl = fabsf(rl);
@@ -447,7 +498,7 @@ struct Track {
                         const float xlo = (e1 < e2 ? e1 : e2) - margin;
                         const float xhi = (e1 < e2 ? e2 : e1) + margin;
                         if (fabsf(xlo) < 1e30f && fabsf(xhi) < 1e30f) {
-                            bounds_sorted<NW>(L.wx[l2], n2, xlo, xhi, jlo, jhi);
+                            bounds_sorted<NW>(L.wx[sd][l2], n2, xlo, xhi, jlo, jhi);
                         }
                     }
                 }
@@ -463,7 +514,7 @@ struct Track {
                 bool pass = false;
                 float txd = 0.0f;
                 if (i2 < jhi) {
-                    const float x2 = L.wx[l2][i2], z2 = L.wz[l2][i2];
+                    const float x2 = L.wx[sd][l2][i2], z2 = L.wz[sd][l2][i2];
                     txd = (x2 - x0) / (z2 - z0);
                     pass = !(low_p && !((txd - tx_in) * qop > 0.0f));
                     const float xm = x0 + txd * (P->z_mag - z0);
@@ -479,7 +530,7 @@ struct Track {
                 }
                 if (pass) {
                     const int at = qn + lanes_below(bal);
-                    L.qkey[at] = ((uint32_t)s << 16) | ((uint32_t)i0 << 8) | (uint32_t)i2;
+                    L.qkey[at] = ((uint32_t)sd << 17) | ((uint32_t)s << 16) | ((uint32_t)i0 << 8) | (uint32_t)i2;
                 }
                 qn += __popcll(bal);
                 if (qn >= WAVE) {
@@ -511,11 +562,13 @@ struct Track {
         // ---- triplet x(z) models ----
         if (lane < nL) {
             const uint32_t lo = (uint32_t)L.tk[lane];
+            const int sd = NS > 1 ? (int)((lo >> 13) & 1u) : 0;
             const int s = (int)((lo >> 12) & 1u), i0 = (int)((lo >> 6) & 63u), i2 = (int)(lo & 63u);
             const int i1 = L.th1[lane];
             const int l0 = s ? 3 : 0, l1 = s ? 7 : 4, l2 = s ? 11 : 8;
-            const float u0 = L.wz[l0][i0] - P->z_ref, u1 = L.wz[l1][i1] - P->z_ref, u2 = L.wz[l2][i2] - P->z_ref;
-            const float X0 = L.wx[l0][i0], X1 = L.wx[l1][i1], X2 = L.wx[l2][i2];
+            const float u0 = L.wz[sd][l0][i0] - P->z_ref, u1 = L.wz[sd][l1][i1] - P->z_ref,
+                        u2 = L.wz[sd][l2][i2] - P->z_ref;
+            const float X0 = L.wx[sd][l0][i0], X1 = L.wx[sd][l1][i1], X2 = L.wx[sd][l2][i2];
             const float g0 = g_of(u0, dR), g1 = g_of(u1, dR), g2 = g_of(u2, dR);
             const float s01 = (X1 - X0) / (u1 - u0);
             const float s12 = (X2 - X1) / (u2 - u1);
@@ -541,15 +594,16 @@ struct Track {
         const float T_uv = T_uv0 < P->T_uv_floor ? P->T_uv_floor : T_uv0;
         for (int it = lane; it < nL * NSLOT; it += WAVE) {
             const int r = it / NSLOT, slot = it - NSLOT * (it / NSLOT);
-            const int s = (int)(((uint32_t)L.tk[r] >> 12) & 1u);
+            const uint32_t kr = (uint32_t)L.tk[r];
+            const int s = (int)((kr >> 12) & 1u), sd = NS > 1 ? (int)((kr >> 13) & 1u) : 0;
             int l;
             if (slot < 3) l = s ? 4 * slot : 4 * slot + 3;
             else l = 4 * ((slot - 3) >> 1) + 1 + ((slot - 3) & 1);
             const float a = L.ca[r], b = L.cb[r], c = L.cc[r];
             const float u = P->z[l] - P->z_ref;
             const float xe = a + b * u + c * g_of(u, dR);
-            const int n = L.wlen[l];
-            const float *wxl = L.wx[l];
+            const int n = L.wlen[sd][l];
+            const float *wxl = L.wx[sd][l];
             float bd = INFINITY;
             if (slot < 3) {
                 const int best = closest_sorted<NW>([wxl](int j) { return wxl[j]; }, n, xe, bd);
@@ -558,9 +612,10 @@ struct Track {
                 // the hit's x at y = 0 moved along its fibre to the predicted y; with a
                 // common stereo slope in the window these values stay sorted
                 const float yp = y_in + ty_in * (P->z[l] - P->z_in);
-                const float *wdl = L.wd[uv_index(l)];
+                const float *wdl = L.wd[sd][uv_index(l)];
                 auto val = [wxl, wdl, yp](int j) { return wxl[j] + wdl[j] * yp; };
-                const int best = ((dvar >> l) & 1u) ? closest_scan(val, n, xe, bd) : closest_sorted<NW>(val, n, xe, bd);
+                const int best = ((dvar >> (NL * sd + l)) & 1u) ? closest_scan(val, n, xe, bd)
+                                                                : closest_sorted<NW>(val, n, xe, bd);
                 if (best >= 0 && bd * bd < T_uv) L.ch[r][l] = (int8_t)best;
             }
         }
@@ -608,18 +663,22 @@ struct Track {
             const bool pres = hit >= 0;
             const bool pres_uv = pres && uvj;
             float a = 0.0f, b = 0.0f, c = 0.0f;
-            if (r >= 0) { a = L.ca[r]; b = L.cb[r]; c = L.cc[r]; }
+            int sd = 0;
+            if (r >= 0) {
+                a = L.ca[r]; b = L.cb[r]; c = L.cc[r];
+                if constexpr (NS > 1) sd = (int)(((uint32_t)L.tk[r] >> 13) & 1u);
+            }
             float sv = 0.0f, h = 0.0f, rr = 0.0f, dxy = 1.0f;
             if (pres) {
-                const float zh = L.wz[j][hit];
+                const float zh = L.wz[sd][j][hit];
                 const float u = zh - P->z_ref;
                 float xm;
                 if (uvj) {
-                    dxy = L.wd[uv_index(j)][hit];
+                    dxy = L.wd[sd][uv_index(j)][hit];
                     const float yv = y_in + ty_in * (zh - P->z_in);
-                    xm = L.wx[j][hit] + dxy * yv;
+                    xm = L.wx[sd][j][hit] + dxy * yv;
                 } else {
-                    xm = L.wx[j][hit];
+                    xm = L.wx[sd][j][hit];
                 }
                 sv = u * INV1024;
                 h = sv * sv * (1.0f + dR * u);
@@ -695,8 +754,9 @@ struct Track {
             B.Q[t] = best_Q;
         }
         if (lane < NL) {
+            const int sd = NS > 1 ? (int)(((uint32_t)L.tk[best_r] >> 13) & 1u) : 0;
             const int h = L.ch[best_r][lane];
-            B.hit_idx[o12 + lane] = h >= 0 ? L.wfirst[lane] + h : -1;
+            B.hit_idx[o12 + lane] = h >= 0 ? L.wfirst[sd][lane] + h : -1;
         }
         mark(C_CY_SELECT);
     }
@@ -713,13 +773,13 @@ struct Track {
     }
 };
 
-template <int NW, int WPB>
+template <int NW, int NS, int WPB>
 __global__ __launch_bounds__(WPB * WAVE) void k_plain(DevBatch B, const KParams *__restrict__ P, uint32_t ev) {
-    __shared__ WaveLds<NW> lds[WPB];
+    __shared__ WaveLds<NW, NS> lds[WPB];
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const uint32_t t = B.trk_off[ev] + blockIdx.x * WPB + w;
     if (t >= B.trk_off[ev + 1]) return;
-    Track<NW> tr{B, P, lds[w], 0, {}, 0};
+    Track<NW, NS> tr{B, P, lds[w], 0, {}, 0};
     tr.run(t, ev);
 }
 
@@ -728,15 +788,15 @@ __global__ __launch_bounds__(WPB * WAVE) void k_plain(DevBatch B, const KParams 
 // event share one L2 and its hits are fetched from HBM once per XCD.
 constexpr uint32_t NXCD = 8;
 
-template <int NW, int WPB, bool CNT = false>
+template <int NW, int NS, int WPB, bool CNT = false>
 __global__ __launch_bounds__(WPB * WAVE) void k_grid(DevBatch B, const KParams *__restrict__ P) {
-    __shared__ WaveLds<NW> lds[WPB];
+    __shared__ WaveLds<NW, NS> lds[WPB];
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const uint32_t per = gridDim.x / NXCD;
     const uint32_t lb = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
     const uint32_t t = lb * WPB + w;
     if (t >= B.n_tracks) return;
-    Track<NW, CNT> tr{B, P, lds[w], 0, {}, 0};
+    Track<NW, NS, CNT> tr{B, P, lds[w], 0, {}, 0};
     tr.run(t, B.trk_ev[t]);
     if constexpr (CNT) {
         if (lane_id() == 0)
@@ -751,10 +811,10 @@ __global__ __launch_bounds__(WPB * WAVE) void k_grid(DevBatch B, const KParams *
 // exited waves, and the last wave out puts every word back to zero, so the
 // next launch on the batch starts clean without a reset kernel (or a memset
 // node in a captured graph).
-template <int NW, int WPB>
+template <int NW, int NS, int WPB>
 __global__ __launch_bounds__(WPB * WAVE) void k_persistent(DevBatch B, const KParams *__restrict__ P,
                                                             uint32_t items) {
-    __shared__ WaveLds<NW> lds[WPB];
+    __shared__ WaveLds<NW, NS> lds[WPB];
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     uint32_t *q = B.counter;
     const uint32_t T = B.n_tracks;
@@ -780,7 +840,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_persistent(DevBatch B, const KPa
             // keep per-track loads inside the loop: hoisting them across tracks
             // costs ~30 VGPRs of loop-carried state and two waves per SIMD
             asm volatile("" ::: "memory");
-            Track<NW> tr{B, P, lds[w], 0, {}, 0};
+            Track<NW, NS> tr{B, P, lds[w], 0, {}, 0};
             tr.run(t, B.trk_ev[t]);
         }
     }
@@ -847,7 +907,7 @@ __global__ void k_track_event(const uint32_t *__restrict__ trk_off, uint32_t n_e
     trk_ev[t] = lo - 1;
 }
 
-template <int NW, int WPB>
+template <int NW, int NS, int WPB>
 hipError_t launch_nw_wpb(const DevBatch &b, const KParams *P, int mode, const ExecCfg &cfg,
                          const uint32_t *trk_off_host, hipStream_t s) {
     const dim3 block(WPB * WAVE);
@@ -855,30 +915,30 @@ hipError_t launch_nw_wpb(const DevBatch &b, const KParams *P, int mode, const Ex
         for (uint32_t e = 0; e < b.n_events; ++e) {
             const uint32_t nt = trk_off_host[e + 1] - trk_off_host[e];
             if (nt == 0) continue;
-            hipLaunchKernelGGL((k_plain<NW, WPB>), dim3((nt + WPB - 1) / WPB), block, 0, s, b, P, e);
+            hipLaunchKernelGGL((k_plain<NW, NS, WPB>), dim3((nt + WPB - 1) / WPB), block, 0, s, b, P, e);
         }
     } else if (mode == 2) {   // persistent: resident waves, per-XCD work queues
         uint32_t grid = (uint32_t)(cfg.blocks_per_cu * cfg.n_cu);
         const uint32_t need = (b.n_tracks + WPB - 1) / WPB;
         if (grid > need) grid = need;
         if (grid == 0) grid = 1;
-        hipLaunchKernelGGL((k_persistent<NW, WPB>), dim3(grid), block, 0, s, b, P,
+        hipLaunchKernelGGL((k_persistent<NW, NS, WPB>), dim3(grid), block, 0, s, b, P,
                            (uint32_t)cfg.items_per_grab);
     } else {   // batched: one launch, one wavefront per track, XCD-ordered
         const uint32_t need = (b.n_tracks + WPB - 1) / WPB;
         const uint32_t grid = (need + NXCD - 1) / NXCD * NXCD;
-        if (grid) hipLaunchKernelGGL((k_grid<NW, WPB>), dim3(grid), block, 0, s, b, P);
+        if (grid) hipLaunchKernelGGL((k_grid<NW, NS, WPB>), dim3(grid), block, 0, s, b, P);
     }
     return hipGetLastError();
 }
 
-template <int NW>
+template <int NW, int NS>
 hipError_t launch_nw(const DevBatch &b, const KParams *P, int mode, const ExecCfg &cfg,
                      const uint32_t *trk_off_host, hipStream_t s) {
     switch (cfg.waves_per_block) {
-        case 1: return launch_nw_wpb<NW, 1>(b, P, mode, cfg, trk_off_host, s);
-        case 2: return launch_nw_wpb<NW, 2>(b, P, mode, cfg, trk_off_host, s);
-        default: return launch_nw_wpb<NW, 4>(b, P, mode, cfg, trk_off_host, s);
+        case 1: return launch_nw_wpb<NW, NS, 1>(b, P, mode, cfg, trk_off_host, s);
+        case 2: return launch_nw_wpb<NW, NS, 2>(b, P, mode, cfg, trk_off_host, s);
+        default: return launch_nw_wpb<NW, NS, 4>(b, P, mode, cfg, trk_off_host, s);
     }
 }
 
@@ -938,12 +998,18 @@ hipError_t launch_digest(const DevBatch &b, const uint32_t *trk_off, uint32_t n_
     return hipGetLastError();
 }
 
-hipError_t launch_count(const DevBatch &b, const KParams *P, int n_hits_window, hipStream_t s) {
+hipError_t launch_count(const DevBatch &b, const KParams *P, int n_hits_window, int n_sides, hipStream_t s) {
     if (b.n_tracks == 0) return hipSuccess;
     const uint32_t need = (b.n_tracks + 1) / 2;
     const uint32_t grid = (need + NXCD - 1) / NXCD * NXCD;
-    if (n_hits_window <= 32) hipLaunchKernelGGL((k_grid<32, 2, true>), dim3(grid), dim3(2 * WAVE), 0, s, b, P);
-    else hipLaunchKernelGGL((k_grid<64, 2, true>), dim3(grid), dim3(2 * WAVE), 0, s, b, P);
+    const dim3 g(grid), blk(2 * WAVE);
+    if (n_sides == 2) {
+        if (n_hits_window <= 32) hipLaunchKernelGGL((k_grid<32, 2, 2, true>), g, blk, 0, s, b, P);
+        else hipLaunchKernelGGL((k_grid<64, 2, 2, true>), g, blk, 0, s, b, P);
+    } else {
+        if (n_hits_window <= 32) hipLaunchKernelGGL((k_grid<32, 1, 2, true>), g, blk, 0, s, b, P);
+        else hipLaunchKernelGGL((k_grid<64, 1, 2, true>), g, blk, 0, s, b, P);
+    }
     return hipGetLastError();
 }
 
@@ -960,33 +1026,38 @@ hipError_t launch_track_event(const DevBatch &b, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_find(const DevBatch &b, const KParams *P, int n_hits_window, int mode, const ExecCfg &cfg,
-                       const uint32_t *trk_off_host, hipStream_t s) {
+hipError_t launch_find(const DevBatch &b, const KParams *P, int n_hits_window, int n_sides, int mode,
+                       const ExecCfg &cfg, const uint32_t *trk_off_host, hipStream_t s) {
     if (b.n_tracks == 0) return hipSuccess;
-    if (n_hits_window <= 32) return launch_nw<32>(b, P, mode, cfg, trk_off_host, s);
-    return launch_nw<64>(b, P, mode, cfg, trk_off_host, s);
+    if (n_sides == 2) {
+        if (n_hits_window <= 32) return launch_nw<32, 2>(b, P, mode, cfg, trk_off_host, s);
+        return launch_nw<64, 2>(b, P, mode, cfg, trk_off_host, s);
+    }
+    if (n_hits_window <= 32) return launch_nw<32, 1>(b, P, mode, cfg, trk_off_host, s);
+    return launch_nw<64, 1>(b, P, mode, cfg, trk_off_host, s);
 }
 
 namespace {
-template <int NW, int WPB>
+template <int NW, int NS, int WPB>
 int occ() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_persistent<NW, WPB>),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_persistent<NW, NS, WPB>),
                                                      WPB * WAVE, 0) != hipSuccess)
         return 0;
     return n;
 }
 }  // namespace
 
-int persistent_blocks_per_cu(int n_hits_window, int waves_per_block) {
-    if (n_hits_window <= 32) {
-        if (waves_per_block == 1) return occ<32, 1>();
-        if (waves_per_block == 2) return occ<32, 2>();
-        return occ<32, 4>();
-    }
-    if (waves_per_block == 1) return occ<64, 1>();
-    if (waves_per_block == 2) return occ<64, 2>();
-    return occ<64, 4>();
+template <int NW, int NS>
+int occ_wpb(int waves_per_block) {
+    if (waves_per_block == 1) return occ<NW, NS, 1>();
+    if (waves_per_block == 2) return occ<NW, NS, 2>();
+    return occ<NW, NS, 4>();
+}
+
+int persistent_blocks_per_cu(int n_hits_window, int n_sides, int waves_per_block) {
+    if (n_sides == 2) return n_hits_window <= 32 ? occ_wpb<32, 2>(waves_per_block) : occ_wpb<64, 2>(waves_per_block);
+    return n_hits_window <= 32 ? occ_wpb<32, 1>(waves_per_block) : occ_wpb<64, 1>(waves_per_block);
 }
 
 }  // namespace lfk

@@ -36,6 +36,7 @@ namespace lfapi {
 int ctx_fail(lf_ctx *c, int code, const std::string &msg);
 const lfk::KParams *ctx_dparams(const lf_ctx *c);
 int ctx_nhits_window(const lf_ctx *c);
+int ctx_sides(const lf_ctx *c);
 const lfk::ExecCfg &ctx_exec(const lf_ctx *c);
 int check_batch(const lf_batch *b, std::string &why);
 }  // namespace lfapi
@@ -242,6 +243,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
     }
     const lfk::KParams *P = lfapi::ctx_dparams(ctx);
     const int nhw = lfapi::ctx_nhits_window(ctx);
+    const int n_sides = lfapi::ctx_sides(ctx);
     const lfk::ExecCfg exec = lfapi::ctx_exec(ctx);
 
     // Writes the descriptors of pool events evs[0..E) and enqueues
@@ -298,7 +300,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
         hipError_t e = hipMemcpyAsync(dr + lay.desc, s.stage, (size_t)E * sizeof(lfk::GatherDesc),
                                       hipMemcpyHostToDevice, s.stream);
         if (e == hipSuccess) e = lfk::launch_gather(ddesc, E, in, s.stream);
-        if (e == hipSuccess) e = lfk::launch_find(d, P, nhw, 1, exec, nullptr, s.stream);
+        if (e == hipSuccess) e = lfk::launch_find(d, P, nhw, n_sides, 1, exec, nullptr, s.stream);
         if (e == hipSuccess)
             e = lfk::launch_digest(d, d.trk_off, E, reinterpret_cast<unsigned long long *>(dr + lay.dig), s.stream);
         if (e == hipSuccess) e = hipMemcpyAsync(s.out, dr + lay.dig, lay.out_bytes, hipMemcpyDeviceToHost, s.stream);

@@ -54,7 +54,12 @@ _PARAM_FLOATS = ("T_triplet", "T_x", "T_uv_scale", "T_uv_floor", "T_ty", "T_y", 
 
 class lf_params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_float) for n in _PARAM_FLOATS] + [
-        ("C_nhits", ctypes.c_float * 4), ("n_hits_window", ctypes.c_int32), ("n_triplets", ctypes.c_int32)]
+        ("C_nhits", ctypes.c_float * 4), ("n_hits_window", ctypes.c_int32), ("n_triplets", ctypes.c_int32),
+        ("velo_only", ctypes.c_int32), ("noUT_c", ctypes.c_float * 8), ("noUT_p_min", ctypes.c_float),
+        ("noUT_pt_min", ctypes.c_float), ("noUT_overlap", ctypes.c_float)]
+
+
+_PARAM_ARRAYS = ("C_nhits", "noUT_c")
 
 
 class lf_batch(ctypes.Structure):
@@ -89,7 +94,7 @@ class lf_exec(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32)]
 
 
-EXPORTS = ("lf_default_params", "lf_check_batch", "lf_create", "lf_upload_events", "lf_find_tracks",
+EXPORTS = ("lf_default_params", "lf_default_params_no_ut", "lf_check_batch", "lf_create", "lf_upload_events", "lf_find_tracks",
            "lf_work_counts", "lf_fetch_tracks", "lf_copy_tracks", "lf_poison_tracks", "lf_release_batch", "lf_set_exec", "lf_batch_info",
            "lf_device_bytes_in_use", "lf_serve_run", "lf_graph_create", "lf_graph_launch", "lf_graph_destroy",
            "lf_destroy", "lf_last_error")
@@ -109,6 +114,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     P, vp, i32, u64, sz = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t
     lib.lf_default_params.argtypes = [P(lf_params)]
     lib.lf_default_params.restype = None
+    lib.lf_default_params_no_ut.argtypes = [P(lf_params)]
+    lib.lf_default_params_no_ut.restype = None
     lib.lf_check_batch.argtypes = [P(lf_batch)]
     lib.lf_create.argtypes = [P(lf_geometry), P(lf_params), sz, P(vp)]
     lib.lf_upload_events.argtypes = [vp, P(lf_batch), vp, P(u64)]
@@ -164,14 +171,19 @@ def _arr(a, dtype) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ C names
-def lf_default_params() -> dict:
+def lf_default_params(no_ut: bool = False) -> dict:
+    """The library's defaults: the Forward column, or (no_ut) the Forward no-UT column."""
     p = lf_params()
-    lib().lf_default_params(ctypes.byref(p))
-    d = {n: getattr(p, n) for n in _PARAM_FLOATS}
-    d["C_nhits"] = list(p.C_nhits)
-    d["n_hits_window"] = p.n_hits_window
-    d["n_triplets"] = p.n_triplets
+    (lib().lf_default_params_no_ut if no_ut else lib().lf_default_params)(ctypes.byref(p))
+    d = {}
+    for n, _ in lf_params._fields_:
+        v = getattr(p, n)
+        d[n] = list(v) if n in _PARAM_ARRAYS else v
     return d
+
+
+def lf_default_params_no_ut() -> dict:
+    return lf_default_params(no_ut=True)
 
 
 def make_geometry(world: dict) -> lf_geometry:
@@ -191,12 +203,15 @@ def make_geometry(world: dict) -> lf_geometry:
 
 
 def make_params(params: dict | None = None) -> lf_params:
+    """Defaults (the no-UT column when params sets velo_only) overridden by params."""
     p = lf_params()
-    lib().lf_default_params(ctypes.byref(p))
+    no_ut = bool((params or {}).get("velo_only", 0))
+    (lib().lf_default_params_no_ut if no_ut else lib().lf_default_params)(ctypes.byref(p))
     for k, v in (params or {}).items():
-        if k == "C_nhits":
-            for i in range(4):
-                p.C_nhits[i] = v[i]
+        if k in _PARAM_ARRAYS:
+            arr = getattr(p, k)
+            for i in range(len(arr)):
+                arr[i] = v[i]
         else:
             setattr(p, k, v)
     return p

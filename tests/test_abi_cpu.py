@@ -48,6 +48,26 @@ def test_default_params_match_paper(lf):
             assert f32(d[k]) == f32(v), k
 
 
+def test_default_no_ut_params_match_paper(lf):
+    d = lf.lf_default_params(no_ut=True)
+    f32 = np.float32
+    n = 0
+    with open(pins.GOLDEN_NO_UT) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split("|")[0].split()
+            got = d["noUT_c"][int(k[6:])] if k.startswith("noUT_c") else d[k]
+            assert f32(got) == f32(float(v)), k
+            n += 1
+    assert n >= 20
+    # every field the no-UT column leaves alone keeps the Forward default
+    fwd = lf.lf_default_params()
+    for k in ("K_first", "K_last", "C_nhits", "T_uv_floor"):
+        assert d[k] == fwd[k], k
+
+
 def test_check_batch_accepts_generated(lf):
     lf.lf_check_batch(lfgen.generate("nominal", n_events=2))
     lf.lf_check_batch(lfgen.select_events(lfgen.generate("single"), []))

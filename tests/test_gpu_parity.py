@@ -181,6 +181,69 @@ def test_work_counters_match_oracle():
     say(f"    {wc}")
 
 
+# ---- no-UT tuning: VELO-only input, two windows per layer, per-side seeding ----
+NO_UT = {"velo_only": 1}
+
+
+def test_no_ut_single_and_nominal():
+    _check_all_modes(lfgen.generate("single"), "single no-UT", NO_UT)
+    _check_all_modes(lfgen.generate("nominal", n_events=10), "nominal[10] no-UT", NO_UT)
+
+
+def test_no_ut_stress_and_uneven():
+    _check_all_modes(lfgen.generate("stress", n_events=2), "stress[2] no-UT", NO_UT)
+    ev = lfgen.generate("uneven", n_events=40)
+    parts = [lfgen.select_events(ev, range(0, 20)), lfgen.select_events(ev, []),
+             lfgen.select_events(ev, range(20, 40))]
+    _check_all_modes(lfgen.concat(parts), "uneven[40] no-UT", NO_UT)
+
+
+@pytest.mark.parametrize("params", [
+    {"n_hits_window": 32},
+    {"n_hits_window": 17, "n_triplets": 5},
+    {"noUT_overlap": 40.0, "n_triplets": 32, "T_triplet": 6.0},
+    {"noUT_p_min": 3.0, "noUT_pt_min": 0.5, "magtol_max": 25.0, "magtol_const": 25.0, "magtol_min": 25.0},
+], ids=["w32", "w17_t5", "overlap40_t32", "wide"])
+def test_no_ut_parameter_variants(params):
+    _check_all_modes(lfgen.generate("nominal", n_events=4), "nominal[4] no-UT", dict(NO_UT, **params))
+
+
+def test_no_ut_whole_bucket_and_per_hit_geometry():
+    ev = lfgen.generate("single", seed=7, n_events=6, n_particles=8, n_noise=20, p_min=1.5, p_max=20.0)
+    big = dict(NO_UT, noUT_c=[1e9] * 8, noUT_overlap=1e7, uv_halfwidth=1e7, n_hits_window=64, n_triplets=7,
+               T_triplet=40.0)
+    _check_all_modes(ev, "tiny whole-bucket no-UT", big)
+    ev = _jitter(lfgen.generate("nominal", n_events=4), 1.5, 0.02, seed=12)
+    _check_all_modes(ev, "nominal[4] no-UT, per-hit z and slope", NO_UT)
+
+
+def test_no_ut_work_counters_match_oracle():
+    from paper_2402_14670_amd import lf
+    ev = lfgen.generate("nominal", n_events=6)
+    o = oracle.run(ev, W, NO_UT, debug=True)
+    n0 = (o["win"][:, :, 1] - o["win"][:, :, 0]).astype(np.int64)
+    n1 = (o["win1"][:, :, 1] - o["win1"][:, :, 0]).astype(np.int64)
+    ctx = lf.lf_create(W, NO_UT)
+    try:
+        bid = lf.lf_upload_events(ctx, ev)
+        say("[gpu] work counters, nominal[6] no-UT")
+        wc = lf.lf_work_counts(ctx, bid)
+        got = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks)
+    finally:
+        lf.lf_destroy(ctx)
+    compare(oracle.run(ev, W, NO_UT), got, label="counting build no-UT")
+    c = o["counts"]
+    assert wc["staged_hits"] == int(n0.sum() + n1.sum())
+    assert wc["pairs_all"] == int(sum((n[:, 0] * n[:, 8] + n[:, 3] * n[:, 11]).sum() for n in (n0, n1)))
+    assert wc["seed_items"] == int(sum((n[:, 0] + n[:, 3]).sum() for n in (n0, n1)))
+    assert wc["doublets"] == int(c[:, 1].sum())
+    assert wc["triplets"] == int(c[:, 2].sum())
+    assert wc["kept"] == int(np.minimum(c[:, 2], 20).sum())
+    assert wc["accepted"] == int(c[:, 3].sum())
+    assert wc["found"] == int(o["found"].sum())
+    say(f"    {wc}")
+
+
 def test_determinism_and_event_order():
     ev = lfgen.generate("nominal", n_events=8)
     say("[gpu] determinism: batched twice, then reversed event order")
