@@ -213,6 +213,31 @@ def cpu_baseline(ev, world, min_seconds, gpu_out):
                 events_equal_gpu=int(ok.sum()), events_checked=int(ok.size))
 
 
+def truth_summary(ev, out) -> dict:
+    from lfgen import truth
+    ph = truth.physics(ev, out, p_min=5.0)
+    return {"efficiency_p_gt_5GeV": ph["efficiency"], "ghost_rate": ph["ghost_rate"],
+            "qop_resolution": ph["qop_resolution"], "reconstructible_p_gt_5GeV": ph["n_reconstructible"]}
+
+
+def no_ut_mode(lf, world, ev, stream, steps, warmup):
+    """The same batch under the paper's no-UT tuning (VELO-only input: two
+    windows per layer, 64 hits each, per-side seeding), batched mode."""
+    from lfgen import truth
+    ctx = lf.lf_create(world, lf.lf_default_params(no_ut=True))
+    try:
+        bid = lf.lf_upload_events(ctx, ev, stream.cuda_stream)
+        ms, _ = time_mode(lf, ctx, bid, lf.LF_MODE_BATCHED, max(5, steps // 2), warmup, stream)
+        out = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
+    finally:
+        lf.lf_destroy(ctx)
+    ph = truth.physics(ev, out, p_min=5.0)
+    print(f"bench: no-UT      {ms:8.3f} ms/step  {ev.n_events / ms * 1e3:12.0f} events/s", file=sys.stderr, flush=True)
+    return {"ms_per_step": round(ms, 4), "events_per_s": round(ev.n_events / ms * 1e3, 1),
+            "found_tracks": ph["n_found"], "efficiency_p_gt_5GeV": round(ph["efficiency"], 5),
+            "ghost_rate": round(ph["ghost_rate"], 5)}
+
+
 def end_to_end(lf, ctx, ev, stream, reps=3):
     """The whole batch from host buffers: validation and upload, the hot path,
     and the download of the results (host link included)."""
@@ -334,6 +359,7 @@ def main():
     work = lf.lf_work_counts(ctx, bid, stream.cuda_stream)
     out = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
     e2e = end_to_end(lf, ctx, ev, stream)
+    no_ut = no_ut_mode(lf, world, ev, stream, args.steps, args.warmup)
     print(f"bench: end to end {e2e['ms_per_batch']:8.3f} ms/batch  {e2e['events_per_s']:12.0f} events/s",
           file=sys.stderr, flush=True)
     serve = serving(lf, ctx, ev, out, args.serve_requests) if args.serve_requests else None
@@ -369,6 +395,8 @@ def main():
         "autotune": ({m: {k: v for k, v in c.items() if k != "mode"} for m, c in tuned["per_mode"].items()}
                      if tuned else None),
         "found_tracks": int(out["found"].sum()),
+        "physics": {k: round(v, 5) if isinstance(v, float) else v
+                    for k, v in truth_summary(ev, out).items()},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": traffic,
                      "kernel": KERNEL, "ops_per_launch": ops,
@@ -384,6 +412,7 @@ def main():
                        if serve else None),
         "serving": serve,
         "end_to_end": e2e,
+        "no_ut": no_ut,
     }
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(ev, world, args.cpu_seconds, out)
