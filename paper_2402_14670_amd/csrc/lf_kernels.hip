@@ -118,12 +118,9 @@ __device__ __forceinline__ void bounds_sorted(const float *v, int n, float klo, 
 // RN(val(j) - xe) is non-decreasing too, so d falls up to the first j with
 // val(j) >= xe and rises after it: only that index, its left neighbour and
 // the plateau of equal d ending at the left neighbour can hold the answer.
-template <int NMAX, class Val>
-__device__ __forceinline__ int closest_sorted(Val val, int n, float xe, float &bd) {
-    int p = 0;
-#pragma unroll
-    for (int s = NMAX; s > 0; s >>= 1)
-        if (p + s <= n && val(p + s - 1) < xe) p += s;
+// Given p = #{j < n: val(j) < xe}: the closest index as described above.
+template <class Val>
+__device__ __forceinline__ int closest_finish(Val val, int n, float xe, int p, float &bd) {
     int best = p;
     float d = p < n ? fabsf(val(p) - xe) : INFINITY;
     if (p > 0) {
@@ -137,6 +134,32 @@ __device__ __forceinline__ int closest_sorted(Val val, int n, float xe, float &b
     if (!(d < INFINITY)) return -1;
     bd = d;
     return best;
+}
+
+template <int NMAX, class Val>
+__device__ __forceinline__ int closest_sorted(Val val, int n, float xe, float &bd) {
+    int p = 0;
+#pragma unroll
+    for (int s = NMAX; s > 0; s >>= 1)
+        if (p + s <= n && val(p + s - 1) < xe) p += s;
+    return closest_finish(val, n, xe, p, bd);
+}
+
+// Two independent sorted searches advanced step by step together, so that
+// their dependent LDS reads overlap.
+template <int NMAX, class ValA, class ValB>
+__device__ __forceinline__ void closest_sorted2(ValA va, int na, float xa, int &ba, float &da,
+                                                ValB vb, int nb, float xb, int &bb, float &db) {
+    int pa = 0, pb = 0;
+#pragma unroll
+    for (int s = NMAX; s > 0; s >>= 1) {
+        const bool ta = pa + s <= na && va(pa + s - 1) < xa;
+        const bool tb = pb + s <= nb && vb(pb + s - 1) < xb;
+        if (ta) pa += s;
+        if (tb) pb += s;
+    }
+    ba = closest_finish(va, na, xa, pa, da);
+    bb = closest_finish(vb, nb, xb, pb, db);
 }
 
 // The same by linear scan, for windows whose values are not sorted.
@@ -592,31 +615,73 @@ struct Track {
         // ---- extension: lanes = (candidate, missing layer) ----
         const float T_uv0 = P->T_uv_scale * (fabsf(tx_in) + fabsf(ty_in));
         const float T_uv = T_uv0 < P->T_uv_floor ? P->T_uv_floor : T_uv0;
-        for (int it = lane; it < nL * NSLOT; it += WAVE) {
-            const int r = it / NSLOT, slot = it - NSLOT * (it / NSLOT);
-            const uint32_t kr = (uint32_t)L.tk[r];
-            const int s = (int)((kr >> 12) & 1u), sd = NS > 1 ? (int)((kr >> 13) & 1u) : 0;
-            int l;
-            if (slot < 3) l = s ? 4 * slot : 4 * slot + 3;
-            else l = 4 * ((slot - 3) >> 1) + 1 + ((slot - 3) & 1);
-            const float a = L.ca[r], b = L.cb[r], c = L.cc[r];
-            const float u = P->z[l] - P->z_ref;
-            const float xe = a + b * u + c * g_of(u, dR);
-            const int n = L.wlen[sd][l];
-            const float *wxl = L.wx[sd][l];
-            float bd = INFINITY;
-            if (slot < 3) {
-                const int best = closest_sorted<NW>([wxl](int j) { return wxl[j]; }, n, xe, bd);
-                if (best >= 0 && bd * bd < P->T_x) L.ch[r][l] = (int8_t)best;
-            } else {
-                // the hit's x at y = 0 moved along its fibre to the predicted y; with a
-                // common stereo slope in the window these values stay sorted
-                const float yp = y_in + ty_in * (P->z[l] - P->z_in);
-                const float *wdl = L.wd[sd][uv_index(l)];
-                auto val = [wxl, wdl, yp](int j) { return wxl[j] + wdl[j] * yp; };
-                const int best = ((dvar >> (NL * sd + l)) & 1u) ? closest_scan(val, n, xe, bd)
-                                                                : closest_sorted<NW>(val, n, xe, bd);
-                if (best >= 0 && bd * bd < T_uv) L.ch[r][l] = (int8_t)best;
+        // item it = (candidate it / 9, slot it % 9): the layer, the model's
+        // prediction there and the search values
+        struct Ext {
+            int r, l, n, sd;
+            bool uv, scan;
+            float xe, yp;
+            const float *wx, *wd;
+        };
+        auto ext_item = [&](int it) {
+            Ext e;
+            e.r = it / NSLOT;
+            const int slot = it - NSLOT * (it / NSLOT);
+            const uint32_t kr = (uint32_t)L.tk[e.r];
+            const int s = (int)((kr >> 12) & 1u);
+            e.sd = NS > 1 ? (int)((kr >> 13) & 1u) : 0;
+            if (slot < 3) e.l = s ? 4 * slot : 4 * slot + 3;
+            else e.l = 4 * ((slot - 3) >> 1) + 1 + ((slot - 3) & 1);
+            const float u = P->z[e.l] - P->z_ref;
+            e.xe = L.ca[e.r] + L.cb[e.r] * u + L.cc[e.r] * g_of(u, dR);
+            e.n = L.wlen[e.sd][e.l];
+            e.wx = L.wx[e.sd][e.l];
+            // one search for x and u/v slots alike: a u/v hit's x at y = 0 is
+            // moved along its fibre to the predicted y; an x hit adds +-0, which
+            // changes no distance and no comparison.  With a common stereo slope
+            // in the window the values stay sorted.
+            e.uv = slot >= 3;
+            e.yp = e.uv ? y_in + ty_in * (P->z[e.l] - P->z_in) : 0.0f;
+            e.wd = L.wd[e.sd][e.uv ? uv_index(e.l) : 0];
+            e.scan = e.uv && ((dvar >> (NL * e.sd + e.l)) & 1u);
+            return e;
+        };
+        auto ext_val = [](const Ext &e) {
+            const float *wx = e.wx, *wd = e.wd;
+            const float yp = e.yp;
+            const bool uv = e.uv;
+            return [wx, wd, yp, uv](int j) { return wx[j] + (uv ? wd[j] : 0.0f) * yp; };
+        };
+        auto ext_keep = [&](const Ext &e, int best, float bd) {
+            if (best >= 0 && bd * bd < (e.uv ? T_uv : P->T_x)) L.ch[e.r][e.l] = (int8_t)best;
+        };
+        const int n_items = nL * NSLOT;
+        if (n_items <= WAVE) {
+            if (lane < n_items) {
+                const Ext e = ext_item(lane);
+                float bd = INFINITY;
+                const int best = e.scan ? closest_scan(ext_val(e), e.n, e.xe, bd)
+                                        : closest_sorted<NW>(ext_val(e), e.n, e.xe, bd);
+                ext_keep(e, best, bd);
+            }
+        } else {
+            // two items per lane, their searches interleaved
+            for (int it = lane; it < n_items; it += 2 * WAVE) {
+                const bool hb = it + WAVE < n_items;
+                const Ext ea = ext_item(it);
+                const Ext eb = ext_item(hb ? it + WAVE : it);
+                float da = INFINITY, db = INFINITY;
+                int ba, bb;
+                if (!ea.scan && !eb.scan) {
+                    closest_sorted2<NW>(ext_val(ea), ea.n, ea.xe, ba, da, ext_val(eb), eb.n, eb.xe, bb, db);
+                } else {
+                    ba = ea.scan ? closest_scan(ext_val(ea), ea.n, ea.xe, da)
+                                 : closest_sorted<NW>(ext_val(ea), ea.n, ea.xe, da);
+                    bb = eb.scan ? closest_scan(ext_val(eb), eb.n, eb.xe, db)
+                                 : closest_sorted<NW>(ext_val(eb), eb.n, eb.xe, db);
+                }
+                ext_keep(ea, ba, da);
+                if (hb) ext_keep(eb, bb, db);
             }
         }
         wave_sync();
