@@ -356,6 +356,26 @@ def main():
     if tuned:
         c = tuned["per_mode"]["batched"]
         lf.lf_set_exec(ctx, waves_per_block=c["waves_per_block"])
+    # the workload as a sequence of 4 resident sub-batches, replayed from one HIP graph
+    parts = [lfgen.select_events(ev, range(ev.n_events * k // 4, ev.n_events * (k + 1) // 4)) for k in range(4)]
+    sub = [lf.lf_upload_events(ctx, part, stream.cuda_stream) for part in parts if part.n_events]
+    g = lf.lf_graph_create(ctx, sub, "batched")
+    try:
+        lf.lf_graph_launch(ctx, g, stream.cuda_stream)
+        torch.cuda.synchronize()
+        st_, en_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        st_.record(stream)
+        for _ in range(args.steps):
+            lf.lf_graph_launch(ctx, g, stream.cuda_stream)
+        en_.record(stream)
+        torch.cuda.synchronize()
+        res["batched_graph_4_batches"] = st_.elapsed_time(en_) / args.steps
+    finally:
+        lf.lf_graph_destroy(g)
+        for b in sub:
+            lf.lf_release_batch(ctx, b)
+    print(f"bench: {'graph x4':10s} {res['batched_graph_4_batches']:8.3f} ms/step  "
+          f"{ev.n_events / res['batched_graph_4_batches'] * 1e3:12.0f} events/s", file=sys.stderr, flush=True)
     work = lf.lf_work_counts(ctx, bid, stream.cuda_stream)
     out = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
     e2e = end_to_end(lf, ctx, ev, stream)
@@ -390,7 +410,8 @@ def main():
                    "events": ev.n_events, "input_tracks": ev.n_tracks, "hits": ev.n_hits,
                    "n_hits_window": 32, "n_triplets": 12},
         "modes": {m: {"ms_per_step": round(v, 4), "events_per_s": round(ev.n_events / v * 1e3, 1),
-                      "input_tracks_per_s": round(ev.n_tracks / v * 1e3, 1)} for m, v in res.items()},
+                      "input_tracks_per_s": round(ev.n_tracks / v * 1e3, 1),
+                      "hbm_frac": round(nbytes / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)} for m, v in res.items()},
         "batched_over_plain": round(res["plain"] / ms, 2) if "plain" in res else None,
         "autotune": ({m: {k: v for k, v in c.items() if k != "mode"} for m, c in tuned["per_mode"].items()}
                      if tuned else None),
