@@ -83,6 +83,9 @@ def parse():
                     help="comma-separated subset of batched,persistent,plain to time (batched is always timed)")
     ap.add_argument("--serve-requests", type=int, default=200000,
                     help="requests per serving run (0 skips the serving runs)")
+    ap.add_argument("--variants", default="no_ut,paper",
+                    help="method variants timed after the main modes: no_ut (VELO-only input), paper "
+                         "(paper-form field and momentum); 'none' for neither")
     ap.add_argument("--scan-window", action="store_true",
                     help="instead of the throughput line: events/s and physics efficiency of the batched mode "
                          "for n_hits_window = 16, 32, 48, 64 (one JSON line)")
@@ -238,6 +241,41 @@ def no_ut_mode(lf, world, ev, stream, steps, warmup):
             "ghost_rate": round(ph["ghost_rate"], 5)}
 
 
+def paper_field_mode(lf, workload, n_events, stream, steps, warmup):
+    """The same workload generated in the paper-form field (sqrt-normalised
+    pt-kick, an integrated field that depends on the entry slopes and the
+    bending, a falling tail) and followed with the kick solved for the
+    windows and q/p from the fitted parametrisation F(tx, ty, dSlope);
+    batched mode.  The q/p resolution is also given for F replaced by its
+    constant term."""
+    import lfgen
+    from lfgen import truth
+    ev = lfgen.generate(workload, field="paper", **({"n_events": n_events} if n_events else {}))
+    world = lfgen.world("paper")
+    res = {}
+    for label, w in (("fitted", world), ("constant", dict(world, F_coef=[lfgen.KICK] + [0.0] * 49))):
+        ctx = lf.lf_create(w)
+        try:
+            bid = lf.lf_upload_events(ctx, ev, stream.cuda_stream)
+            if label == "fitted":
+                ms, _ = time_mode(lf, ctx, bid, lf.LF_MODE_BATCHED, max(5, steps // 2), warmup, stream)
+            else:
+                lf.lf_find_tracks(ctx, bid, lf.LF_MODE_BATCHED, stream.cuda_stream)
+            res[label] = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
+        finally:
+            lf.lf_destroy(ctx)
+    ph = truth.physics(ev, res["fitted"], p_min=5.0)
+    ph_c = truth.physics(ev, res["constant"], p_min=5.0)
+    print(f"bench: paper field {ms:8.3f} ms/step  {ev.n_events / ms * 1e3:12.0f} events/s  "
+          f"q/p resolution {ph['qop_resolution']:.4f} (constant F: {ph_c['qop_resolution']:.4f})",
+          file=sys.stderr, flush=True)
+    return {"ms_per_step": round(ms, 4), "events_per_s": round(ev.n_events / ms * 1e3, 1),
+            "events": ev.n_events, "input_tracks": ev.n_tracks, "hits": ev.n_hits,
+            "found_tracks": ph["n_found"], "efficiency_p_gt_5GeV": round(ph["efficiency"], 5),
+            "ghost_rate": round(ph["ghost_rate"], 5), "qop_resolution": round(ph["qop_resolution"], 5),
+            "qop_resolution_constant_F": round(ph_c["qop_resolution"], 5)}
+
+
 def end_to_end(lf, ctx, ev, stream, reps=3):
     """The whole batch from host buffers: validation and upload, the hot path,
     and the download of the results (host link included)."""
@@ -379,7 +417,10 @@ def main():
     work = lf.lf_work_counts(ctx, bid, stream.cuda_stream)
     out = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
     e2e = end_to_end(lf, ctx, ev, stream)
-    no_ut = no_ut_mode(lf, world, ev, stream, args.steps, args.warmup)
+    variants = set(args.variants.split(","))
+    no_ut = no_ut_mode(lf, world, ev, stream, args.steps, args.warmup) if "no_ut" in variants else None
+    paper = (paper_field_mode(lf, args.workload, args.events, stream, args.steps, args.warmup)
+             if "paper" in variants else None)
     print(f"bench: end to end {e2e['ms_per_batch']:8.3f} ms/batch  {e2e['events_per_s']:12.0f} events/s",
           file=sys.stderr, flush=True)
     serve = serving(lf, ctx, ev, out, args.serve_requests) if args.serve_requests else None
@@ -434,6 +475,7 @@ def main():
         "serving": serve,
         "end_to_end": e2e,
         "no_ut": no_ut,
+        "paper_field": paper,
     }
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(ev, world, args.cpu_seconds, out)

@@ -83,10 +83,28 @@ enum {
 
 /* Detector and field description.  Layers 0..11 are three stations of
  * x-u-v-x planes: x layers 0,3,4,7,8,11 and stereo layers 1,2,5,6,9,10
- * (Context section).  The field enters through the pt-kick at z_mag with
- * slope kick dtx = kick * q/p ("Defining the search windows") and the
- * x(z) model of the "Propagation" section with residual curvature kappa*dtx
- * about z_T and cubic term dRatio. */
+ * (Context section).  The field enters through the pt-kick at z_mag ("Defining
+ * the search windows") and the x(z) model of the "Propagation" section with
+ * residual curvature kappa*dtx about z_T and cubic term dRatio:
+ *   x(z) = x_mag + (tx + dtx)(z - z_mag) + kappa dtx (z - z_T)^2 (1 + dRatio (z - z_T)).
+ * Two forms of the kick and of the momentum (field_form):
+ *   0: dtx = kick * q/p, and q/p = (tx(z_T) - tx) / kick from the fit;
+ *   1: the sqrt-normalised pt-kick equation s_f - s_i = (q/p) F with
+ *      s = tx / sqrt(1 + tx^2 + ty^2) and the integrated field F the
+ *      fourth-order polynomial in dSlope of "Calculation of momentum and
+ *      track states", F = sum_{i=0..4} c_i dSlope^i, evaluated as
+ *      c0 + d (c1 + d (c2 + d (c3 + d c4))), whose coefficients are 2D
+ *      polynomials of the input slopes:
+ *        c_i = sum_{j=0..9} F_coef[i][j] m_j          (i even)
+ *        c_i = tx * sum_{j=0..5} F_coef[i][j] m_j     (i odd; j = 6..9 unused)
+ *      m = (1, tx2, ty2, tx2^2, tx2 ty2, ty2^2, tx2^3, tx2^2 ty2, tx2 ty2^2,
+ *      ty2^3), tx2 = tx^2, ty2 = ty^2, sums in order of j.  For the windows
+ *      the equation is solved for the slope after the magnet with F at
+ *      dSlope = 0 and then twice at the previous solution's slope change
+ *      (ty unchanged); a track whose kick has no solution (|s_f| >= 1) gets
+ *      no windows and is not found.  The output q/p uses the fitted slopes at
+ *      z_T and F at dSlope = tx(z_T) - tx.  With velo_only the windows are
+ *      straight lines in either form. */
 typedef struct {
     float z[LF_NLAYERS];     /* z of each layer plane */
     float dxdy[LF_NLAYERS];  /* stereo tangent (0 for x layers, +-tan 5 deg for u/v) */
@@ -94,10 +112,12 @@ typedef struct {
     float z_mag;             /* bending plane z_bending */
     float z_ref;             /* reference plane of the track model (8520 mm) */
     float z_T;               /* plane where the post-magnet slope is read for q/p */
-    float kick;              /* dtx = kick * q/p */
+    float kick;              /* field_form 0: dtx = kick * q/p (non-zero) */
     float kappa;             /* residual curvature per unit dtx */
     float dRatio;            /* cubic term of x(z) */
     int32_t polarity;        /* +1: q > 0 bends towards +x; -1 the opposite */
+    int32_t field_form;      /* 0: linear kick; 1: sqrt-normalised pt-kick with F (above) */
+    float F_coef[5][10];     /* field_form 1: coefficients of F (finite; zero for form 0) */
 } lf_geometry;
 
 /* Tunable parameters.  Defaults (lf_default_params) are the "Forward"

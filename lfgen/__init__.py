@@ -14,6 +14,7 @@ Usage::
 from __future__ import annotations
 
 import ctypes
+import functools
 import math
 import os
 import subprocess
@@ -34,13 +35,28 @@ LAYER_DXDY = tuple(math.tan(math.radians(a)) for a in STEREO_DEG)
 X_LAYERS = (0, 3, 4, 7, 8, 11)
 UV_LAYERS = (1, 2, 5, 6, 9, 10)
 
-# Toy field: kick at Z_MAG with dtx = KICK * q/p; residual curvature
-# KAPPA * dtx * (z - Z_T)^2 after the magnet.  Upstream states at Z_UP.
+# Toy field: kick at Z_MAG changing the slope by dtx; residual curvature
+# KAPPA * dtx * (z - Z_T)^2 (1 + dRatio (z - Z_T)) after the magnet.
+# Upstream states at Z_UP.  Two kicks (lfgen.c): the linear toy kick
+# dtx = KICK * q/p with a constant B_y tail ("toy"), and the sqrt-normalised
+# pt-kick with an integrated field that depends on the entry slopes and on
+# the bending, and a linearly falling tail ("paper").
 Z_UP = 2700.0
 Z_MAG = 5200.0
 Z_T = 8500.0
 KICK = 1.2
 KAPPA = 2e-5
+# Reference plane of the x(z) model; the paper fields expand their falling
+# tail about it (z_T = Z_REF), so the model of the method is exact for them.
+Z_REF = 8520.0
+FIELDS = {
+    "toy": dict(field_form=0, dRatio=0.0, bl0=KICK, bl_tx2=0.0, bl_ty2=0.0, bl_q2=0.0),
+    "paper": dict(field_form=1, dRatio=-2.0e-4, bl0=KICK, bl_tx2=-0.25, bl_ty2=-0.6, bl_q2=-0.15,
+                  z_T=Z_REF),
+    # the sqrt-normalised pt-kick with a constant integrated field: a paper
+    # field whose momentum parametrisation is exactly F = KICK
+    "kick": dict(field_form=1, dRatio=-2.0e-4, bl0=KICK, bl_tx2=0.0, bl_ty2=0.0, bl_q2=0.0, z_T=Z_REF),
+}
 
 
 class _Cfg(ctypes.Structure):
@@ -66,6 +82,9 @@ class _Cfg(ctypes.Structure):
         ("z_up", ctypes.c_double), ("z_mag", ctypes.c_double), ("z_T", ctypes.c_double),
         ("kick", ctypes.c_double), ("kappa", ctypes.c_double),
         ("z", ctypes.c_double * NL), ("dxdy", ctypes.c_double * NL),
+        ("field_form", ctypes.c_int32), ("dRatio", ctypes.c_double),
+        ("bl0", ctypes.c_double), ("bl_tx2", ctypes.c_double), ("bl_ty2", ctypes.c_double),
+        ("bl_q2", ctypes.c_double),
     ]
 
 
@@ -172,6 +191,7 @@ def _load():
         lib.lfgen_free.argtypes = [ctypes.c_void_p]
         lib.lfgen_sizes.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_uint64)] * 4
         lib.lfgen_copy.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 19
+        lib.lfgen_kick_many.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int64] + [ctypes.c_void_p] * 6
         _lib = lib
     return _lib
 
@@ -186,20 +206,30 @@ def config(preset: str = "single", **overrides) -> dict:
     return c
 
 
-def generate(preset: str = "single", **overrides) -> Events:
-    """Generate events of a preset (``n_events``/``first_event``/... may be overridden)."""
-    c = config(preset, **overrides)
+def _make_cfg(c: dict, field: str) -> _Cfg:
+    if field not in FIELDS:
+        raise KeyError(f"unknown field {field!r}; have {sorted(FIELDS)}")
     cfg = _Cfg()
     for k, v in c.items():
         if k in ("z", "dxdy"):
             continue
         setattr(cfg, k, v)
     cfg.z_up, cfg.z_mag, cfg.z_T, cfg.kick, cfg.kappa = Z_UP, Z_MAG, Z_T, KICK, KAPPA
+    for k, v in FIELDS[field].items():
+        setattr(cfg, k, v)
     zs = c.get("z", LAYER_Z)
     ds = c.get("dxdy", LAYER_DXDY)
     for i in range(NL):
         cfg.z[i] = zs[i]
         cfg.dxdy[i] = ds[i]
+    return cfg
+
+
+def generate(preset: str = "single", field: str = "toy", **overrides) -> Events:
+    """Generate events of a preset (``n_events``/``first_event``/... may be
+    overridden) in the field ``field`` ("toy" or "paper")."""
+    c = config(preset, **overrides)
+    cfg = _make_cfg(c, field)
     lib = _load()
     h = lib.lfgen_run(ctypes.byref(cfg))
     if not h:
@@ -284,9 +314,76 @@ def select_events(ev: Events, idx) -> Events:
     return concat(parts)
 
 
-def world(**overrides) -> dict:
-    """Detector and field description of the generated events (inputs of the method)."""
-    w = dict(z=list(LAYER_Z), dxdy=list(LAYER_DXDY), z_in=Z_UP, z_mag=Z_MAG, z_T=Z_T, kick=KICK,
-             kappa=KAPPA, dRatio=0.0, polarity=1)
+def kick(tx, ty, qop, field: str = "paper"):
+    """The world's kick over arrays: (slope change d, integrated field BL, forward mask)."""
+    tx, ty, qop = (np.ascontiguousarray(a, dtype=np.float64) for a in (tx, ty, qop))
+    n = tx.size
+    d, bl = np.zeros(n), np.zeros(n)
+    ok = np.zeros(n, np.uint8)
+    cfg = _make_cfg(config("single"), field)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _load().lfgen_kick_many(ctypes.byref(cfg), n, p(tx), p(ty), p(qop), p(d), p(bl), p(ok))
+    return d, bl, ok.astype(bool)
+
+
+# Momentum parametrisation F(tx, ty, dSlope) = sum_i c_i(tx, ty) dSlope^i,
+# i = 0..4, of the paper's "Calculation of momentum and track states", as a
+# table F_coef[i][j]: c_i = sum_j F_coef[i][j] m_j for even i and
+# c_i = tx * sum_{j<6} F_coef[i][j] m_j for odd i, with the monomials
+# m = (1, tx2, ty2, tx2^2, tx2 ty2, ty2^2, tx2^3, tx2^2 ty2, tx2 ty2^2, ty2^3),
+# tx2 = tx^2, ty2 = ty^2: total degree <= 6, even in ty, and even (odd) in
+# tx for even (odd) powers of dSlope -- the symmetries of a field mirror-
+# symmetric in x and y.
+FIT_P_MIN = 1.5
+FIT_SAMPLES = 400_000
+FIT_SEED = 7
+
+
+@functools.lru_cache(maxsize=None)
+def field_table(field: str = "paper") -> tuple:
+    """F_coef (5 x 10, row-major, float32 values) fitted by least squares on
+    toy tracks that populate the slope acceptance evenly with a flat q/p
+    spectrum (|p| >= FIT_P_MIN) and reach the first and last SciFi layers
+    inside the acceptance -- the calibration of the paper's momentum
+    parametrisation, done for this synthetic field."""
+    b = _BASE
+    rng = np.random.default_rng(FIT_SEED)
+    n = FIT_SAMPLES
+    tx = rng.uniform(-b["tx_max"], b["tx_max"], n)
+    ty = rng.uniform(-b["ty_max"], b["ty_max"], n)
+    qop = rng.uniform(-1.0 / FIT_P_MIN, 1.0 / FIT_P_MIN, n)
+    d, bl, ok = kick(tx, ty, qop, field)
+    fc = FIELDS[field]
+    zT = fc.get("z_T", Z_T)
+    for z in (LAYER_Z[0], LAYER_Z[-1]):
+        x = tx * Z_MAG + (tx + d) * (z - Z_MAG) + KAPPA * d * (z - zT) ** 2 * (1.0 + fc["dRatio"] * (z - zT))
+        ok &= (np.abs(x) < b["x_acc"]) & (np.abs(ty * z) < b["y_acc"])
+    tx, ty, d, bl = tx[ok], ty[ok], d[ok], bl[ok]
+    x2, y2 = tx * tx, ty * ty
+    m = [np.ones_like(tx), x2, y2, x2 * x2, x2 * y2, y2 * y2, x2 * x2 * x2, x2 * x2 * y2, x2 * y2 * y2,
+         y2 * y2 * y2]
+    cols, where = [], []
+    for i in range(5):
+        for j in range(10 if i % 2 == 0 else 6):
+            cols.append(m[j] * d ** i * (tx if i % 2 else 1.0))
+            where.append((i, j))
+    coef, *_ = np.linalg.lstsq(np.stack(cols, 1), bl, rcond=None)
+    table = np.zeros((5, 10), np.float32)
+    for (i, j), v in zip(where, coef):
+        table[i, j] = v
+    return tuple(float(v) for v in table.ravel())
+
+
+def world(field: str = "toy", **overrides) -> dict:
+    """Detector and field description of events generated in ``field``
+    (inputs of the method): geometry, the linear-kick constants, the cubic
+    term and, for the paper field, the fitted momentum parametrisation."""
+    if field not in FIELDS:
+        raise KeyError(f"unknown field {field!r}; have {sorted(FIELDS)}")
+    fc = FIELDS[field]
+    w = dict(z=list(LAYER_Z), dxdy=list(LAYER_DXDY), z_in=Z_UP, z_mag=Z_MAG, z_T=fc.get("z_T", Z_T),
+             kick=KICK, kappa=KAPPA, dRatio=fc["dRatio"], polarity=1, field_form=fc["field_form"])
+    if fc["field_form"] == 1:
+        w["F_coef"] = list(field_table(field))
     w.update(overrides)
     return w

@@ -11,11 +11,20 @@
  * Detector layout follows the paper's Context section (three stations of
  * x-u-v-x layers, stereo +-5 degrees) and the "Defining the search windows"
  * subsection (about 400 hits per layer, y>0 / y<0 halves).  The field is a
- * toy: an instantaneous kick dtx = kick * q/p at z_mag, then
- *   x(z) = tx*z_mag + (tx + dtx)*(z - z_mag) + kappa*dtx*(z - z_T)^2,
- *   y(z) = ty*z,
- * which is the track model of the paper's "Propagation" section with a
- * constant B_y tail (dRatio = 0).
+ * toy: an instantaneous kick at z_mag that changes the slope from tx to
+ * tx_f, then
+ *   x(z) = tx*z_mag + tx_f*(z - z_mag) + kappa*d*(z - z_T)^2 (1 + dRatio (z - z_T)),
+ *   y(z) = ty*z,   d = tx_f - tx,
+ * which is the track model of the paper's "Propagation" section (dRatio = 0:
+ * a constant B_y tail; dRatio < 0: a linearly falling one).  Two kicks:
+ *   field_form 0: tx_f = tx + kick * q/p;
+ *   field_form 1: the sqrt-normalised pt-kick equation of "Defining the search
+ *     windows", s_f = s_i + (q/p) BL with s = tx / sqrt(1 + tx^2 + ty^2) and
+ *     ty unchanged, where the integrated field BL = bl0 (1 + bl_tx2 tx^2 +
+ *     bl_ty2 ty^2 + bl_q2 (bl0 q/p)^2) falls for steep and for strongly
+ *     bending tracks, so that the momentum parametrisation F(tx, ty, dSlope)
+ *     of "Calculation of momentum" has work to do.  A particle with
+ *     |s_f| >= 1 curls up in the magnet and leaves no SciFi hit.
  *
  * Random numbers: xoshiro256** (Blackman & Vigna, 2018) seeded per event by
  * SplitMix64 (Steele, Lea & Flood, 2014); uniforms are (next >> 11) * 2^-53;
@@ -51,6 +60,9 @@ typedef struct {
     double x_acc, y_acc;      /* acceptance |x| < x_acc, |y| < y_acc (mm) */
     double z_up, z_mag, z_T, kick, kappa;
     double z[LFG_NL], dxdy[LFG_NL];
+    int32_t field_form;       /* 0: linear kick; 1: sqrt-normalised pt-kick */
+    double dRatio;            /* cubic term of the post-magnet x(z) */
+    double bl0, bl_tx2, bl_ty2, bl_q2;   /* integrated field of field_form 1 */
 } lfgen_config;
 
 typedef struct {
@@ -156,6 +168,27 @@ static int cmp_rawhit(const void *a, const void *b) {
 
 typedef struct { double p, q, tx, ty; } kin;
 
+/* Slope change d = tx_f - tx of the kick for entry slopes (tx, ty), charge q
+ * and momentum p; returns 0 when the particle does not leave the magnet
+ * forwards (field_form 1, |s_f| >= 1).  *bl receives the integrated field
+ * the particle saw (kick for form 0). */
+int lfgen_kick(const lfgen_config *c, double tx, double ty, double q, double p, double *d, double *bl) {
+    if (c->field_form == 0) {
+        *bl = c->kick;
+        *d = c->kick * q / p;
+        return 1;
+    }
+    double qop = q / p;
+    double b = c->bl0 * qop;
+    double BL = c->bl0 * (1.0 + c->bl_tx2 * tx * tx + c->bl_ty2 * ty * ty + c->bl_q2 * b * b);
+    double si = tx / sqrt(1.0 + tx * tx + ty * ty);
+    double sf = si + qop * BL;
+    *bl = BL;
+    if (!(fabs(sf) < 1.0)) { *d = 0.0; return 0; }
+    *d = sf * sqrt((1.0 + ty * ty) / (1.0 - sf * sf)) - tx;
+    return 1;
+}
+
 static kin draw_kin(rng_t *r, const lfgen_config *c) {
     kin k;
     for (;;) {
@@ -166,6 +199,17 @@ static kin draw_kin(rng_t *r, const lfgen_config *c) {
         double t2 = k.tx * k.tx + k.ty * k.ty;
         double pt = k.p * sqrt(t2) / sqrt(1.0 + t2);
         if (c->pt_min <= 0.0 || pt > c->pt_min) return k;
+    }
+}
+
+/* lfgen_kick over arrays (q/p given; q = sign, p = 1/|q/p|); ok[i] = 0 where
+ * the particle does not leave the magnet forwards or q/p is 0. */
+void lfgen_kick_many(const lfgen_config *c, int64_t n, const double *tx, const double *ty,
+                     const double *qop, double *d, double *bl, uint8_t *ok) {
+    for (int64_t i = 0; i < n; ++i) {
+        if (qop[i] == 0.0) { d[i] = 0.0; bl[i] = 0.0; ok[i] = 0; continue; }
+        double q = qop[i] > 0.0 ? 1.0 : -1.0;
+        ok[i] = (uint8_t)lfgen_kick(c, tx[i], ty[i], q, 1.0 / fabs(qop[i]), &d[i], &bl[i]);
     }
 }
 
@@ -188,16 +232,18 @@ static int gen_event(const lfgen_config *c, uint32_t ev_stream, lfgen_out *o, ui
     uint32_t order = 0;
     for (int i = 0; i < npar; ++i) {
         kin k = draw_kin(&r, c);
-        double dtx = c->kick * k.q / k.p;
+        double dtx, bl;
+        int forward = lfgen_kick(c, k.tx, k.ty, k.q, k.p, &dtx, &bl);
         double T = k.tx + dtx;
         uint16_t mask = 0;
         for (int l = 0; l < LFG_NL; ++l) {
             double zl = c->z[l];
-            double x = k.tx * c->z_mag + T * (zl - c->z_mag) + c->kappa * dtx * (zl - c->z_T) * (zl - c->z_T);
+            double x = k.tx * c->z_mag + T * (zl - c->z_mag) +
+                       c->kappa * dtx * (zl - c->z_T) * (zl - c->z_T) * (1.0 + c->dRatio * (zl - c->z_T));
             double y = k.ty * zl;
             double ue = unif(&r);
             double nx = normal(&r);
-            if (fabs(x) < c->x_acc && fabs(y) < c->y_acc && ue < c->hit_eff) {
+            if (forward && fabs(x) < c->x_acc && fabs(y) < c->y_acc && ue < c->hit_eff) {
                 rawhit h;
                 h.bucket = (uint32_t)(l * 2 + (y >= 0.0 ? 1 : 0));
                 h.x = (float)(x - c->dxdy[l] * y + c->sigma_x * nx);

@@ -34,7 +34,8 @@ class Geometry(ctypes.Structure):
     _fields_ = [("z", ctypes.c_float * NL), ("dxdy", ctypes.c_float * NL),
                 ("z_in", ctypes.c_float), ("z_mag", ctypes.c_float), ("z_ref", ctypes.c_float),
                 ("z_T", ctypes.c_float), ("kick", ctypes.c_float), ("kappa", ctypes.c_float),
-                ("dRatio", ctypes.c_float), ("polarity", ctypes.c_int32)]
+                ("dRatio", ctypes.c_float), ("polarity", ctypes.c_int32),
+                ("field_form", ctypes.c_int32), ("F_coef", (ctypes.c_float * 10) * 5)]
 
 
 class Params(ctypes.Structure):
@@ -122,6 +123,11 @@ def make_geometry(world: dict) -> Geometry:
     g.kappa = world["kappa"]
     g.dRatio = world.get("dRatio", 0.0)
     g.polarity = int(world.get("polarity", 1))
+    g.field_form = int(world.get("field_form", 0))
+    coef = world.get("F_coef", [0.0] * 50)
+    for i in range(5):
+        for j in range(10):
+            g.F_coef[i][j] = coef[10 * i + j]
     return g
 
 

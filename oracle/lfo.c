@@ -140,6 +140,35 @@ static int closest_uv(const event_view *ev, int first, int last, float x_pred, f
  *   g(u) = u^2 (1 + dRatio u),  x(u) = a + b u + c g(u),  u = z - z_ref. */
 static float g_of(float u, float dRatio) { return u * u * (1.0f + dRatio * u); }
 
+/* Integrated field of the momentum parametrisation [M1][M2]: the 2D
+ * polynomials c_i(tx, ty) over the monomials m_j summed in order of j, then
+ * F = c0 + d (c1 + d (c2 + d (c3 + d c4))). */
+static float field_F(const lfo_geometry *G, float tx, float ty, float d) {
+    float x2 = tx * tx, y2 = ty * ty;
+    float m[10] = {1.0f, x2, y2, x2 * x2, x2 * y2, y2 * y2, x2 * x2 * x2, x2 * x2 * y2, x2 * y2 * y2,
+                   y2 * y2 * y2};
+    float c[5];
+    for (int i = 0; i < 5; ++i) {
+        int nj = (i & 1) ? 6 : 10;
+        float acc = G->F_coef[i][0] * m[0];
+        for (int j = 1; j < nj; ++j) acc = acc + G->F_coef[i][j] * m[j];
+        c[i] = (i & 1) ? tx * acc : acc;
+    }
+    return c[0] + d * (c[1] + d * (c[2] + d * (c[3] + d * c[4])));
+}
+
+/* Sine-like slope of the pt-kick equation, tx / sqrt(1 + tx^2 + ty^2). */
+static float kick_s(float tx, float ty) { return tx / sqrtf(1.0f + tx * tx + ty * ty); }
+
+/* x slope after the magnet from s_f and ty (ty unchanged by the kick):
+ * tx_f = s_f sqrt((1 + ty^2) / (1 - s_f^2)).  Returns 0 when |s_f| >= 1:
+ * no slope can carry that kick [M4]. */
+static int kick_tx(float sf, float ty, float *txf) {
+    if (!(sf * sf < 1.0f)) return 0;
+    *txf = sf * sqrtf((1.0f + ty * ty) / (1.0f - sf * sf));
+    return 1;
+}
+
 /* Sum of the fit terms of one candidate.  Term l belongs to layer l (slots
  * 12..15 and layers without a hit hold +0) and the 16 slots are added
  * pairwise: (t0+t1), (t2+t3), ..., then pairs of those, and so on [R19]. */
@@ -182,20 +211,36 @@ static void track_one(const lfo_geometry *G, const lfo_params *P, const event_vi
     int zone = ty_in >= 0.0f ? 1 : 0;
 
     /* ---- Extrapolation to every layer.  VELO-UT input: the pt-kick model
-     *      [R1], straight to the bending plane, kick dtx = kick*q/p, then the
-     *      post-magnet model.  VELO input: a straight line [N1]. ---- */
+     *      [R1], straight to the bending plane, the kick, then the post-magnet
+     *      model with its cubic term [M6].  The kick is dtx = kick*q/p, or
+     *      (field_form 1) the sqrt-normalised pt-kick equation solved for the
+     *      slope after the magnet with F taken at dSlope = 0 and then twice at
+     *      the slope change of the previous solution [M3]; a track whose kick
+     *      has no solution is not found [M4].  VELO input: a straight line
+     *      [N1]. ---- */
     float x_mag = x_in + tx_in * (G->z_mag - G->z_in);
     float x_ext[LFO_NL], y_ext[LFO_NL];
     if (velo) {
         for (int l = 0; l < LFO_NL; ++l) x_ext[l] = x_in + tx_in * (G->z[l] - G->z_in);
     } else {
-        float dtx = G->kick * qop;
+        float dtx;
+        if (G->field_form == 1) {
+            float si = kick_s(tx_in, ty_in);
+            float d = 0.0f, txf = 0.0f;
+            for (int it = 0; it < 3; ++it) {
+                if (!kick_tx(si + qop * field_F(G, tx_in, ty_in, d), ty_in, &txf)) return;
+                d = txf - tx_in;
+            }
+            dtx = d;
+        } else {
+            dtx = G->kick * qop;
+        }
         float T = tx_in + dtx;
         float kd = G->kappa * dtx;
         for (int l = 0; l < LFO_NL; ++l) {
             float dz = G->z[l] - G->z_mag;
             float dzT = G->z[l] - G->z_T;
-            x_ext[l] = x_mag + T * dz + kd * dzT * dzT;
+            x_ext[l] = x_mag + T * dz + kd * dzT * dzT * (1.0f + G->dRatio * dzT);
         }
     }
     for (int l = 0; l < LFO_NL; ++l) y_ext[l] = y_in + ty_in * (G->z[l] - G->z_in);
@@ -492,11 +537,17 @@ static void track_one(const lfo_geometry *G, const lfo_params *P, const event_vi
     }
     if (best_rank < 0) return;
 
-    /* ---- momentum from the slope change at z_T [R24] ---- */
+    /* ---- momentum from the slope change at z_T [R24]; field_form 1: the
+     *      pt-kick equation with the fitted slopes after the magnet and F at
+     *      the measured dSlope [M5] ---- */
     float bb = best_par[1], cc = best_par[2];
     float uT = G->z_T - G->z_ref;
     float txT = bb + 2.0f * cc * uT + 3.0f * cc * G->dRatio * uT * uT;
-    float qop_out = (txT - tx_in) / G->kick;
+    float qop_out;
+    if (G->field_form == 1)
+        qop_out = (kick_s(txT, best_par[4]) - kick_s(tx_in, ty_in)) / field_F(G, tx_in, ty_in, txT - tx_in);
+    else
+        qop_out = (txT - tx_in) / G->kick;
 
     *found = 1;
     *n_out = (uint8_t)best_n;
@@ -519,6 +570,7 @@ int lfo_find_tracks(const lfo_geometry *g, const lfo_params *P, uint32_t n_event
     if (!g || !P || !hit_off || !trk_off || !out || ev_end > n_events || ev_begin > ev_end)
         return -1;
     if (P->n_triplets < 1 || P->n_triplets > LFO_MAX_TRIPLETS || P->n_hits_window < 1) return -1;
+    if (g->field_form != 0 && g->field_form != 1) return -1;
     const int NT = P->n_triplets;
     for (uint32_t e = ev_begin; e < ev_end; ++e) {
         uint32_t base = hit_off[24 * e];

@@ -35,6 +35,17 @@ typedef struct {
     float kappa;          /* residual curvature after the magnet, per unit dtx */
     float dRatio;         /* cubic term of the x(z) model */
     int32_t polarity;     /* +1: q > 0 bends towards +x (window asymmetry on +x) */
+    /* Momentum form.  0: linear kick, slope change = kick * q/p, and
+     * q/p = slope change / kick.  1: the sqrt-normalised pt-kick equation
+     * with the integrated field given by the fourth-order polynomial F in
+     * dSlope of "Calculation of momentum and track states":
+     *   F = sum_{i=0..4} c_i dSlope^i,
+     *   c_i = sum_j F_coef[i][j] m_j          (i even, j = 0..9),
+     *   c_i = tx * sum_j F_coef[i][j] m_j     (i odd,  j = 0..5),
+     *   m = 1, tx2, ty2, tx2^2, tx2 ty2, ty2^2, tx2^3, tx2^2 ty2, tx2 ty2^2, ty2^3,
+     * with tx, ty the input (VELO) slopes; F_coef[odd][6..9] are unused. */
+    int32_t field_form;
+    float F_coef[5][10];
 } lfo_geometry;
 
 /* Tunable parameters (Table of tolerances, Forward column; C(n_hits) table). */

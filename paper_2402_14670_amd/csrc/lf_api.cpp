@@ -64,7 +64,11 @@ int check_params(const lf_geometry *g, const lf_params *p, std::string &why) {
         if (!finitef(g->z[l]) || !finitef(g->dxdy[l])) { why = "geometry: non-finite layer z or dxdy"; return 0; }
     const float gs[] = {g->z_in, g->z_mag, g->z_ref, g->z_T, g->kick, g->kappa, g->dRatio};
     for (float v : gs) if (!finitef(v)) { why = "geometry: non-finite value"; return 0; }
-    if (g->kick == 0.0f) { why = "geometry: kick must be non-zero"; return 0; }
+    if (g->field_form != 0 && g->field_form != 1) { why = "geometry: field_form must be 0 or 1"; return 0; }
+    if (g->field_form == 0 && g->kick == 0.0f) { why = "geometry: kick must be non-zero"; return 0; }
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 10; ++j)
+            if (!finitef(g->F_coef[i][j])) { why = "geometry: non-finite F_coef entry"; return 0; }
     if (g->polarity != 1 && g->polarity != -1) { why = "geometry: polarity must be +1 or -1"; return 0; }
     if (p->n_hits_window < 1 || p->n_hits_window > lfk::MAX_WINDOW) { why = "params: n_hits_window must be 1..64"; return 0; }
     if (p->n_triplets < 1 || p->n_triplets > lfk::MAX_TRIPLETS) { why = "params: n_triplets must be 1..32"; return 0; }
@@ -89,6 +93,9 @@ lfk::KParams to_kparams(const lf_geometry &g, const lf_params &p) {
     for (int l = 0; l < LF_NLAYERS; ++l) { k.z[l] = g.z[l]; k.dxdy[l] = g.dxdy[l]; }
     k.z_in = g.z_in; k.z_mag = g.z_mag; k.z_ref = g.z_ref; k.z_T = g.z_T;
     k.kick = g.kick; k.kappa = g.kappa; k.dRatio = g.dRatio; k.polarity = g.polarity;
+    k.field_form = g.field_form;
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 10; ++j) k.F_coef[i][j] = g.F_coef[i][j];
     k.T_triplet = p.T_triplet; k.T_x = p.T_x; k.T_uv_scale = p.T_uv_scale; k.T_uv_floor = p.T_uv_floor;
     k.T_ty = p.T_ty; k.T_y = p.T_y; k.T_Q = p.T_Q;
     k.xtol_const = p.xtol_const; k.xtol_pscale = p.xtol_pscale; k.xasym = p.xasym;

@@ -25,6 +25,10 @@ struct KParams {
     // minimum momentum, two windows per layer
     int32_t velo_only;
     float noUT_c[8], noUT_p_min, noUT_pt_min, noUT_overlap;
+    // Momentum form: 0 linear kick; 1 sqrt-normalised pt-kick with the
+    // integrated field F(tx, ty, dSlope) = sum_i c_i dSlope^i, c_i from F_coef
+    int32_t field_form;
+    float F_coef[5][10];
 };
 
 // Device view of one resident batch (SoA, all in HBM).

@@ -93,6 +93,39 @@ __device__ __forceinline__ bool is_uv(int l) {
 // x(z) model term g(u) = u^2 (1 + dRatio u), u = z - z_ref.
 __device__ __forceinline__ float g_of(float u, float dR) { return u * u * (1.0f + dR * u); }
 
+// Sine-like slope of the pt-kick equation ("Defining the search windows"),
+// tx / sqrt(1 + tx^2 + ty^2).
+__device__ __forceinline__ float kick_s(float tx, float ty) { return tx / sqrtf(1.0f + tx * tx + ty * ty); }
+
+// Momentum parametrisation ("Calculation of momentum and track states"):
+// F = c0 + d (c1 + d (c2 + d (c3 + d c4))) for dSlope d.
+__device__ __forceinline__ float field_F(const float c[5], float d) {
+    return c[0] + d * (c[1] + d * (c[2] + d * (c[3] + d * c[4])));
+}
+
+// Coefficient c_i(tx, ty) of the parametrisation for i = lane (lanes 0..4;
+// other lanes return row 0): the monomials 1, tx2, ty2, tx2^2, tx2 ty2,
+// ty2^2, tx2^3, tx2^2 ty2, tx2 ty2^2, ty2^3 (tx2 = tx^2, ty2 = ty^2) weighted
+// by row i of the table and summed in that order, ten terms for even i, the
+// first six times tx for odd i.
+__device__ __forceinline__ float field_c_lane(const KParams *__restrict__ P, float tx, float ty, int lane) {
+    const int i = lane < 5 ? lane : 0;
+    const float *row = &P->F_coef[i][0];
+    const float x2 = tx * tx, y2 = ty * ty;
+    const float m[10] = {1.0f, x2, y2, x2 * x2, x2 * y2, y2 * y2, x2 * x2 * x2, x2 * x2 * y2, x2 * y2 * y2,
+                         y2 * y2 * y2};
+    float w[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) w[j] = row[j];
+    float acc = w[0] * m[0];
+#pragma unroll
+    for (int j = 1; j < 6; ++j) acc = acc + w[j] * m[j];
+    if (i & 1) return tx * acc;
+#pragma unroll
+    for (int j = 6; j < 10; ++j) acc = acc + w[j] * m[j];
+    return acc;
+}
+
 // Binary searches over at most NMAX (a power of two) window entries, in a
 // fixed number of steps: p advances by s = NMAX, NMAX/2, .., 1 while the
 // entry before p + s still satisfies the (monotone) predicate, so p ends as
@@ -320,7 +353,37 @@ struct Track {
         }
         const int zone = ty_in >= 0.0f ? 1 : 0;
         const float x_mag = x_in + tx_in * (P->z_mag - P->z_in);
-        const float dtx = P->kick * qop;
+        // The kick.  Linear: dtx = kick * q/p.  Paper form: the sqrt-normalised
+        // pt-kick equation s_f = s_i + (q/p) F solved for the slope after the
+        // magnet, F taken at dSlope = 0 and then twice at the slope change of
+        // the previous solution; no solution (|s_f| >= 1): the track is not
+        // searched.  The c_i also serve the momentum at the end.
+        const bool paper = P->field_form == 1;
+        float fc[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        float dtx = 0.0f;
+        if (paper) {
+            const float cl = field_c_lane(P, tx_in, ty_in, lane);
+#pragma unroll
+            for (int i = 0; i < 5; ++i) fc[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cl), i));
+            if constexpr (NS == 1) {
+                const float si = kick_s(tx_in, ty_in);
+                float d = 0.0f;
+                bool ok = true;
+#pragma unroll
+                for (int it = 0; it < 3; ++it) {
+                    const float sf = si + qop * field_F(fc, d);
+                    if (!(sf * sf < 1.0f)) { ok = false; break; }
+                    d = sf * sqrtf((1.0f + ty_in * ty_in) / (1.0f - sf * sf)) - tx_in;
+                }
+                if (!ok) {
+                    write_none(t, (size_t)t * NL);
+                    return;
+                }
+                dtx = d;
+            }
+        } else {
+            dtx = P->kick * qop;
+        }
         const float T = tx_in + dtx;
         const float kd = P->kappa * dtx;
         const uint32_t ebase = (uint32_t)__builtin_amdgcn_readlane((int)ho, 0);
@@ -360,7 +423,7 @@ struct Track {
                     } else {
                         const float dz = P->z[l] - P->z_mag;
                         const float dzT = P->z[l] - P->z_T;
-                        const float xe = x_mag + T * dz + kd * dzT * dzT;
+                        const float xe = x_mag + T * dz + kd * dzT * dzT * (1.0f + dR * dzT);
                         if (is_uv(l)) {
                             xc = xe - P->dxdy[l] * ye;
                             xmin = xc - P->uv_halfwidth;
@@ -815,7 +878,8 @@ struct Track {
             B.c[t] = bfc;
             B.y0[t] = bfy0;
             B.ty[t] = bfty;
-            B.qop[t] = (txT - tx_in) / P->kick;
+            B.qop[t] = paper ? (kick_s(txT, bfty) - kick_s(tx_in, ty_in)) / field_F(fc, txT - tx_in)
+                             : (txT - tx_in) / P->kick;
             B.Q[t] = best_Q;
         }
         if (lane < NL) {

@@ -19,9 +19,9 @@ def say(*a):
     sys.stdout.flush()
 
 
-def run_gpu(ev, mode="batched", params=None, exec_cfg=None, stream=None):
+def run_gpu(ev, mode="batched", params=None, exec_cfg=None, stream=None, world=None):
     from paper_2402_14670_amd import lf
-    ctx = lf.lf_create(W, params)
+    ctx = lf.lf_create(W if world is None else world, params)
     try:
         if exec_cfg:
             lf.lf_set_exec(ctx, **exec_cfg)
@@ -60,10 +60,10 @@ def oracle_rows(ev, events):
     return np.concatenate(rows) if rows else np.zeros(0, np.int64)
 
 
-def oracle_on_events(ev, events, params=None):
+def oracle_on_events(ev, events, params=None, world=None):
     """Oracle results for the listed events, placed in a full-size result."""
     sub = lfgen.select_events(ev, events)
-    o = oracle.run(sub, W, params)
+    o = oracle.run(sub, W if world is None else world, params)
     T = ev.n_tracks
     full = dict(found=np.zeros(T, np.uint8), n_hits=np.zeros(T, np.uint8), hit_idx=np.full((T, 12), -1, np.int32))
     for k in PARAM_KEYS:

@@ -882,8 +882,182 @@ def pin_no_ut_invariants(lib=None):
 NO_UT_PINS = [pin_no_ut_constants, pin_no_ut_containment, pin_no_ut_low_pt_excluded, pin_no_ut_physics,
               pin_no_ut_bruteforce, pin_no_ut_window_formula, pin_no_ut_invariants]
 
+
+# ------------------------------------------------------------------ paper-form field
+# Events in the "paper" field (sqrt-normalised pt-kick, an integrated field
+# that depends on the entry slopes and on the bending, a falling B_y tail)
+# and in the "kick" field (the same kick with a constant integral, for which
+# F = 1.2 GeV is exact); the method reads the fitted F table.
+W_PAPER = lfgen.world("paper")
+F_CONST = [lfgen.KICK] + [0.0] * 49
+W_KICK = lfgen.world("kick", F_coef=F_CONST)
+
+
+@functools.lru_cache(maxsize=None)
+def ev_field_noise_free(field: str, seed: int = 11, n: int = 120):
+    return lfgen.generate("single", field=field, seed=seed, sigma_x=0.0, qop_sigma=0.0, hit_eff=1.0,
+                          n_noise=0, p_min=1.5, p_max=50.0, n_particles=n)
+
+
+def _centre_errors(ev, o):
+    """(p, |window centre - exact hit x|) of every truth hit; asserts every
+    truth hit lies inside its window."""
+    out = []
+    for t in range(ev.n_tracks):
+        p = particle(ev, t)[0]
+        base = int(ev.hit_off[24 * int(ev.track_event()[t])])
+        for l in range(NL):
+            h = truth_hit(ev, t, l)
+            if h < 0:
+                continue
+            assert o["win"][t, l, 0] <= h < o["win"][t, l, 1], f"truth hit outside window t={t} l={l}"
+            out.append((p, abs(float(o["wx"][t, l, 1]) - float(ev.hit_x[base + h]))))
+    return np.array(out)
+
+
+def pin_kick_extrapolation_exact(lib=None):
+    """Constant integrated field: the pt-kick equation with F = 1.2 GeV is
+    the world's exact kick, so with exact q/p every window centre sits on
+    the exact hit position (x layers: x; u/v: x - dxdy*y), including the
+    falling-tail cubic term, at every momentum."""
+    ev = ev_field_noise_free("kick")
+    o = oracle.run(ev, W_KICK, debug=True, lib=lib)
+    e = _centre_errors(ev, o)
+    assert len(e) > 1000 and (e[:, 0] < 3.0).sum() > 30
+    assert e[:, 1].max() <= 2e-3, f"window centre off the exact hit by {e[:, 1].max()} mm"
+
+
+def pin_kick_momentum_exact(lib=None):
+    """Constant integrated field, noise-free tracks: the pt-kick equation
+    returns the true q/p from the fitted slope after the magnet."""
+    ev = ev_field_noise_free("kick")
+    o = oracle.run(ev, W_KICK, lib=lib)
+    n = 0
+    for t in np.nonzero(o["found"])[0]:
+        p, q, tx, ty = particle(ev, t)
+        assert all(o["hit_idx"][t, l] == truth_hit(ev, t, l) for l in range(NL))
+        assert abs(o["qop"][t] * p / q - 1.0) < 2e-5, (t, p, o["qop"][t] * p / q)
+        n += 1
+    assert n >= 90
+
+
+def pin_paper_extrapolation(lib=None):
+    """Paper field, exact q/p: the window centres follow the exact hits to
+    within what the calibrated F and two refinements of the kick allow
+    (below 3 GeV, where the slope change is largest, tens of mm against a
+    half-width of 817 mm; above 5 GeV a fraction of a mm), and every truth
+    hit is inside its window."""
+    ev = ev_field_noise_free("paper")
+    o = oracle.run(ev, W_PAPER, debug=True, lib=lib)
+    e = _centre_errors(ev, o)
+    for lo, hi, tol in ((1.5, 3.0, 40.0), (3.0, 5.0, 0.6), (5.0, 1e9, 0.2)):
+        m = (e[:, 0] >= lo) & (e[:, 0] < hi)
+        assert m.sum() > 30
+        assert e[m, 1].max() <= tol, (lo, hi, e[m, 1].max())
+
+
+def pin_paper_momentum(lib=None):
+    """Paper field, noise-free tracks whose hits are all the particle's: the
+    q/p from the pt-kick equation with the fitted F matches the truth to
+    the calibration's accuracy (the table's largest relative residual over
+    its acceptance sample is 1.6e-3), and typically to a few 1e-4."""
+    ev = ev_field_noise_free("paper")
+    o = oracle.run(ev, W_PAPER, lib=lib)
+    rel = []
+    for t in np.nonzero(o["found"])[0]:
+        if not all(o["hit_idx"][t, l] == truth_hit(ev, t, l) for l in range(NL)):
+            continue
+        p, q, tx, ty = particle(ev, t)
+        rel.append(float(o["qop"][t]) * p / q - 1.0)
+    rel = np.abs(np.array(rel))
+    assert len(rel) >= 90
+    assert rel.max() <= 2e-3, rel.max()
+    assert np.median(rel) <= 3e-4, np.median(rel)
+
+
+def pin_paper_no_kick_solution(lib=None):
+    """A kick that no slope can carry (|s_f| >= 1: a track too soft for the
+    field) gives no windows and no track; a slightly harder one is searched."""
+    ev = ev_field_noise_free("paper")
+    import copy
+    bad = copy.deepcopy(ev)
+    t_s = np.arange(0, ev.n_tracks, 3)
+    tx = bad.trk_tx[t_s].astype(np.float64)
+    # q/p that moves s by 1.5 (F is about 1.2 GeV) in the direction of tx
+    bad.trk_qop[t_s] = np.where(tx >= 0, 1.25, -1.25).astype(np.float32)
+    o = oracle.run(bad, W_PAPER, debug=True, lib=lib)
+    assert not o["found"][t_s].any()
+    assert (o["win"][t_s] == 0).all()
+    # the other tracks are unaffected
+    o0 = oracle.run(ev, W_PAPER, lib=lib)
+    keep = np.setdiff1d(np.arange(ev.n_tracks), t_s)
+    assert np.array_equal(o["found"][keep], o0["found"][keep])
+    assert np.array_equal(o["qop"][keep], o0["qop"][keep])
+    # a soft track whose kick still has a solution keeps its windows
+    soft = copy.deepcopy(ev)
+    soft.trk_qop[t_s] = np.where(tx >= 0, -0.45, 0.45).astype(np.float32)
+    o = oracle.run(soft, W_PAPER, debug=True, lib=lib)
+    assert (o["win"][t_s, :, 1] > o["win"][t_s, :, 0]).any(axis=1).mean() > 0.5
+
+
+def pin_paper_physics(lib=None):
+    """Nominal-shape events in the paper field: efficiency >= 95%, ghost
+    rate <= 2%, q/p resolution below 1% with the fitted F, and at least three
+    times worse when F is replaced by its constant -- the dSlope dependence
+    of the parametrisation carries the resolution."""
+    ev = lfgen.generate("nominal", field="paper", n_events=2)
+    o = oracle.run(ev, W_PAPER, lib=lib)
+    ph = truth.physics(ev, o)
+    assert ph["efficiency"] >= 0.95 and ph["ghost_rate"] <= 0.02, ph
+    assert ph["qop_resolution"] < 0.01, ph
+    oc = oracle.run(ev, dict(W_PAPER, F_coef=F_CONST), lib=lib)
+    assert truth.physics(ev, oc)["qop_resolution"] > 3.0 * ph["qop_resolution"]
+
+
+# exponents (k, m) of tx^k ty^m for the columns of F_coef: even rows use all
+# ten, odd rows the first six times one more power of tx
+_F_EXPONENTS = ((0, 0), (2, 0), (0, 2), (4, 0), (2, 2), (0, 4), (6, 0), (4, 2), (2, 4), (0, 6))
+
+
+def pin_F_single_terms(lib=None):
+    """Constant integrated field (s_f - s_i = 1.2 q/p exactly) read with a
+    table of the constant 1.2 plus one extra term w * tx^k ty^m dSlope^i:
+    then the method's q/p is the truth times 1.2 / (1.2 + w tx^k ty^m d^i),
+    with d the true slope change -- for every term of the table in turn (the
+    weight w sized for a change of at most 3% of F)."""
+    ev = ev_field_noise_free("kick")
+    tev = ev.track_event()
+    g = ev.par_off[tev].astype(np.int64) + ev.trk_pid.astype(np.int64)
+    p, q = ev.par_p[g].astype(np.float64), ev.par_q[g].astype(np.float64)
+    tx, ty = ev.trk_tx.astype(np.float64), ev.trk_ty.astype(np.float64)
+    d, bl, fwd = lfgen.kick(tx, ty, q / p, "kick")
+    for i in range(5):
+        for j in range(10 if i % 2 == 0 else 6):
+            k, m = _F_EXPONENTS[j]
+            k += i % 2
+            term = tx ** k * ty ** m * d ** i
+            if not np.any(term):
+                continue
+            w = 0.03 * lfgen.KICK / np.abs(term).max()
+            coef = list(F_CONST)
+            coef[10 * i + j] += float(np.float32(w))
+            w = float(np.float32(w))
+            o = oracle.run(ev, dict(W_KICK, F_coef=coef), lib=lib)
+            f = np.nonzero(o["found"])[0]
+            assert len(f) >= 80, (i, j, len(f))
+            pure = [t for t in f if all(o["hit_idx"][t, l] == truth_hit(ev, t, l) for l in range(NL))]
+            assert len(pure) >= 80, (i, j, len(pure))
+            pure = np.array(pure)
+            want = (q[pure] / p[pure]) * lfgen.KICK / (lfgen.KICK + w * term[pure])
+            err = np.abs(o["qop"][pure].astype(np.float64) / want - 1.0)
+            assert err.max() < 3e-5, (i, j, err.max())
+
+
+PAPER_FIELD_PINS = [pin_kick_extrapolation_exact, pin_kick_momentum_exact, pin_paper_extrapolation,
+                    pin_paper_momentum, pin_paper_no_kick_solution, pin_paper_physics, pin_F_single_terms]
+
 ALL_PINS = [pin_constants, pin_extrapolation_noise_free, pin_window_bounds, pin_window_search,
             pin_window_edges_closed, pin_triplet_closed_form, pin_magnet_threshold,
             pin_charge_filter, pin_bruteforce_triplets, pin_fit_noise_free, pin_fit_lstsq,
             pin_y_fit_recovers_slope, pin_physics_single, pin_invariants, pin_batch_independence,
-            pin_tie_breaks, pin_extension_rule, pin_nine_hit_tracks] + NO_UT_PINS
+            pin_tie_breaks, pin_extension_rule, pin_nine_hit_tracks] + NO_UT_PINS + PAPER_FIELD_PINS

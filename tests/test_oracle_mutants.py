@@ -21,8 +21,8 @@ MUTANTS = [
     ("swapped_K", "float K = s == 0 ? P->K_first : P->K_last;",
      "float K = s == 0 ? P->K_last : P->K_first;"),
     ("dropped_K", "(x0 - txd * z0) * K;", "(x0 - txd * z0);"),
-    ("curvature_sign", "x_ext[l] = x_mag + T * dz + kd * dzT * dzT;",
-     "x_ext[l] = x_mag + T * dz - kd * dzT * dzT;"),
+    ("curvature_sign", "x_ext[l] = x_mag + T * dz + kd * dzT * dzT * (1.0f + G->dRatio * dzT);",
+     "x_ext[l] = x_mag + T * dz - kd * dzT * dzT * (1.0f + G->dRatio * dzT);"),
     ("kick_dropped", "float T = tx_in + dtx;", "float T = tx_in;"),
     ("zone_flipped", "int zone = ty_in >= 0.0f ? 1 : 0;", "int zone = ty_in >= 0.0f ? 0 : 1;"),
     ("uv_centre_sign", "xc = x_ext[l] - G->dxdy[l] * y_ext[l];", "xc = x_ext[l] + G->dxdy[l] * y_ext[l];"),
@@ -73,6 +73,20 @@ MUTANTS = [
     ("noUT_poly_c7", "ip * (c8[6] * tx_in + c8[7] * ip)", "ip * (c8[6] * tx_in + c8[7])"),
     ("noUT_centre_edge", "xc = 0.5f * (xmin + xmax);", "xc = xmin;"),
     ("noUT_uv_tol_as_x", "float tol = is_uv(l) ? P->uv_halfwidth : xtol;", "float tol = xtol;"),
+    # paper-form field (sqrt-normalised pt-kick, momentum polynomial F)
+    ("pf_extrap_cubic_dropped", "kd * dzT * dzT * (1.0f + G->dRatio * dzT);", "kd * dzT * dzT;"),
+    ("pf_s_without_ty", "return tx / sqrtf(1.0f + tx * tx + ty * ty);", "return tx / sqrtf(1.0f + tx * tx);"),
+    ("pf_txf_without_ty", "sqrtf((1.0f + ty * ty) / (1.0f - sf * sf))", "sqrtf(1.0f / (1.0f - sf * sf))"),
+    ("pf_horner_c2_dropped", "c[1] + d * (c[2] + d * (c[3] + d * c[4]))", "c[1] + d * (d * (c[3] + d * c[4]))"),
+    ("pf_odd_rows_without_tx", "c[i] = (i & 1) ? tx * acc : acc;", "c[i] = acc;"),
+    ("pf_monomials_swapped", "x2 * x2 * y2, x2 * y2 * y2,", "x2 * y2 * y2, x2 * x2 * y2,"),
+    ("pf_no_refinement", "for (int it = 0; it < 3; ++it) {", "for (int it = 0; it < 1; ++it) {"),
+    ("pf_one_refinement", "for (int it = 0; it < 3; ++it) {", "for (int it = 0; it < 2; ++it) {"),
+    ("pf_momentum_F_at_zero", "field_F(G, tx_in, ty_in, txT - tx_in)", "field_F(G, tx_in, ty_in, 0.0f)"),
+    ("pf_momentum_sign", "(kick_s(txT, best_par[4]) - kick_s(tx_in, ty_in))",
+     "(kick_s(txT, best_par[4]) + kick_s(tx_in, ty_in))"),
+    ("pf_momentum_linear", "qop_out = (kick_s(txT, best_par[4]) - kick_s(tx_in, ty_in)) /",
+     "qop_out = (txT - tx_in) /"),
 ]
 
 
