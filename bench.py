@@ -56,8 +56,8 @@ BYTES_PER_TRACK_OUT = 78
 # HBM traffic of the batched kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (per launch, scaled by the counters' reading of a known-size copy), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha256": "49355b0bf9cd73ac9d8d0c57cbfab6e721622203219b377d7e4e89c4180ce6c1",
-           "bytes_per_launch": 80136894}
+TRAFFIC = {"kernel_sha256": "e3b38f9c1874990af78e024bb825ccd1087f974883af6e0507bcf9739e3d3b93",
+           "bytes_per_launch": 80188348}
 WORKLOADS = {
     "nominal": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",
     "uneven": "uneven: 20000 events, Poisson(7.6) x 50 particles, 0-13k hits and 0-600 tracks/event",
