@@ -213,11 +213,15 @@ __device__ __forceinline__ int uv_index(int l) { return 2 * (l >> 2) + (l & 3) -
 
 // NS = 1: one window per layer; NS = 2 (VELO-only input): two windows per
 // layer, side 0 for bending towards -x, side 1 towards +x.
+// With two windows per layer (LDS-bound occupancy) the hits keep only x in
+// LDS: a window keeps its first hit's z (stereo tangent), the value of all
+// its hits unless the window is mixed, whose hits are then read from HBM.
 template <int NW, int NS>
 struct WaveLds {
+    static constexpr int ZW = NS == 1 ? NW : 1;
     float wx[NS][NL][NW];      // window hits: x at y = 0
-    float wz[NS][NL][NW];      //              z
-    float wd[NS][6][NW];       //              stereo tangent (stereo layers only)
+    float wz[NS][NL][ZW];      //              z (NS = 2: first hit only)
+    float wd[NS][6][ZW];       //              stereo tangent (stereo layers; NS = 2: first hit only)
     int32_t wfirst[NS][NL];    // event-local index of each window's first hit
     int32_t wlen[NS][NL];
     uint64_t tk[MAX_TRIPLETS];      // top-n keys, sorted
@@ -247,6 +251,22 @@ struct Track {
     int nL;    // kept triplets
     uint32_t cnt[CNT ? C_N : 1];
     uint64_t tphase;
+    // bit NL * side + layer: the window's hits do not all share one z
+    // (zvar) or one stereo tangent (dvar); ebase: the event's first hit
+    uint32_t zvar = 0, dvar = 0, ebase = 0;
+
+    // z and stereo tangent of hit i of a window: from LDS with one window per
+    // layer; with two, the window's one value, or from HBM for a mixed window
+    __device__ __forceinline__ float zat(int sd, int l, int i) const {
+        if constexpr (NS == 1) return L.wz[sd][l][i];
+        if ((zvar >> (NL * sd + l)) & 1u) return ld32(B.hz, ebase + (uint32_t)(L.wfirst[sd][l] + i));
+        return L.wz[sd][l][0];
+    }
+    __device__ __forceinline__ float dat(int sd, int l, int i) const {
+        if constexpr (NS == 1) return L.wd[sd][uv_index(l)][i];
+        if ((dvar >> (NL * sd + l)) & 1u) return ld32(B.hd, ebase + (uint32_t)(L.wfirst[sd][l] + i));
+        return L.wd[sd][uv_index(l)][0];
+    }
 
     // Adds the shader-clock cycles since the previous mark to counter k.
     __device__ __forceinline__ void mark(int k) {
@@ -301,8 +321,8 @@ struct Track {
             const int s = (int)((e >> 16) & 1u), i0 = (int)((e >> 8) & 0xffu), i2 = (int)(e & 0xffu);
             const int l0 = s ? 3 : 0, l1 = s ? 7 : 4, l2 = s ? 11 : 8;
             const float K = s ? P->K_last : P->K_first;
-            const float x0 = L.wx[sd][l0][i0], z0 = L.wz[sd][l0][i0];
-            const float txd = (L.wx[sd][l2][i2] - x0) / (L.wz[sd][l2][i2] - z0);   // the doublet's slope, as queued
+            const float x0 = L.wx[sd][l0][i0], z0 = zat(sd, l0, i0);
+            const float txd = (L.wx[sd][l2][i2] - x0) / (zat(sd, l2, i2) - z0);   // the doublet's slope, as queued
             const float x1e = P->z[l1] * txd + (x0 - txd * z0) * K;
             float bd = INFINITY;
             const float *wx1 = L.wx[sd][l1];
@@ -386,7 +406,7 @@ struct Track {
         }
         const float T = tx_in + dtx;
         const float kd = P->kappa * dtx;
-        const uint32_t ebase = (uint32_t)__builtin_amdgcn_readlane((int)ho, 0);
+        ebase = (uint32_t)__builtin_amdgcn_readlane((int)ho, 0);
         // x tolerance of the x-layer windows
         float xtol;
         if constexpr (NS == 2) {
@@ -478,10 +498,10 @@ struct Track {
         // Round u covers slots lane + 64 u of the 12 x NW window slots (layer
         // (lane + 64 u) / NW); every load of a side is issued before its first
         // LDS write.  The same registers tell which windows have hits that do
-        // not all share one z (resp. one stereo slope): bit NL * side + layer
-        // of zvar (dvar); those take the general paths below.
+        // not all share one z (resp. one stereo slope), compared bit for bit:
+        // bit NL * side + layer of zvar (dvar); those read z (the slope) from
+        // HBM and take the general paths below.
         constexpr int SU = NL * NW / WAVE;
-        uint32_t zvar = 0, dvar = 0;
 #pragma unroll
         for (int sd = 0; sd < NS; ++sd) {
             float sx[SU], sz[SU], sd_[SU];
@@ -510,14 +530,16 @@ struct Track {
                 const bool in = (smask >> u) & 1u;
                 if (in) {
                     L.wx[sd][l][j] = sx[u];
-                    L.wz[sd][l][j] = sz[u];
-                    if (is_uv(l)) L.wd[sd][uv_index(l)][j] = sd_[u];
+                    if (NS == 1 || j == 0) {
+                        L.wz[sd][l][NS == 1 ? j : 0] = sz[u];
+                        if (is_uv(l)) L.wd[sd][uv_index(l)][NS == 1 ? j : 0] = sd_[u];
+                    }
                 }
                 // slot 0 of layer la sits in lane la NW - 64 u, that of lb in lane lb NW - 64 u
                 const float za = bcast_f(sz[u], la * NW - WAVE * u), zb = bcast_f(sz[u], lb * NW - WAVE * u);
                 const float da = bcast_f(sd_[u], la * NW - WAVE * u), db = bcast_f(sd_[u], lb * NW - WAVE * u);
-                const bool zd = in && sz[u] != (l == la ? za : zb);
-                const bool dd = in && sd_[u] != (l == la ? da : db);
+                const bool zd = in && __float_as_uint(sz[u]) != __float_as_uint(l == la ? za : zb);
+                const bool dd = in && __float_as_uint(sd_[u]) != __float_as_uint(l == la ? da : db);
                 if (__ballot(zd && l == la)) zvar |= 1u << (NL * sd + la);
                 if (__ballot(zd && l == lb)) zvar |= 1u << (NL * sd + lb);
                 if (is_uv(la) && __ballot(dd && l == la)) dvar |= 1u << (NL * sd + la);
@@ -564,9 +586,9 @@ struct Track {
             float x0 = 0.0f, z0 = 0.0f;
             if (item < items_total) {
                 x0 = L.wx[sd][l0][i0];
-                z0 = L.wz[sd][l0][i0];
+                z0 = zat(sd, l0, i0);
                 jhi = n2;
-                if (n2 > 0 && !((zvar >> (NL * sd + l0)) & 1u) && !((zvar >> (NL * sd + l2)) & 1u)) {
+                if (n2 > 0 && !(((zvar >> (NL * sd + l0)) | (zvar >> (NL * sd + l2))) & 1u)) {
                     const float lev = P->z_mag - z0;
                     const float dz = L.wz[sd][l2][0] - z0;
                     if (fabsf(lev) > 1.0f && fabsf(dz) > 1.0f) {
@@ -600,7 +622,7 @@ struct Track {
                 bool pass = false;
                 float txd = 0.0f;
                 if (i2 < jhi) {
-                    const float x2 = L.wx[sd][l2][i2], z2 = L.wz[sd][l2][i2];
+                    const float x2 = L.wx[sd][l2][i2], z2 = zat(sd, l2, i2);
                     txd = (x2 - x0) / (z2 - z0);
                     pass = !(low_p && !((txd - tx_in) * qop > 0.0f));
                     const float xm = x0 + txd * (P->z_mag - z0);
@@ -652,8 +674,8 @@ struct Track {
             const int s = (int)((lo >> 12) & 1u), i0 = (int)((lo >> 6) & 63u), i2 = (int)(lo & 63u);
             const int i1 = L.th1[lane];
             const int l0 = s ? 3 : 0, l1 = s ? 7 : 4, l2 = s ? 11 : 8;
-            const float u0 = L.wz[sd][l0][i0] - P->z_ref, u1 = L.wz[sd][l1][i1] - P->z_ref,
-                        u2 = L.wz[sd][l2][i2] - P->z_ref;
+            const float u0 = zat(sd, l0, i0) - P->z_ref, u1 = zat(sd, l1, i1) - P->z_ref,
+                        u2 = zat(sd, l2, i2) - P->z_ref;
             const float X0 = L.wx[sd][l0][i0], X1 = L.wx[sd][l1][i1], X2 = L.wx[sd][l2][i2];
             const float g0 = g_of(u0, dR), g1 = g_of(u1, dR), g2 = g_of(u2, dR);
             const float s01 = (X1 - X0) / (u1 - u0);
@@ -683,8 +705,9 @@ struct Track {
         struct Ext {
             int r, l, n, sd;
             bool uv, scan;
-            float xe, yp;
-            const float *wx, *wd;
+            float xe, yp, wd1;
+            uint32_t gb;    // batch index of the window's first hit
+            const float *wx, *wdv;
         };
         auto ext_item = [&](int it) {
             Ext e;
@@ -705,15 +728,27 @@ struct Track {
             // in the window the values stay sorted.
             e.uv = slot >= 3;
             e.yp = e.uv ? y_in + ty_in * (P->z[e.l] - P->z_in) : 0.0f;
-            e.wd = L.wd[e.sd][e.uv ? uv_index(e.l) : 0];
             e.scan = e.uv && ((dvar >> (NL * e.sd + e.l)) & 1u);
+            e.wd1 = e.uv ? L.wd[e.sd][uv_index(e.l)][0] : 0.0f;
+            e.wdv = L.wd[e.sd][e.uv ? uv_index(e.l) : 0];
+            e.gb = ebase + (uint32_t)L.wfirst[e.sd][e.l];
             return e;
         };
+        // sorted searches: the window's one tangent (0 for x slots, where it
+        // adds +-0); scans (stereo windows whose tangents differ): per hit
         auto ext_val = [](const Ext &e) {
-            const float *wx = e.wx, *wd = e.wd;
+            const float *wx = e.wx;
+            const float yp = e.yp, wd1 = e.wd1;
+            return [wx, yp, wd1](int j) { return wx[j] + wd1 * yp; };
+        };
+        const float *hd = B.hd;
+        auto ext_scan = [hd](const Ext &e) {
+            const float *wx = e.wx, *wdv = e.wdv;
             const float yp = e.yp;
-            const bool uv = e.uv;
-            return [wx, wd, yp, uv](int j) { return wx[j] + (uv ? wd[j] : 0.0f) * yp; };
+            const uint32_t gb = e.gb;
+            return [wx, wdv, yp, gb, hd](int j) {
+                return wx[j] + (NS == 1 ? wdv[j] : ld32(hd, gb + (uint32_t)j)) * yp;
+            };
         };
         auto ext_keep = [&](const Ext &e, int best, float bd) {
             if (best >= 0 && bd * bd < (e.uv ? T_uv : P->T_x)) L.ch[e.r][e.l] = (int8_t)best;
@@ -723,7 +758,7 @@ struct Track {
             if (lane < n_items) {
                 const Ext e = ext_item(lane);
                 float bd = INFINITY;
-                const int best = e.scan ? closest_scan(ext_val(e), e.n, e.xe, bd)
+                const int best = e.scan ? closest_scan(ext_scan(e), e.n, e.xe, bd)
                                         : closest_sorted<NW>(ext_val(e), e.n, e.xe, bd);
                 ext_keep(e, best, bd);
             }
@@ -738,9 +773,9 @@ struct Track {
                 if (!ea.scan && !eb.scan) {
                     closest_sorted2<NW>(ext_val(ea), ea.n, ea.xe, ba, da, ext_val(eb), eb.n, eb.xe, bb, db);
                 } else {
-                    ba = ea.scan ? closest_scan(ext_val(ea), ea.n, ea.xe, da)
+                    ba = ea.scan ? closest_scan(ext_scan(ea), ea.n, ea.xe, da)
                                  : closest_sorted<NW>(ext_val(ea), ea.n, ea.xe, da);
-                    bb = eb.scan ? closest_scan(ext_val(eb), eb.n, eb.xe, db)
+                    bb = eb.scan ? closest_scan(ext_scan(eb), eb.n, eb.xe, db)
                                  : closest_sorted<NW>(ext_val(eb), eb.n, eb.xe, db);
                 }
                 ext_keep(ea, ba, da);
@@ -798,11 +833,11 @@ struct Track {
             }
             float sv = 0.0f, h = 0.0f, rr = 0.0f, dxy = 1.0f;
             if (pres) {
-                const float zh = L.wz[sd][j][hit];
+                const float zh = zat(sd, j, hit);
                 const float u = zh - P->z_ref;
                 float xm;
                 if (uvj) {
-                    dxy = L.wd[sd][uv_index(j)][hit];
+                    dxy = dat(sd, j, hit);
                     const float yv = y_in + ty_in * (zh - P->z_in);
                     xm = L.wx[sd][j][hit] + dxy * yv;
                 } else {
