@@ -213,15 +213,17 @@ __device__ __forceinline__ int uv_index(int l) { return 2 * (l >> 2) + (l & 3) -
 
 // NS = 1: one window per layer; NS = 2 (VELO-only input): two windows per
 // layer, side 0 for bending towards -x, side 1 towards +x.
-// With two windows per layer (LDS-bound occupancy) the hits keep only x in
-// LDS: a window keeps its first hit's z (stereo tangent), the value of all
-// its hits unless the window is mixed, whose hits are then read from HBM.
+// Where LDS bounds the occupancy (two windows per layer, or 64-hit windows)
+// the hits keep only x in LDS (XO): a window keeps its first hit's z (stereo
+// tangent), the value of all its hits unless the window is mixed, whose
+// hits are then read from HBM.
 template <int NW, int NS>
 struct WaveLds {
-    static constexpr int ZW = NS == 1 ? NW : 1;
+    static constexpr bool XO = NS == 2 || NW > 32;
+    static constexpr int ZW = XO ? 1 : NW;
     float wx[NS][NL][NW];      // window hits: x at y = 0
-    float wz[NS][NL][ZW];      //              z (NS = 2: first hit only)
-    float wd[NS][6][ZW];       //              stereo tangent (stereo layers; NS = 2: first hit only)
+    float wz[NS][NL][ZW];      //              z (XO: first hit only)
+    float wd[NS][6][ZW];       //              stereo tangent (stereo layers; XO: first hit only)
     int32_t wfirst[NS][NL];    // event-local index of each window's first hit
     int32_t wlen[NS][NL];
     uint64_t tk[MAX_TRIPLETS];      // top-n keys, sorted
@@ -255,15 +257,16 @@ struct Track {
     // (zvar) or one stereo tangent (dvar); ebase: the event's first hit
     uint32_t zvar = 0, dvar = 0, ebase = 0;
 
-    // z and stereo tangent of hit i of a window: from LDS with one window per
-    // layer; with two, the window's one value, or from HBM for a mixed window
+    // z and stereo tangent of hit i of a window: from LDS, or (XO) the
+    // window's one value, or from HBM for a mixed window
+    static constexpr bool XO = WaveLds<NW, NS>::XO;
     __device__ __forceinline__ float zat(int sd, int l, int i) const {
-        if constexpr (NS == 1) return L.wz[sd][l][i];
+        if constexpr (!XO) return L.wz[sd][l][i];
         if ((zvar >> (NL * sd + l)) & 1u) return ld32(B.hz, ebase + (uint32_t)(L.wfirst[sd][l] + i));
         return L.wz[sd][l][0];
     }
     __device__ __forceinline__ float dat(int sd, int l, int i) const {
-        if constexpr (NS == 1) return L.wd[sd][uv_index(l)][i];
+        if constexpr (!XO) return L.wd[sd][uv_index(l)][i];
         if ((dvar >> (NL * sd + l)) & 1u) return ld32(B.hd, ebase + (uint32_t)(L.wfirst[sd][l] + i));
         return L.wd[sd][uv_index(l)][0];
     }
@@ -502,12 +505,15 @@ struct Track {
         // bit NL * side + layer of zvar (dvar); those read z (the slope) from
         // HBM and take the general paths below.
         constexpr int SU = NL * NW / WAVE;
+        constexpr int SC = SU > 6 ? 6 : SU;   // rounds per chunk of loads in flight
 #pragma unroll
         for (int sd = 0; sd < NS; ++sd) {
+#pragma unroll
+          for (int u0 = 0; u0 < SU; u0 += SC) {
             float sx[SU], sz[SU], sd_[SU];
             uint32_t smask = 0;
 #pragma unroll
-            for (int u = 0; u < SU; ++u) {
+            for (int u = u0; u < u0 + SC; ++u) {
                 const int it = lane + WAVE * u, l = it / NW, j = it - NW * (it / NW);
                 const int la = WAVE * u / NW, lb = (WAVE * u + WAVE - 1) / NW;
                 const int fa = __builtin_amdgcn_readlane(wf[sd], la), fb = __builtin_amdgcn_readlane(wf[sd], lb);
@@ -524,15 +530,15 @@ struct Track {
                 }
             }
 #pragma unroll
-            for (int u = 0; u < SU; ++u) {
+            for (int u = u0; u < u0 + SC; ++u) {
                 const int it = lane + WAVE * u, l = it / NW, j = it - NW * (it / NW);
                 const int la = WAVE * u / NW, lb = (WAVE * u + WAVE - 1) / NW;
                 const bool in = (smask >> u) & 1u;
                 if (in) {
                     L.wx[sd][l][j] = sx[u];
-                    if (NS == 1 || j == 0) {
-                        L.wz[sd][l][NS == 1 ? j : 0] = sz[u];
-                        if (is_uv(l)) L.wd[sd][uv_index(l)][NS == 1 ? j : 0] = sd_[u];
+                    if (!XO || j == 0) {
+                        L.wz[sd][l][XO ? 0 : j] = sz[u];
+                        if (is_uv(l)) L.wd[sd][uv_index(l)][XO ? 0 : j] = sd_[u];
                     }
                 }
                 // slot 0 of layer la sits in lane la NW - 64 u, that of lb in lane lb NW - 64 u
@@ -545,6 +551,7 @@ struct Track {
                 if (is_uv(la) && __ballot(dd && l == la)) dvar |= 1u << (NL * sd + la);
                 if (is_uv(lb) && __ballot(dd && l == lb)) dvar |= 1u << (NL * sd + lb);
             }
+          }
         }
         wave_sync();
         if constexpr (CNT) {
@@ -747,7 +754,7 @@ struct Track {
             const float yp = e.yp;
             const uint32_t gb = e.gb;
             return [wx, wdv, yp, gb, hd](int j) {
-                return wx[j] + (NS == 1 ? wdv[j] : ld32(hd, gb + (uint32_t)j)) * yp;
+                return wx[j] + (XO ? ld32(hd, gb + (uint32_t)j) : wdv[j]) * yp;
             };
         };
         auto ext_keep = [&](const Ext &e, int best, float bd) {
