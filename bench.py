@@ -56,8 +56,8 @@ BYTES_PER_TRACK_OUT = 78
 # HBM traffic of the batched kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (per launch, scaled by the counters' reading of a known-size copy), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha256": "e3b38f9c1874990af78e024bb825ccd1087f974883af6e0507bcf9739e3d3b93",
-           "bytes_per_launch": 80188348}
+TRAFFIC = {"kernel_sha256": "b7129ec18acfc10e8f1020b5a7d544116eeefc37e13bd214fe50517215b2fac4",
+           "bytes_per_launch": 80151882}
 WORKLOADS = {
     "nominal": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",
     "uneven": "uneven: 20000 events, Poisson(7.6) x 50 particles, 0-13k hits and 0-600 tracks/event",
@@ -223,13 +223,22 @@ def truth_summary(ev, out) -> dict:
             "qop_resolution": ph["qop_resolution"], "reconstructible_p_gt_5GeV": ph["n_reconstructible"]}
 
 
-def no_ut_mode(lf, world, ev, stream, steps, warmup):
+def tune_batched(ctx, bid, stream, tune):
+    """Wavefronts per block of the batched mode, autotuned (or the default)."""
+    if not tune:
+        return None
+    from paper_2402_14670_amd import autotune
+    return autotune.autotune(ctx, bid, stream, modes=("batched",), steps=3)["best"]["waves_per_block"]
+
+
+def no_ut_mode(lf, world, ev, stream, steps, warmup, tune=True):
     """The same batch under the paper's no-UT tuning (VELO-only input: two
     windows per layer, 64 hits each, per-side seeding), batched mode."""
     from lfgen import truth
     ctx = lf.lf_create(world, lf.lf_default_params(no_ut=True))
     try:
         bid = lf.lf_upload_events(ctx, ev, stream.cuda_stream)
+        wpb = tune_batched(ctx, bid, stream, tune)
         ms, _ = time_mode(lf, ctx, bid, lf.LF_MODE_BATCHED, max(5, steps // 2), warmup, stream)
         out = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
     finally:
@@ -237,11 +246,11 @@ def no_ut_mode(lf, world, ev, stream, steps, warmup):
     ph = truth.physics(ev, out, p_min=5.0)
     print(f"bench: no-UT      {ms:8.3f} ms/step  {ev.n_events / ms * 1e3:12.0f} events/s", file=sys.stderr, flush=True)
     return {"ms_per_step": round(ms, 4), "events_per_s": round(ev.n_events / ms * 1e3, 1),
-            "found_tracks": ph["n_found"], "efficiency_p_gt_5GeV": round(ph["efficiency"], 5),
-            "ghost_rate": round(ph["ghost_rate"], 5)}
+            "waves_per_block": wpb, "found_tracks": ph["n_found"],
+            "efficiency_p_gt_5GeV": round(ph["efficiency"], 5), "ghost_rate": round(ph["ghost_rate"], 5)}
 
 
-def paper_field_mode(lf, workload, n_events, stream, steps, warmup):
+def paper_field_mode(lf, workload, n_events, stream, steps, warmup, tune=True):
     """The same workload generated in the paper-form field (sqrt-normalised
     pt-kick, an integrated field that depends on the entry slopes and the
     bending, a falling tail) and followed with the kick solved for the
@@ -258,6 +267,7 @@ def paper_field_mode(lf, workload, n_events, stream, steps, warmup):
         try:
             bid = lf.lf_upload_events(ctx, ev, stream.cuda_stream)
             if label == "fitted":
+                wpb = tune_batched(ctx, bid, stream, tune)
                 ms, _ = time_mode(lf, ctx, bid, lf.LF_MODE_BATCHED, max(5, steps // 2), warmup, stream)
             else:
                 lf.lf_find_tracks(ctx, bid, lf.LF_MODE_BATCHED, stream.cuda_stream)
@@ -270,7 +280,7 @@ def paper_field_mode(lf, workload, n_events, stream, steps, warmup):
           f"q/p resolution {ph['qop_resolution']:.4f} (constant F: {ph_c['qop_resolution']:.4f})",
           file=sys.stderr, flush=True)
     return {"ms_per_step": round(ms, 4), "events_per_s": round(ev.n_events / ms * 1e3, 1),
-            "events": ev.n_events, "input_tracks": ev.n_tracks, "hits": ev.n_hits,
+            "waves_per_block": wpb, "events": ev.n_events, "input_tracks": ev.n_tracks, "hits": ev.n_hits,
             "found_tracks": ph["n_found"], "efficiency_p_gt_5GeV": round(ph["efficiency"], 5),
             "ghost_rate": round(ph["ghost_rate"], 5), "qop_resolution": round(ph["qop_resolution"], 5),
             "qop_resolution_constant_F": round(ph_c["qop_resolution"], 5)}
@@ -303,12 +313,13 @@ def scan_window(lf, world, ev, stream, steps, warmup, workload):
         ctx = lf.lf_create(world, {"n_hits_window": n})
         try:
             bid = lf.lf_upload_events(ctx, ev, stream.cuda_stream)
+            wpb = tune_batched(ctx, bid, stream, True)
             ms, _ = time_mode(lf, ctx, bid, lf.LF_MODE_BATCHED, steps, warmup, stream)
             out = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
         finally:
             lf.lf_destroy(ctx)
         ph = truth.physics(ev, out, p_min=5.0)
-        rows.append({"n_hits_window": n, "ms_per_step": round(ms, 4), "events_per_s": round(ev.n_events / ms * 1e3, 1),
+        rows.append({"n_hits_window": n, "waves_per_block": wpb, "ms_per_step": round(ms, 4), "events_per_s": round(ev.n_events / ms * 1e3, 1),
                      "efficiency_p_gt_5GeV": round(ph["efficiency"], 5), "ghost_rate": round(ph["ghost_rate"], 5),
                      "found_tracks": ph["n_found"], "qop_resolution": round(ph["qop_resolution"], 6)})
         print(f"bench: n_hits_window {n:3d}  {ms:8.3f} ms/step  efficiency {ph['efficiency']:.4f}  "
@@ -418,8 +429,9 @@ def main():
     out = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
     e2e = end_to_end(lf, ctx, ev, stream)
     variants = set(args.variants.split(","))
-    no_ut = no_ut_mode(lf, world, ev, stream, args.steps, args.warmup) if "no_ut" in variants else None
-    paper = (paper_field_mode(lf, args.workload, args.events, stream, args.steps, args.warmup)
+    tune = not args.no_autotune
+    no_ut = no_ut_mode(lf, world, ev, stream, args.steps, args.warmup, tune) if "no_ut" in variants else None
+    paper = (paper_field_mode(lf, args.workload, args.events, stream, args.steps, args.warmup, tune)
              if "paper" in variants else None)
     print(f"bench: end to end {e2e['ms_per_batch']:8.3f} ms/batch  {e2e['events_per_s']:12.0f} events/s",
           file=sys.stderr, flush=True)
