@@ -108,6 +108,28 @@ def test_per_hit_z_and_slope(z_mm, slope_rel):
     _check_all_modes(ev, f"nominal[5] z+-{z_mm} slope+-{slope_rel}")
 
 
+def _jitter_layers(ev, layers, z_mm, slope_rel, seed):
+    """Per-hit z and stereo slope on some layers only: mixed and common
+    windows side by side in one track."""
+    rng = np.random.default_rng(seed)
+    sel = np.isin(ev.hit_z, np.array([lfgen.LAYER_Z[l] for l in layers], np.float32))
+    hz = ev.hit_z + np.where(sel, rng.uniform(-z_mm, z_mm, ev.n_hits), 0.0).astype(np.float32)
+    hd = ev.hit_dxdy * (1.0 + np.where(sel, rng.uniform(-slope_rel, slope_rel, ev.n_hits), 0.0)).astype(np.float32)
+    return lfgen.Events(**{**ev.__dict__, "hit_z": hz.astype(np.float32), "hit_dxdy": hd.astype(np.float32)})
+
+
+@pytest.mark.parametrize("n_hits_window", [64, 48, 32])
+def test_per_hit_geometry_with_x_only_staging(n_hits_window):
+    """Windows of more than 32 hits stage only x and read a mixed window's z
+    and slopes from HBM: all layers mixed, and some layers mixed."""
+    params = {"n_hits_window": n_hits_window}
+    ev = _jitter(lfgen.generate("nominal", n_events=4), 1.5, 0.02, seed=13)
+    _check_all_modes(ev, f"nominal[4] w{n_hits_window} per-hit z and slope", params)
+    ev = _jitter_layers(lfgen.generate("nominal", n_events=4), (0, 5, 9, 11), 2.0, 0.03, seed=14)
+    _check_all_modes(ev, f"nominal[4] w{n_hits_window} layers 0 5 9 11 mixed", params)
+    _check_all_modes(ev, f"nominal[4] w{n_hits_window} layers 0 5 9 11 mixed, no-UT", dict(NO_UT, **params))
+
+
 def test_inverted_windows():
     """Negative tolerances: high-momentum x windows have x_max < x_min
     (empty), the stereo windows have their centre outside the bounds."""
