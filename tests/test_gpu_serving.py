@@ -76,3 +76,23 @@ def test_backpressure_under_small_budget(pool):
         assert e.value.code == lf.LF_ERR_TOO_LARGE
     finally:
         lf.lf_destroy(ctx)
+
+
+def test_paper_field_and_no_ut_served():
+    """The serving loop under the paper-form field (kick solved per track,
+    q/p from F) and under the no-UT tuning gives each request the oracle's
+    result for its event alone."""
+    from paper_2402_14670_amd import lf
+    ev = lfgen.generate("nominal", field="paper", n_events=30)
+    world = lfgen.world("paper")
+    for params in (None, {"velo_only": 1}):
+        ref = event_digests(oracle.run(ev, world, params), ev.trk_off)
+        req, arr = _stream(ev.n_events, 600, 20000.0, seed=41)
+        ctx = lf.lf_create(world, params)
+        try:
+            say(f"[gpu] serving paper field params={params} requests={len(req)}")
+            dig, lat, st = lf.lf_serve_run(ctx, ev, req, arr, {})
+        finally:
+            lf.lf_destroy(ctx)
+        bad = np.nonzero(dig != ref[req])[0]
+        assert len(bad) == 0, f"{len(bad)} requests differ from the oracle, first {bad[:5]}"
