@@ -102,3 +102,13 @@ def test_check_batch_rejects_malformed(lf, case):
         lf.lf_check_batch(bad)
     assert e.value.code == lf.LF_ERR_INVALID
     assert "batch" in str(e.value)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N > 1 exits with a message before touching a GPU."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr and r.stdout == ""

@@ -328,6 +328,13 @@ def test_error_codes():
     with pytest.raises(lf.LFError) as e:
         lf.lf_create(W, {"n_triplets": 33})
     assert e.value.code == lf.LF_ERR_INVALID
+    # geometry: unknown momentum form, non-finite F coefficient, zero kick in the linear form
+    for bad in (dict(W, field_form=2), dict(lfgen.world("paper"), F_coef=[float("nan")] + [0.0] * 49),
+                dict(W, kick=0.0)):
+        with pytest.raises(lf.LFError) as e:
+            lf.lf_create(bad)
+        assert e.value.code == lf.LF_ERR_INVALID
+    lf.lf_destroy(lf.lf_create(dict(lfgen.world("paper"), kick=0.0)))   # the paper form does not use kick
 
 
 @pytest.mark.parametrize("mode", ["batched", "persistent", "plain"])
