@@ -56,7 +56,7 @@ BYTES_PER_TRACK_OUT = 78
 # HBM traffic of the batched kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (per launch, scaled by the counters' reading of a known-size copy), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha256": "b7129ec18acfc10e8f1020b5a7d544116eeefc37e13bd214fe50517215b2fac4",
+TRAFFIC = {"kernel_sha256": "3ced7ba079ac12a16b5fb3ad4facf85ee504ad8c3d6c881d0e538b9968661f31",
            "bytes_per_launch": 80151882}
 WORKLOADS = {
     "nominal": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",

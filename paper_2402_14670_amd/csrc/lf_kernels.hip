@@ -3,22 +3,27 @@
 // One wavefront (64 lanes) carries one upstream input track through every
 // step of the method (arXiv 2402.14670, "Algorithm logic"):
 //
-//   windows    36 lanes: (layer, bound) binary searches over the x-sorted
-//              bucket in HBM; 12 lanes apply the symmetric cap
-//              ("Defining the search windows").
-//   staging    the <= 12 x n_hits_window window hits (x, z, dxdy) are read
-//              coalesced from HBM into this wave's LDS slice.
-//   doublets   all (h0, h2) pairs of both seed sets, one pair per lane,
-//              filtered by charge and magnet opening; survivors compacted
-//              with ballot + mbcnt into an LDS queue ("Triplet Seeding").
+//   windows    the kick (linear, or the sqrt-normalised pt-kick with the
+//              momentum parametrisation F), then 36 lanes: (layer, bound)
+//              binary searches over the x-sorted bucket in HBM; 12 lanes
+//              apply the symmetric cap ("Defining the search windows").
+//   staging    the <= 12 x n_hits_window window hits are read coalesced from
+//              HBM into this wave's LDS slice: x, z and dxdy per hit, or x
+//              only where LDS bounds the occupancy.
+//   doublets   one first-layer hit of a seed set per lane; the range of
+//              third-layer hits that can pass the magnet filter is
+//              bracketed by a sorted search, each pair in it tested with the
+//              charge and magnet-opening filters; survivors compacted with
+//              ballot + mbcnt into an LDS queue ("Triplet Seeding").
 //   triplets   64 queued doublets per pass search the middle layer for the
 //              closest hit; accepted triplets merge into an exact top-n list
-//              keyed by (chi2, set, h0, h2) by rank counting.
+//              keyed by (chi2, side, set, h0, h2) by rank counting.
 //   extension  lanes = (candidate, missing layer): closest hit to the
 //              triplet's x(z) model ("Extending triplets to other layers").
-//   fit        one lane per candidate: x and y least squares, Q, cuts
-//              ("Quality Filter"); wave argmin over (Q, rank) picks the
-//              track; q/p from the slope change ("Calculation of momentum").
+//   fit        16 lanes per candidate (lane = layer slot), four candidates
+//              per pass: x and y least squares, Q, cuts ("Quality Filter");
+//              the argmin over (Q, rank) picks the track; q/p from the slope
+//              change ("Calculation of momentum and track states").
 //
 // The arithmetic is binary32 in a fixed order (the library is built with
 // -ffp-contract=off, correctly rounded division, no fast-math), so every
