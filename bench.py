@@ -48,6 +48,12 @@ OPS_PER_UNIT = {
     "kept": 328,           # triplet model 28, nine closest-hit searches 270, candidate rule 30
     "fitted": 514,         # x and y least squares, residuals, Q
 }
+# No-UT tuning: two windows per layer, 72 bound searches per track, straight
+# extrapolation (the other units cost the same).
+NO_UT_TRACK_OPS = 2100
+# Paper-form kick per track: the five coefficients of F (42 terms), the sine
+# of the input slope, three solves of the kick equation.
+PAPER_KICK_OPS = 150
 # Algorithmic HBM bytes: 12 B per hit in (x, z, dxdy), 20 B per input track
 # in, 78 B per track out, plus the offsets.
 BYTES_PER_HIT_IN = 12
@@ -223,6 +229,19 @@ def truth_summary(ev, out) -> dict:
             "qop_resolution": ph["qop_resolution"], "reconstructible_p_gt_5GeV": ph["n_reconstructible"]}
 
 
+def alu_roofline(lf, ctx, bid, stream, ms, track_ops=None, extra_per_track=0):
+    """Algorithmic lane-ops of one launch from the counting build, and their
+    rate against the VALU peak."""
+    work = lf.lf_work_counts(ctx, bid, stream.cuda_stream)
+    ops = sum(OPS_PER_UNIT[k] * work[k] for k in OPS_PER_UNIT)
+    if track_ops is not None:
+        ops += (track_ops - OPS_PER_UNIT["tracks"]) * work["tracks"]
+    ops += extra_per_track * work["tracks"]
+    achieved = ops / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
+            "frac": round(achieved / VALU_PEAK_TOPS, 4), "ops_per_launch": ops}
+
+
 def tune_batched(ctx, bid, stream, tune):
     """Wavefronts per block of the batched mode, autotuned (or the default)."""
     if not tune:
@@ -240,6 +259,7 @@ def no_ut_mode(lf, world, ev, stream, steps, warmup, tune=True):
         bid = lf.lf_upload_events(ctx, ev, stream.cuda_stream)
         wpb = tune_batched(ctx, bid, stream, tune)
         ms, _ = time_mode(lf, ctx, bid, lf.LF_MODE_BATCHED, max(5, steps // 2), warmup, stream)
+        roof = alu_roofline(lf, ctx, bid, stream, ms, track_ops=NO_UT_TRACK_OPS)
         out = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
     finally:
         lf.lf_destroy(ctx)
@@ -247,7 +267,8 @@ def no_ut_mode(lf, world, ev, stream, steps, warmup, tune=True):
     print(f"bench: no-UT      {ms:8.3f} ms/step  {ev.n_events / ms * 1e3:12.0f} events/s", file=sys.stderr, flush=True)
     return {"ms_per_step": round(ms, 4), "events_per_s": round(ev.n_events / ms * 1e3, 1),
             "waves_per_block": wpb, "found_tracks": ph["n_found"],
-            "efficiency_p_gt_5GeV": round(ph["efficiency"], 5), "ghost_rate": round(ph["ghost_rate"], 5)}
+            "efficiency_p_gt_5GeV": round(ph["efficiency"], 5), "ghost_rate": round(ph["ghost_rate"], 5),
+            "roofline": roof}
 
 
 def paper_field_mode(lf, workload, n_events, stream, steps, warmup, tune=True):
@@ -269,6 +290,7 @@ def paper_field_mode(lf, workload, n_events, stream, steps, warmup, tune=True):
             if label == "fitted":
                 wpb = tune_batched(ctx, bid, stream, tune)
                 ms, _ = time_mode(lf, ctx, bid, lf.LF_MODE_BATCHED, max(5, steps // 2), warmup, stream)
+                roof = alu_roofline(lf, ctx, bid, stream, ms, extra_per_track=PAPER_KICK_OPS)
             else:
                 lf.lf_find_tracks(ctx, bid, lf.LF_MODE_BATCHED, stream.cuda_stream)
             res[label] = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
@@ -283,7 +305,7 @@ def paper_field_mode(lf, workload, n_events, stream, steps, warmup, tune=True):
             "waves_per_block": wpb, "events": ev.n_events, "input_tracks": ev.n_tracks, "hits": ev.n_hits,
             "found_tracks": ph["n_found"], "efficiency_p_gt_5GeV": round(ph["efficiency"], 5),
             "ghost_rate": round(ph["ghost_rate"], 5), "qop_resolution": round(ph["qop_resolution"], 5),
-            "qop_resolution_constant_F": round(ph_c["qop_resolution"], 5)}
+            "qop_resolution_constant_F": round(ph_c["qop_resolution"], 5), "roofline": roof}
 
 
 def end_to_end(lf, ctx, ev, stream, reps=3):
