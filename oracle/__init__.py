@@ -46,7 +46,8 @@ class Params(ctypes.Structure):
         "p_charge_cut")] + [("C_nhits", ctypes.c_float * 4), ("n_hits_window", ctypes.c_int32),
                             ("n_triplets", ctypes.c_int32), ("velo_only", ctypes.c_int32),
                             ("noUT_c", ctypes.c_float * 8), ("noUT_p_min", ctypes.c_float),
-                            ("noUT_pt_min", ctypes.c_float), ("noUT_overlap", ctypes.c_float)]
+                            ("noUT_pt_min", ctypes.c_float), ("noUT_overlap", ctypes.c_float),
+                            ("seed_fp16", ctypes.c_int32)]
 _ARRAYS = ("C_nhits", "noUT_c")
 
 
@@ -75,6 +76,8 @@ _lib = None
 
 def _bind(lib):
     lib.lfo_default_params.argtypes = [ctypes.POINTER(Params)]
+    lib.lfo_h16.argtypes = [ctypes.c_float]
+    lib.lfo_h16.restype = ctypes.c_float
     lib.lfo_default_params_no_ut.argtypes = [ctypes.POINTER(Params)]
     lib.lfo_find_tracks.restype = ctypes.c_int
     lib.lfo_find_tracks.argtypes = (
@@ -196,3 +199,8 @@ def run(ev, world: dict, params: dict | None = None, events: tuple[int, int] | N
     if rc != 0:
         raise ValueError("lfo_find_tracks rejected its arguments")
     return out
+
+
+def h16(x: float, lib=None) -> float:
+    """The oracle's binary16 rounding of one binary32 value."""
+    return float((lib or _load()).lfo_h16(float(x)))

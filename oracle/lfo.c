@@ -109,6 +109,36 @@ static int triplet_cmp(const void *pa, const void *pb) {
     return 0;
 }
 
+/* The binary16 value nearest to x (IEEE 754 round to nearest, ties to even;
+ * subnormals below 2^-14 with the quantum 2^-24; 65520 and above round to
+ * infinity), returned as a binary32.  A binary16 operation on binary16
+ * operands is the binary32 operation rounded by h16: binary32 carries more
+ * than twice binary16's precision plus two bits, so the double rounding is
+ * exact for +, -, * and /.  [H1] */
+static float h16(float x) {
+    if (x != x) return x;
+    float ax = fabsf(x);
+    if (ax >= 65520.0f) return copysignf(INFINITY, x);
+    float q;
+    if (ax < 6.103515625e-05f) {
+        q = 5.9604644775390625e-08f;
+    } else {
+        int e;
+        frexpf(ax, &e);            /* ax = m 2^e, m in [0.5, 1): 11 significant bits end at 2^(e - 11) */
+        q = ldexpf(1.0f, e - 11);
+    }
+    return copysignf(rintf(ax / q) * q, x);
+}
+
+float lfo_h16(float x) { return h16(x); }
+
+/* All hits of [first, last) share one z, bit for bit (an empty window does). */
+static int common_z(const event_view *ev, int first, int last) {
+    for (int i = first + 1; i < last; ++i)
+        if (memcmp(&ev->z[i], &ev->z[first], sizeof(float)) != 0) return 0;
+    return 1;
+}
+
 /* Closest hit to x_expected inside [first, last): linear scan, strict '<'
  * so the lowest index wins a tie [R12].  Returns -1 if none is finite. */
 static int closest_x(const event_view *ev, int first, int last, float x_expected, float *dist) {
@@ -321,9 +351,67 @@ static void track_one(const lfo_geometry *G, const lfo_params *P, const event_vi
     for (int s = 0; s < 2; ++s) {
         int l0 = SEED_SETS[s][0], l1 = SEED_SETS[s][1], l2 = SEED_SETS[s][2];
         float K = s == 0 ? P->K_first : P->K_last;
+        /* binary16 seeding [H2]-[H5]: coordinates relative to the window
+         * centres c_l = x_ext(z_l) of the three layers, the windows' common
+         * z0 and z2, per-set constants rounded once from binary32 */
+        int half = P->seed_fp16 && common_z(ev, wfirst[sd][l0], wlast[sd][l0]) &&
+                   common_z(ev, wfirst[sd][l2], wlast[sd][l2]) &&
+                   wlast[sd][l0] > wfirst[sd][l0] && wlast[sd][l2] > wfirst[sd][l2];
+        float c0 = x_ext[l0], c1 = x_ext[l1], c2 = x_ext[l2];
+        float RZ = 0, C02 = 0, E0 = 0, L0 = 0, A = 0, KK = 0, B = 0, TX = 0, QP = 0, TC = 0, TXS = 0, TMIN = 0,
+              TMAX = 0, T3 = 0;
+        if (half) {
+            float zw0 = ev->z[wfirst[sd][l0]], zw2 = ev->z[wfirst[sd][l2]];
+            RZ = h16(1.0f / (zw2 - zw0));
+            C02 = h16(c2 - c0);
+            E0 = h16(c0 - x_mag);
+            L0 = h16(G->z_mag - zw0);
+            A = h16(G->z[l1] - zw0 * K);
+            KK = h16(K);
+            B = h16(c0 * K - c1);
+            TX = h16(tx_in);
+            QP = h16(qop);
+            TC = h16(P->magtol_const + P->magtol_pscale / p);
+            TXS = h16(P->magtol_txscale);
+            TMIN = h16(P->magtol_min);
+            TMAX = h16(P->magtol_max);
+            T3 = h16(P->T_triplet);
+        }
         for (int i0 = wfirst[sd][l0]; i0 < wlast[sd][l0]; ++i0) {
             for (int i2 = wfirst[sd][l2]; i2 < wlast[sd][l2]; ++i2) {
                 ++n_pairs;
+                if (half) {
+                    float X0 = h16(ev->x[i0] - c0), X2 = h16(ev->x[i2] - c2);
+                    /* the doublet's slope, and the two filters [H3] */
+                    float t = h16(h16(h16(X2 - X0) + C02) * RZ);
+                    if (p < P->p_charge_cut && !(h16(h16(t - TX) * QP) > 0.0f)) continue;
+                    float M = h16(h16(E0 + X0) + h16(t * L0));
+                    float tol = h16(TC + h16(TXS * fabsf(t)));
+                    if (tol < TMIN) tol = TMIN;
+                    if (tol > TMAX) tol = TMAX;
+                    if (!(fabsf(M) < tol)) continue;
+                    ++n_doublets;
+                    /* middle hit relative to c1, closest by linear scan [H4] */
+                    float X1e = h16(h16(h16(t * A) + h16(X0 * KK)) + B);
+                    int i1 = -1;
+                    float bd = INFINITY;
+                    for (int i = wfirst[sd][l1]; i < wlast[sd][l1]; ++i) {
+                        float dd = fabsf(h16(h16(ev->x[i] - c1) - X1e));
+                        if (dd < bd) { bd = dd; i1 = i; }
+                    }
+                    if (i1 < 0) continue;
+                    float chi2 = h16(bd * bd);
+                    if (!(chi2 < T3)) continue;
+                    if (ntrip == cap) {
+                        cap *= 2;
+                        triplet *nt = (triplet *)realloc(trips, cap * sizeof(triplet));
+                        if (!nt) { free(trips); return; }
+                        trips = nt;
+                    }
+                    triplet th = {chi2, sd, s, i0, i1, i2};
+                    trips[ntrip++] = th;
+                    continue;
+                }
                 float x0 = ev->x[i0], z0 = ev->z[i0];
                 float x2 = ev->x[i2], z2 = ev->z[i2];
                 float txd = (x2 - x0) / (z2 - z0);
@@ -571,6 +659,8 @@ int lfo_find_tracks(const lfo_geometry *g, const lfo_params *P, uint32_t n_event
         return -1;
     if (P->n_triplets < 1 || P->n_triplets > LFO_MAX_TRIPLETS || P->n_hits_window < 1) return -1;
     if (g->field_form != 0 && g->field_form != 1) return -1;
+    if (P->seed_fp16 != 0 && P->seed_fp16 != 1) return -1;
+    if (P->seed_fp16 && P->velo_only) return -1;
     const int NT = P->n_triplets;
     for (uint32_t e = ev_begin; e < ev_end; ++e) {
         uint32_t base = hit_off[24 * e];

@@ -67,6 +67,13 @@ typedef struct {
     float noUT_p_min;     /* assumed minimum momentum, GeV */
     float noUT_pt_min;    /* assumed minimum transverse momentum, GeV */
     float noUT_overlap;   /* overlap of the two windows of a layer, mm */
+    /* Triplet seeding in binary16 (Performance section: the seeding needs
+     * only half precision).  1: the doublet filters and the middle-hit chi2
+     * of a seed set whose first- and last-layer windows each share one z
+     * are evaluated in binary16 on coordinates relative to the window
+     * centres, every pair of the windows tested; other sets, and every other
+     * step, stay binary32.  VELO-UT input only (velo_only = 0). */
+    int32_t seed_fp16;
 } lfo_params;
 
 /* One result slot per input track.  hit_idx is event-local (index into the
@@ -105,5 +112,9 @@ int lfo_find_tracks(const lfo_geometry *g, const lfo_params *P, uint32_t n_event
                     const float *trk_y, const float *trk_tx, const float *trk_ty,
                     const float *trk_qop, uint32_t ev_begin, uint32_t ev_end,
                     lfo_out *out, lfo_debug *dbg);
+
+/* The binary16 value nearest to x, as a binary32 (round to nearest even,
+ * subnormals, overflow to infinity): the rounding of the binary16 seeding. */
+float lfo_h16(float x);
 
 #endif

@@ -209,13 +209,14 @@ def pin_window_edges_closed(lib=None):
     assert not (win < xmin).any() and not (win > xmax).any(), "hits beyond the edges must be outside"
 
 
-def closed_form_triplet_residual() -> tuple[float, float]:
+def closed_form_triplet_residual(Ks=(1.00177513, 1.00142634)) -> tuple[float, float]:
     """Middle-hit residual per unit dtx for each seed set, derived in float64
-    from the toy field and the paper's K factors (independent of the oracle):
-    x1_true - [z1*t + (x0 - t*z0)*K] for the line t through (z0,x0),(z2,x2)."""
+    from the toy field and the K factors (the paper's by default; independent
+    of the oracle): x1_true - [z1*t + (x0 - t*z0)*K] for the line t through
+    (z0,x0),(z2,x2)."""
     z = W["z"]
     out = []
-    for (l0, l1, l2), K in zip(SEED_SETS, (1.00177513, 1.00142634)):
+    for (l0, l1, l2), K in zip(SEED_SETS, Ks):
         # residual is linear in dtx and independent of tx: evaluate at dtx = 1, tx = 0
         x = [(z[i] - W["z_mag"]) + W["kappa"] * (z[i] - W["z_T"]) ** 2 for i in (l0, l1, l2)]
         t = (x[2] - x[0]) / (z[l2] - z[l0])
@@ -1056,8 +1057,94 @@ def pin_F_single_terms(lib=None):
 PAPER_FIELD_PINS = [pin_kick_extrapolation_exact, pin_kick_momentum_exact, pin_paper_extrapolation,
                     pin_paper_momentum, pin_paper_no_kick_solution, pin_paper_physics, pin_F_single_terms]
 
+
+# ------------------------------------------------------------------ binary16 seeding
+FP16 = {"seed_fp16": 1}
+
+
+def pin_h16_is_ieee_half(lib=None):
+    """The oracle's binary16 rounding equals numpy's float16 conversion (IEEE
+    754 round to nearest even) on normal, subnormal, tie and overflowing
+    values."""
+    rng = np.random.default_rng(5)
+    vals = np.concatenate([
+        rng.uniform(-3000, 3000, 4000), rng.uniform(-1, 1, 2000) * 10.0 ** rng.integers(-9, 5, 2000),
+        (np.arange(-2048, 2048) + 0.5) * 2.0 ** rng.integers(-24, 6, 4096),     # ties at many scales
+        np.array([65503.0, 65504.0, 65519.0, 65520.0, 70000.0, -65520.0, 6.1e-5, 6.0e-5, 2.0 ** -25,
+                  2.0 ** -25 * 3, 0.0, -0.0])]).astype(np.float32)
+    got = np.array([oracle.h16(v, lib) for v in vals], np.float32)
+    with np.errstate(over="ignore"):
+        want = vals.astype(np.float16).astype(np.float32)
+    same = (got == want) | (np.isnan(got) & np.isnan(want))
+    assert same.all(), (vals[~same][:5], got[~same][:5], want[~same][:5])
+    assert np.array_equal(np.signbit(got), np.signbit(want))
+
+
+def pin_fp16_true_triplets(lib=None):
+    """binary16 seeding, noise-free tracks: every true triplet is accepted with
+    a chi2 whose root matches the closed-form sagitta residual to the binary16
+    accuracy of the window-relative coordinates (0.5 mm), with the paper's K
+    and with K = 1.01, which makes the residuals a few mm (chi2 cut 100)."""
+    ev = ev_noise_free()
+    for Ks, extra in (((1.00177513, 1.00142634), {}),
+                      ((1.01, 1.01), {"K_first": 1.01, "K_last": 1.01, "T_triplet": 100.0})):
+        o = oracle.run(ev, W, debug=True, lib=lib, params=dict(FP16, n_triplets=64, **extra))
+        cf = closed_form_triplet_residual(Ks)
+        T = extra.get("T_triplet", 8.0)
+        checked = 0
+        for t in range(ev.n_tracks):
+            p, q, tx, ty = particle(ev, t)
+            dtx = 1.2 * q / p
+            for s, layers in enumerate(SEED_SETS):
+                hs = [truth_hit(ev, t, l) for l in layers]
+                if min(hs) < 0:
+                    continue
+                expect = abs(cf[s] * dtx)
+                if (expect + 0.5) ** 2 >= T:
+                    continue
+                rows = np.nonzero((o["trip"][t, :, 0] == s) & (o["trip"][t, :, 1] == hs[0]) &
+                                  (o["trip"][t, :, 3] == hs[2]))[0]
+                assert len(rows) == 1, f"true doublet missing t={t} set={s} K={Ks}"
+                got = math.sqrt(float(o["trip_chi2"][t, rows[0]]))
+                if o["trip"][t, rows[0], 2] == hs[1]:
+                    assert abs(got - expect) < 0.5, (t, s, got, expect, Ks)
+                    checked += 1
+        assert checked > 40, checked
+
+
+def pin_fp16_physics(lib=None):
+    """binary16 seeding changes only tracks whose seeding decisions sit within
+    the half-precision error of a cut: on nominal events at least 98% of the
+    outputs equal the binary32 ones and efficiency and ghost rate move by less
+    than 0.5%."""
+    ev = ev_nominal(4)
+    o32 = oracle.run(ev, W, lib=lib)
+    o16 = oracle.run(ev, W, FP16, lib=lib)
+    same = (o32["found"] == o16["found"]) & np.all(o32["hit_idx"] == o16["hit_idx"], axis=1)
+    assert same.mean() >= 0.98, same.mean()
+    a, b = truth.physics(ev, o32, p_min=5.0), truth.physics(ev, o16, p_min=5.0)
+    assert abs(a["efficiency"] - b["efficiency"]) < 0.005 and abs(a["ghost_rate"] - b["ghost_rate"]) < 0.005
+    assert b["efficiency"] > 0.95
+
+
+def pin_fp16_mixed_windows_stay_binary32(lib=None):
+    """A seed set whose first- or last-layer window has hits at different z is
+    seeded in binary32: with every hit's z jittered the binary16 option
+    changes nothing."""
+    ev = ev_nominal(2)
+    rng = np.random.default_rng(9)
+    hz = (ev.hit_z + rng.uniform(-20.0, 20.0, ev.n_hits)).astype(np.float32)
+    ev = lfgen.Events(**{**ev.__dict__, "hit_z": hz})
+    o32 = oracle.run(ev, W, lib=lib)
+    o16 = oracle.run(ev, W, FP16, lib=lib)
+    for k in ("found", "hit_idx", "qop", "Q"):
+        assert np.array_equal(o32[k], o16[k]), k
+
+
+FP16_PINS = [pin_h16_is_ieee_half, pin_fp16_true_triplets, pin_fp16_physics, pin_fp16_mixed_windows_stay_binary32]
+
 ALL_PINS = [pin_constants, pin_extrapolation_noise_free, pin_window_bounds, pin_window_search,
             pin_window_edges_closed, pin_triplet_closed_form, pin_magnet_threshold,
             pin_charge_filter, pin_bruteforce_triplets, pin_fit_noise_free, pin_fit_lstsq,
             pin_y_fit_recovers_slope, pin_physics_single, pin_invariants, pin_batch_independence,
-            pin_tie_breaks, pin_extension_rule, pin_nine_hit_tracks] + NO_UT_PINS + PAPER_FIELD_PINS
+            pin_tie_breaks, pin_extension_rule, pin_nine_hit_tracks] + NO_UT_PINS + PAPER_FIELD_PINS + FP16_PINS

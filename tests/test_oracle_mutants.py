@@ -87,6 +87,20 @@ MUTANTS = [
      "(kick_s(txT, best_par[4]) + kick_s(tx_in, ty_in))"),
     ("pf_momentum_linear", "qop_out = (kick_s(txT, best_par[4]) - kick_s(tx_in, ty_in)) /",
      "qop_out = (txT - tx_in) /"),
+    # binary16 seeding
+    ("fp16_C02_dropped", "float t = h16(h16(h16(X2 - X0) + C02) * RZ);", "float t = h16(h16(X2 - X0) * RZ);"),
+    ("fp16_B_dropped", "float X1e = h16(h16(h16(t * A) + h16(X0 * KK)) + B);",
+     "float X1e = h16(h16(t * A) + h16(X0 * KK));"),
+    ("fp16_E0_sign", "float M = h16(h16(E0 + X0) + h16(t * L0));", "float M = h16(h16(X0 - E0) + h16(t * L0));"),
+    ("fp16_RZ_not_inverted", "RZ = h16(1.0f / (zw2 - zw0));", "RZ = h16(zw2 - zw0);"),
+    ("fp16_middle_wrong_centre", "float dd = fabsf(h16(h16(ev->x[i] - c1) - X1e));",
+     "float dd = fabsf(h16(h16(ev->x[i] - c2) - X1e));"),
+    ("fp16_chi2_not_squared", "float chi2 = h16(bd * bd);", "float chi2 = bd;"),
+    ("fp16_twelve_bits", "q = ldexpf(1.0f, e - 11);", "q = ldexpf(1.0f, e - 12);"),
+    ("fp16_subnormal_quantum", "q = 5.9604644775390625e-08f;", "q = 1.1920928955078125e-07f;"),
+    ("fp16_mixed_windows_in_half",
+     "common_z(ev, wfirst[sd][l0], wlast[sd][l0]) &&\n                   common_z(ev, wfirst[sd][l2], wlast[sd][l2]) &&",
+     "1 &&"),
 ]
 
 
