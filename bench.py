@@ -89,9 +89,9 @@ def parse():
                     help="comma-separated subset of batched,persistent,plain to time (batched is always timed)")
     ap.add_argument("--serve-requests", type=int, default=200000,
                     help="requests per serving run (0 skips the serving runs)")
-    ap.add_argument("--variants", default="no_ut,paper",
+    ap.add_argument("--variants", default="no_ut,paper,fp16",
                     help="method variants timed after the main modes: no_ut (VELO-only input), paper "
-                         "(paper-form field and momentum); 'none' for neither")
+                         "(paper-form field and momentum), fp16 (binary16 triplet seeding); 'none' for none")
     ap.add_argument("--scan-window", action="store_true",
                     help="instead of the throughput line: events/s and physics efficiency of the batched mode "
                          "for n_hits_window = 16, 32, 48, 64 (one JSON line)")
@@ -269,6 +269,29 @@ def no_ut_mode(lf, world, ev, stream, steps, warmup, tune=True):
             "waves_per_block": wpb, "found_tracks": ph["n_found"],
             "efficiency_p_gt_5GeV": round(ph["efficiency"], 5), "ghost_rate": round(ph["ghost_rate"], 5),
             "roofline": roof}
+
+
+def fp16_mode(lf, world, ev, stream, steps, warmup, tune=True):
+    """The same batch with the triplet seeding in binary16 (the paper's
+    Performance section): packed half-precision doublet filters and
+    middle-hit search over every pair of the seed windows; batched mode."""
+    from lfgen import truth
+    ctx = lf.lf_create(world, {"seed_fp16": 1})
+    try:
+        bid = lf.lf_upload_events(ctx, ev, stream.cuda_stream)
+        wpb = tune_batched(ctx, bid, stream, tune)
+        ms, _ = time_mode(lf, ctx, bid, lf.LF_MODE_BATCHED, max(5, steps // 2), warmup, stream)
+        roof = alu_roofline(lf, ctx, bid, stream, ms)
+        out = lf.lf_fetch_tracks(ctx, bid, ev.n_tracks, stream.cuda_stream)
+    finally:
+        lf.lf_destroy(ctx)
+    ph = truth.physics(ev, out, p_min=5.0)
+    print(f"bench: fp16 seeding {ms:7.3f} ms/step  {ev.n_events / ms * 1e3:12.0f} events/s", file=sys.stderr,
+          flush=True)
+    return {"ms_per_step": round(ms, 4), "events_per_s": round(ev.n_events / ms * 1e3, 1),
+            "waves_per_block": wpb, "found_tracks": ph["n_found"],
+            "efficiency_p_gt_5GeV": round(ph["efficiency"], 5), "ghost_rate": round(ph["ghost_rate"], 5),
+            "qop_resolution": round(ph["qop_resolution"], 5), "roofline": roof}
 
 
 def paper_field_mode(lf, workload, n_events, stream, steps, warmup, tune=True):
@@ -455,6 +478,7 @@ def main():
     no_ut = no_ut_mode(lf, world, ev, stream, args.steps, args.warmup, tune) if "no_ut" in variants else None
     paper = (paper_field_mode(lf, args.workload, args.events, stream, args.steps, args.warmup, tune)
              if "paper" in variants else None)
+    fp16 = fp16_mode(lf, world, ev, stream, args.steps, args.warmup, tune) if "fp16" in variants else None
     print(f"bench: end to end {e2e['ms_per_batch']:8.3f} ms/batch  {e2e['events_per_s']:12.0f} events/s",
           file=sys.stderr, flush=True)
     serve = serving(lf, ctx, ev, out, args.serve_requests) if args.serve_requests else None
@@ -510,6 +534,7 @@ def main():
         "end_to_end": e2e,
         "no_ut": no_ut,
         "paper_field": paper,
+        "fp16_seeding": fp16,
     }
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(ev, world, args.cpu_seconds, out)

@@ -161,6 +161,18 @@ typedef struct {
     float noUT_p_min;      /* assumed minimum momentum, GeV: 5 */
     float noUT_pt_min;     /* assumed minimum transverse momentum, GeV: 1 */
     float noUT_overlap;    /* overlap of the two windows of a layer, mm: 5 */
+    /* Triplet seeding in binary16 (the paper's Performance section: seeding
+     * needs only half precision and runs two combinations per half2
+     * instruction).  seed_fp16 = 1: for a seed set whose first- and
+     * last-layer windows each share one z, every (h0, h2) pair is tested and
+     * the doublet slope, the charge and magnet filters and the middle-hit
+     * search and chi2 are evaluated in binary16 on coordinates relative to
+     * the window centres c_l (x - c_l rounded to binary16; per-set constants
+     * rounded once from binary32), two pairs per packed instruction; other
+     * sets and all other steps stay binary32.  Results are a separate parity
+     * domain from seed_fp16 = 0.  VELO-UT input only (velo_only = 0), else
+     * LF_ERR_INVALID. */
+    int32_t seed_fp16;     /* 0 (default) or 1 */
 } lf_params;
 
 /* A batch of events in host memory, ragged structure-of-arrays.  Hits are

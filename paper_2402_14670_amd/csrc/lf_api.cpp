@@ -85,6 +85,8 @@ int check_params(const lf_geometry *g, const lf_params *p, std::string &why) {
         return 0;
     }
     if (p->velo_only && !(p->noUT_p_min > 0.0f)) { why = "params: velo_only needs noUT_p_min > 0"; return 0; }
+    if (p->seed_fp16 != 0 && p->seed_fp16 != 1) { why = "params: seed_fp16 must be 0 or 1"; return 0; }
+    if (p->seed_fp16 && p->velo_only) { why = "params: seed_fp16 needs VELO-UT input (velo_only = 0)"; return 0; }
     return 1;
 }
 
@@ -105,6 +107,7 @@ lfk::KParams to_kparams(const lf_geometry &g, const lf_params &p) {
     for (int i = 0; i < 4; ++i) k.C_nhits[i] = p.C_nhits[i];
     k.n_hits_window = p.n_hits_window; k.n_triplets = p.n_triplets;
     k.velo_only = p.velo_only;
+    k.seed_fp16 = p.seed_fp16;
     for (int i = 0; i < 8; ++i) k.noUT_c[i] = p.noUT_c[i];
     k.noUT_p_min = p.noUT_p_min; k.noUT_pt_min = p.noUT_pt_min; k.noUT_overlap = p.noUT_overlap;
     return k;
@@ -175,7 +178,9 @@ namespace lfapi {
 int ctx_fail(lf_ctx *c, int code, const std::string &msg) { return fail(c, code, msg); }
 const lfk::KParams *ctx_dparams(const lf_ctx *c) { return c->d_params; }
 int ctx_nhits_window(const lf_ctx *c) { return c->params.n_hits_window; }
-int ctx_sides(const lf_ctx *c) { return c->params.velo_only ? 2 : 1; }
+// The kernel build a context launches: 1 VELO-UT, 2 VELO-only (two windows
+// per layer), 3 VELO-UT with binary16 seeding.
+int ctx_sides(const lf_ctx *c) { return c->params.velo_only ? 2 : (c->params.seed_fp16 ? 3 : 1); }
 const lfk::ExecCfg &ctx_exec(const lf_ctx *c) { return c->exec; }
 int check_batch(const lf_batch *b, std::string &why) { return validate(b, why); }
 }  // namespace lfapi
@@ -279,7 +284,7 @@ int lf_create(const lf_geometry *geom, const lf_params *params, size_t device_bu
         return fail(nullptr, LF_ERR_DEVICE, msg);
     }
     c->exec.n_cu = ncu;
-    c->exec.blocks_per_cu = lfk::persistent_blocks_per_cu(params->n_hits_window, params->velo_only ? 2 : 1,
+    c->exec.blocks_per_cu = lfk::persistent_blocks_per_cu(params->n_hits_window, params->velo_only ? 2 : (params->seed_fp16 ? 3 : 1),
                                                           c->exec.waves_per_block);
     if (c->exec.blocks_per_cu < 1) c->exec.blocks_per_cu = 1;
     *out = c;
@@ -293,7 +298,7 @@ int lf_set_exec(lf_ctx *c, const lf_exec *x) {
         if (x->waves_per_block != 1 && x->waves_per_block != 2 && x->waves_per_block != 4)
             return fail(c, LF_ERR_INVALID, "lf_set_exec: waves_per_block must be 1, 2 or 4");
         n.waves_per_block = x->waves_per_block;
-        n.blocks_per_cu = lfk::persistent_blocks_per_cu(c->params.n_hits_window, c->params.velo_only ? 2 : 1,
+        n.blocks_per_cu = lfk::persistent_blocks_per_cu(c->params.n_hits_window, lfapi::ctx_sides(c),
                                                         n.waves_per_block);
         if (n.blocks_per_cu < 1) n.blocks_per_cu = 1;
     }
@@ -391,7 +396,7 @@ int lf_find_tracks(lf_ctx *c, uint64_t batch_id, int mode, void *hip_stream) {
     if (mode != LF_MODE_PLAIN && mode != LF_MODE_BATCHED && mode != LF_MODE_PERSISTENT)
         return fail(c, LF_ERR_INVALID, "lf_find_tracks: unknown mode");
     Batch &bt = it->second;
-    const hipError_t e = lfk::launch_find(bt.dev, c->d_params, c->params.n_hits_window, c->params.velo_only ? 2 : 1,
+    const hipError_t e = lfk::launch_find(bt.dev, c->d_params, c->params.n_hits_window, lfapi::ctx_sides(c),
                                           mode, c->exec,
                                           bt.trk_off.data(), pick(c, hip_stream));
     if (e != hipSuccess) return hip_fail(c, e, "lf_find_tracks");
@@ -423,7 +428,7 @@ int lf_graph_create(lf_ctx *c, const uint64_t *ids, uint32_t n, int mode, lf_gra
     if (e == hipSuccess) {
         hipError_t le = hipSuccess;
         for (Batch *b : bs) {
-            le = lfk::launch_find(b->dev, c->d_params, c->params.n_hits_window, c->params.velo_only ? 2 : 1, mode,
+            le = lfk::launch_find(b->dev, c->d_params, c->params.n_hits_window, lfapi::ctx_sides(c), mode,
                                   c->exec, b->trk_off.data(), cs);
             if (le != hipSuccess) break;
         }
@@ -465,7 +470,7 @@ int lf_work_counts(lf_ctx *c, uint64_t batch_id, void *hip_stream, int64_t *coun
     unsigned long long host[32] = {0};
     hipError_t e = hipMemsetAsync(bt.dev.stats, 0, sizeof(host), s);
     if (e == hipSuccess)
-        e = lfk::launch_count(bt.dev, c->d_params, c->params.n_hits_window, c->params.velo_only ? 2 : 1, s);
+        e = lfk::launch_count(bt.dev, c->d_params, c->params.n_hits_window, lfapi::ctx_sides(c), s);
     if (e == hipSuccess) e = hipMemcpyAsync(host, bt.dev.stats, sizeof(host), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "lf_work_counts");

@@ -29,6 +29,8 @@ struct KParams {
     // integrated field F(tx, ty, dSlope) = sum_i c_i dSlope^i, c_i from F_coef
     int32_t field_form;
     float F_coef[5][10];
+    // Triplet seeding in binary16 (VELO-UT input only)
+    int32_t seed_fp16;
 };
 
 // Device view of one resident batch (SoA, all in HBM).
@@ -80,7 +82,8 @@ hipError_t launch_track_event(const DevBatch &b, hipStream_t s);
 // (per-event launches), 1 batched (one wavefront per track), 2 persistent
 // (resident wavefronts pulling from per-XCD work queues).
 // trk_off_host is read by mode 0 only.
-// n_sides: 1 for VELO-UT input, 2 for VELO-only input (two windows per layer).
+// n_sides: 1 for VELO-UT input, 2 for VELO-only input (two windows per
+// layer), 3 for VELO-UT input with the binary16 seeding build.
 hipError_t launch_find(const DevBatch &b, const KParams *P, int n_hits_window, int n_sides, int mode,
                        const ExecCfg &cfg, const uint32_t *trk_off_host, hipStream_t s);
 // Counting launch: one wavefront per track, adds the work counters of every

@@ -95,6 +95,11 @@ __device__ __forceinline__ bool is_uv(int l) {
     return k == 1 || k == 2;
 }
 
+// Packed binary16 pair: one instruction handles two seeding combinations.
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ _Float16 habs(_Float16 v) { return v < (_Float16)0.0f ? -v : v; }
+
 // x(z) model term g(u) = u^2 (1 + dRatio u), u = z - z_ref.
 __device__ __forceinline__ float g_of(float u, float dR) { return u * u * (1.0f + dR * u); }
 
@@ -250,7 +255,8 @@ enum { C_TRACKS, C_PAIRS_ALL, C_ITEMS, C_PAIRS_TESTED, C_DOUBLETS, C_TRIPLETS, C
        // shader-clock cycles spent per phase (counting build only)
        C_CY_WINDOWS, C_CY_STAGE, C_CY_DOUBLETS, C_CY_MODEL, C_CY_EXTEND, C_CY_FIT, C_CY_SELECT, C_N };
 
-template <int NW, int NS, bool CNT = false>
+// H16: the binary16 seeding build (seed_fp16, one window per layer).
+template <int NW, int NS, bool CNT = false, bool H16 = false>
 struct Track {
     const DevBatch &B;
     const KParams *__restrict__ P;
@@ -261,6 +267,17 @@ struct Track {
     // bit NL * side + layer: the window's hits do not all share one z
     // (zvar) or one stereo tangent (dvar); ebase: the event's first hit
     uint32_t zvar = 0, dvar = 0, ebase = 0;
+    // Binary16 seeding: per seed set, whether it runs in half precision
+    // (seed_fp16, both outer windows non-empty with one z each), the window
+    // centres and its constants; then the ones shared by both sets.
+    bool hon[2] = {false, false};
+    float hc0[2] = {0.0f, 0.0f}, hc1[2] = {0.0f, 0.0f}, hc2[2] = {0.0f, 0.0f};
+    _Float16 hRZ[2], hC02[2], hE0[2], hL0[2], hA[2], hKK[2], hB[2];
+    _Float16 hTX, hQP, hTC, hTXS, hTMIN, hTMAX, hT3;
+    // element s of a per-set pair, without indexing (a lane-dependent index
+    // would put the arrays in scratch memory)
+    template <class T>
+    __device__ __forceinline__ static T sel(const T (&a)[2], int s) { return s ? a[1] : a[0]; }
 
     // z and stereo tangent of hit i of a window: from LDS, or (XO) the
     // window's one value, or from HBM for a mixed window
@@ -328,11 +345,47 @@ struct Track {
             const int sd = NS > 1 ? (int)((e >> 17) & 1u) : 0;
             const int s = (int)((e >> 16) & 1u), i0 = (int)((e >> 8) & 0xffu), i2 = (int)(e & 0xffu);
             const int l0 = s ? 3 : 0, l1 = s ? 7 : 4, l2 = s ? 11 : 8;
+            float bd = INFINITY;
+            if (H16 && sel(hon, s)) {
+                // binary16: the slope as queued, the prediction relative to
+                // c1, the closest hit by a scan over pairs of hits
+                const _Float16 X0 = (_Float16)(L.wx[0][l0][i0] - sel(hc0, s));
+                const _Float16 X2 = (_Float16)(L.wx[0][l2][i2] - sel(hc2, s));
+                const _Float16 u = X2 - X0;
+                const _Float16 v = u + sel(hC02, s);
+                const _Float16 tt = v * sel(hRZ, s);
+                const _Float16 a1 = tt * sel(hA, s);
+                const _Float16 a2 = X0 * sel(hKK, s);
+                const _Float16 a3 = a1 + a2;
+                const _Float16 X1e = a3 + sel(hB, s);
+                const float *wx1 = L.wx[0][l1];
+                const int n1 = L.wlen[0][l1];
+                const float c1 = sel(hc1, s);
+                _Float16 hb = (_Float16)INFINITY;
+                const half2v e2 = {X1e, X1e};
+                for (int j = 0; j < n1; j += 2) {
+                    const int jb = j + 1 < n1 ? j + 1 : j;
+                    const half2v xv = {(_Float16)(wx1[j] - c1), (_Float16)(wx1[jb] - c1)};
+                    const half2v dv = xv - e2;
+                    const _Float16 da = habs(dv.x), db = habs(dv.y);
+                    if (da < hb) { hb = da; best = j; }
+                    if (j + 1 < n1 && db < hb) { hb = db; best = j + 1; }
+                }
+                if (best >= 0) {
+                    const _Float16 c2h = hb * hb;
+                    if (c2h < hT3) {
+                        tri = true;
+                        key = ((uint64_t)__float_as_uint((float)c2h) << 32) |
+                              (uint64_t)(uint32_t)((sd << 13) | (s << 12) | (i0 << 6) | i2);
+                        valid = nL < P->n_triplets || key < L.tk[nL - 1];
+                    }
+                }
+                best = tri ? best : -1;
+            } else {
             const float K = s ? P->K_last : P->K_first;
             const float x0 = L.wx[sd][l0][i0], z0 = zat(sd, l0, i0);
             const float txd = (L.wx[sd][l2][i2] - x0) / (zat(sd, l2, i2) - z0);   // the doublet's slope, as queued
             const float x1e = P->z[l1] * txd + (x0 - txd * z0) * K;
-            float bd = INFINITY;
             const float *wx1 = L.wx[sd][l1];
             best = closest_sorted<NW>([wx1](int j) { return wx1[j]; }, L.wlen[sd][l1], x1e, bd);
             if (best >= 0) {
@@ -345,6 +398,7 @@ struct Track {
                     // rank count of merge() would keep)
                     valid = nL < P->n_triplets || key < L.tk[nL - 1];
                 }
+            }
             }
         }
         if constexpr (CNT) cnt[C_TRIPLETS] += (uint32_t)__popcll(__ballot(tri));
@@ -429,6 +483,7 @@ struct Track {
 
         // ---- search windows: lane 3*l + k searches bound k of layer l, side by side ----
         int wf[NS], wl[NS];   // lane l < 12: first hit (event-local) and length of layer l's window
+        float xcl = 0.0f;     // lane 3 l + 1: the centre of layer l's window
 #pragma unroll
         for (int sd = 0; sd < NS; ++sd) {
             int pos = 0;
@@ -465,6 +520,7 @@ struct Track {
                         }
                     }
                     const float key = k == 0 ? xmin : (k == 1 ? xc : xmax);
+                    xcl = xc;
                     uint32_t lo = b0;
                     uint32_t n = b1 - b0;
                     // lower bound (x < key) for x_min and the centre, upper bound (x <= key) for x_max
@@ -571,6 +627,36 @@ struct Track {
         nL = 0;
         const float tolc = P->magtol_const + P->magtol_pscale / p;
         const bool low_p = NS == 1 && p < P->p_charge_cut;   // no bend-direction filter without q/p
+        constexpr bool seed16 = H16;
+        if constexpr (H16) {
+            // binary16 seeding: coordinates relative to the window centres,
+            // constants rounded once from binary32
+            hTX = (_Float16)tx_in;
+            hQP = (_Float16)qop;
+            hTC = (_Float16)tolc;
+            hTXS = (_Float16)P->magtol_txscale;
+            hTMIN = (_Float16)P->magtol_min;
+            hTMAX = (_Float16)P->magtol_max;
+            hT3 = (_Float16)P->T_triplet;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int l0 = s ? 3 : 0, l1 = s ? 7 : 4, l2 = s ? 11 : 8;
+                const float K = s ? P->K_last : P->K_first;
+                const float c0 = bcast_f(xcl, 3 * l0 + 1), c1 = bcast_f(xcl, 3 * l1 + 1), c2 = bcast_f(xcl, 3 * l2 + 1);
+                hon[s] = L.wlen[0][l0] > 0 && L.wlen[0][l2] > 0 && !(((zvar >> l0) | (zvar >> l2)) & 1u);
+                const float zw0 = L.wz[0][l0][0], zw2 = L.wz[0][l2][0];
+                hc0[s] = c0;
+                hc1[s] = c1;
+                hc2[s] = c2;
+                hRZ[s] = (_Float16)(1.0f / (zw2 - zw0));
+                hC02[s] = (_Float16)(c2 - c0);
+                hE0[s] = (_Float16)(c0 - x_mag);
+                hL0[s] = (_Float16)(P->z_mag - zw0);
+                hA[s] = (_Float16)(P->z[l1] - zw0 * K);
+                hKK[s] = (_Float16)K;
+                hB[s] = (_Float16)(c0 * K - c1);
+            }
+        }
         int qn = 0;
         // One item per (side, set, h0).  Each item gets the range of h2 in its third
         // window that can pass the magnet filter: with a common z per window,
@@ -623,29 +709,35 @@ struct Track {
                     }
                 }
             }
+            // binary16 sets test every pair of their windows
+            const bool h16 = seed16 && item < items_total && sel(hon, s);
+            if (h16) {
+                jlo = 0;
+                jhi = n2;
+            }
             int span = jhi - jlo;
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
                 const int o = __shfl_xor(span, off);
                 span = o > span ? o : span;
             }
-            for (int k = 0; k < span; ++k) {
-                const int i2 = jlo + k;
-                bool pass = false;
-                float txd = 0.0f;
-                if (i2 < jhi) {
-                    const float x2 = L.wx[sd][l2][i2], z2 = zat(sd, l2, i2);
-                    txd = (x2 - x0) / (z2 - z0);
-                    pass = !(low_p && !((txd - tx_in) * qop > 0.0f));
-                    const float xm = x0 + txd * (P->z_mag - z0);
-                    float tol = tolc + P->magtol_txscale * fabsf(txd);
-                    if (tol < P->magtol_min) tol = P->magtol_min;
-                    if (tol > P->magtol_max) tol = P->magtol_max;
-                    if (!(fabsf(xm - x_mag) < tol)) pass = false;
-                }
+            // the binary32 filter of pair (i0, i2)
+            auto test32 = [&](int i2) {
+                const float x2 = L.wx[sd][l2][i2], z2 = zat(sd, l2, i2);
+                const float txd = (x2 - x0) / (z2 - z0);
+                bool pass = !(low_p && !((txd - tx_in) * qop > 0.0f));
+                const float xm = x0 + txd * (P->z_mag - z0);
+                float tol = tolc + P->magtol_txscale * fabsf(txd);
+                if (tol < P->magtol_min) tol = P->magtol_min;
+                if (tol > P->magtol_max) tol = P->magtol_max;
+                if (!(fabsf(xm - x_mag) < tol)) pass = false;
+                return pass;
+            };
+            // queue the passing pairs of this lane-step; a full queue is completed
+            auto push = [&](bool pass, bool tested, int i2) {
                 const uint64_t bal = __ballot(pass);
                 if constexpr (CNT) {
-                    cnt[C_PAIRS_TESTED] += (uint32_t)__popcll(__ballot(i2 < jhi));
+                    cnt[C_PAIRS_TESTED] += (uint32_t)__popcll(__ballot(tested));
                     cnt[C_DOUBLETS] += (uint32_t)__popcll(bal);
                 }
                 if (pass) {
@@ -663,6 +755,61 @@ struct Track {
                     if (lane < rest) L.qkey[lane] = k2;
                     qn = rest;
                     wave_sync();
+                }
+            };
+            if constexpr (!H16) {
+                for (int k = 0; k < span; ++k) {
+                    const int i2 = jlo + k;
+                    const bool tested = i2 < jhi;
+                    push(tested && test32(i2), tested, i2);
+                }
+            } else {
+                // two pairs (i2, i2 + 1) per step: one packed binary16
+                // evaluation, or two binary32 ones on sets that stay binary32
+                const int s_ = s;
+                const _Float16 X0 = h16 ? (_Float16)(x0 - sel(hc0, s_)) : (_Float16)0.0f;
+                for (int k = 0; k < span; k += 2) {
+                    const int ia = jlo + k, ib = ia + 1;
+                    const bool ta = ia < jhi, tb = ib < jhi;
+                    bool pa = false, pb = false;
+                    if (h16) {
+                        const float c2 = sel(hc2, s_);
+                        const int ja = ta ? ia : 0, jb = tb ? ib : 0;
+                        const half2v X2 = {(_Float16)(L.wx[0][l2][ja] - c2), (_Float16)(L.wx[0][l2][jb] - c2)};
+                        const half2v X0v = {X0, X0};
+                        const half2v C02 = {sel(hC02, s_), sel(hC02, s_)}, RZ = {sel(hRZ, s_), sel(hRZ, s_)};
+                        const half2v u = X2 - X0v;
+                        const half2v v = u + C02;
+                        const half2v t = v * RZ;
+                        bool ca = true, cb = true;
+                        if (low_p) {
+                            const half2v TX = {hTX, hTX}, QP = {hQP, hQP};
+                            const half2v w1 = t - TX;
+                            const half2v w2 = w1 * QP;
+                            ca = w2.x > (_Float16)0.0f;
+                            cb = w2.y > (_Float16)0.0f;
+                        }
+                        const half2v E0 = {sel(hE0, s_), sel(hE0, s_)}, L0 = {sel(hL0, s_), sel(hL0, s_)};
+                        const half2v m1 = E0 + X0v;
+                        const half2v m2 = t * L0;
+                        const half2v M = m1 + m2;
+                        const half2v at = {habs(t.x), habs(t.y)};
+                        const half2v TXS = {hTXS, hTXS}, TC = {hTC, hTC};
+                        const half2v r1 = TXS * at;
+                        const half2v tol = TC + r1;
+                        _Float16 tola = tol.x, tolb = tol.y;
+                        if (tola < hTMIN) tola = hTMIN;
+                        if (tola > hTMAX) tola = hTMAX;
+                        if (tolb < hTMIN) tolb = hTMIN;
+                        if (tolb > hTMAX) tolb = hTMAX;
+                        pa = ta && ca && habs(M.x) < tola;
+                        pb = tb && cb && habs(M.y) < tolb;
+                    } else {
+                        pa = ta && test32(ia);
+                        pb = tb && test32(ib);
+                    }
+                    push(pa, ta, ia);
+                    push(pb, tb, ib);
                 }
             }
         }
@@ -949,13 +1096,13 @@ struct Track {
     }
 };
 
-template <int NW, int NS, int WPB>
+template <int NW, int NS, int WPB, bool H16 = false>
 __global__ __launch_bounds__(WPB * WAVE) void k_plain(DevBatch B, const KParams *__restrict__ P, uint32_t ev) {
     __shared__ WaveLds<NW, NS> lds[WPB];
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const uint32_t t = B.trk_off[ev] + blockIdx.x * WPB + w;
     if (t >= B.trk_off[ev + 1]) return;
-    Track<NW, NS> tr{B, P, lds[w], 0, {}, 0};
+    Track<NW, NS, false, H16> tr{B, P, lds[w], 0, {}, 0};
     tr.run(t, ev);
 }
 
@@ -964,7 +1111,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_plain(DevBatch B, const KParams 
 // event share one L2 and its hits are fetched from HBM once per XCD.
 constexpr uint32_t NXCD = 8;
 
-template <int NW, int NS, int WPB, bool CNT = false>
+template <int NW, int NS, int WPB, bool CNT = false, bool H16 = false>
 __global__ __launch_bounds__(WPB * WAVE) void k_grid(DevBatch B, const KParams *__restrict__ P) {
     __shared__ WaveLds<NW, NS> lds[WPB];
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -972,7 +1119,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_grid(DevBatch B, const KParams *
     const uint32_t lb = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
     const uint32_t t = lb * WPB + w;
     if (t >= B.n_tracks) return;
-    Track<NW, NS, CNT> tr{B, P, lds[w], 0, {}, 0};
+    Track<NW, NS, CNT, H16> tr{B, P, lds[w], 0, {}, 0};
     tr.run(t, B.trk_ev[t]);
     if constexpr (CNT) {
         if (lane_id() == 0)
@@ -987,7 +1134,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_grid(DevBatch B, const KParams *
 // exited waves, and the last wave out puts every word back to zero, so the
 // next launch on the batch starts clean without a reset kernel (or a memset
 // node in a captured graph).
-template <int NW, int NS, int WPB>
+template <int NW, int NS, int WPB, bool H16 = false>
 __global__ __launch_bounds__(WPB * WAVE) void k_persistent(DevBatch B, const KParams *__restrict__ P,
                                                             uint32_t items) {
     __shared__ WaveLds<NW, NS> lds[WPB];
@@ -1016,7 +1163,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_persistent(DevBatch B, const KPa
             // keep per-track loads inside the loop: hoisting them across tracks
             // costs ~30 VGPRs of loop-carried state and two waves per SIMD
             asm volatile("" ::: "memory");
-            Track<NW, NS> tr{B, P, lds[w], 0, {}, 0};
+            Track<NW, NS, false, H16> tr{B, P, lds[w], 0, {}, 0};
             tr.run(t, B.trk_ev[t]);
         }
     }
@@ -1083,7 +1230,7 @@ __global__ void k_track_event(const uint32_t *__restrict__ trk_off, uint32_t n_e
     trk_ev[t] = lo - 1;
 }
 
-template <int NW, int NS, int WPB>
+template <int NW, int NS, int WPB, bool H16>
 hipError_t launch_nw_wpb(const DevBatch &b, const KParams *P, int mode, const ExecCfg &cfg,
                          const uint32_t *trk_off_host, hipStream_t s) {
     const dim3 block(WPB * WAVE);
@@ -1091,30 +1238,30 @@ hipError_t launch_nw_wpb(const DevBatch &b, const KParams *P, int mode, const Ex
         for (uint32_t e = 0; e < b.n_events; ++e) {
             const uint32_t nt = trk_off_host[e + 1] - trk_off_host[e];
             if (nt == 0) continue;
-            hipLaunchKernelGGL((k_plain<NW, NS, WPB>), dim3((nt + WPB - 1) / WPB), block, 0, s, b, P, e);
+            hipLaunchKernelGGL((k_plain<NW, NS, WPB, H16>), dim3((nt + WPB - 1) / WPB), block, 0, s, b, P, e);
         }
     } else if (mode == 2) {   // persistent: resident waves, per-XCD work queues
         uint32_t grid = (uint32_t)(cfg.blocks_per_cu * cfg.n_cu);
         const uint32_t need = (b.n_tracks + WPB - 1) / WPB;
         if (grid > need) grid = need;
         if (grid == 0) grid = 1;
-        hipLaunchKernelGGL((k_persistent<NW, NS, WPB>), dim3(grid), block, 0, s, b, P,
+        hipLaunchKernelGGL((k_persistent<NW, NS, WPB, H16>), dim3(grid), block, 0, s, b, P,
                            (uint32_t)cfg.items_per_grab);
     } else {   // batched: one launch, one wavefront per track, XCD-ordered
         const uint32_t need = (b.n_tracks + WPB - 1) / WPB;
         const uint32_t grid = (need + NXCD - 1) / NXCD * NXCD;
-        if (grid) hipLaunchKernelGGL((k_grid<NW, NS, WPB>), dim3(grid), block, 0, s, b, P);
+        if (grid) hipLaunchKernelGGL((k_grid<NW, NS, WPB, false, H16>), dim3(grid), block, 0, s, b, P);
     }
     return hipGetLastError();
 }
 
-template <int NW, int NS>
+template <int NW, int NS, bool H16 = false>
 hipError_t launch_nw(const DevBatch &b, const KParams *P, int mode, const ExecCfg &cfg,
                      const uint32_t *trk_off_host, hipStream_t s) {
     switch (cfg.waves_per_block) {
-        case 1: return launch_nw_wpb<NW, NS, 1>(b, P, mode, cfg, trk_off_host, s);
-        case 2: return launch_nw_wpb<NW, NS, 2>(b, P, mode, cfg, trk_off_host, s);
-        default: return launch_nw_wpb<NW, NS, 4>(b, P, mode, cfg, trk_off_host, s);
+        case 1: return launch_nw_wpb<NW, NS, 1, H16>(b, P, mode, cfg, trk_off_host, s);
+        case 2: return launch_nw_wpb<NW, NS, 2, H16>(b, P, mode, cfg, trk_off_host, s);
+        default: return launch_nw_wpb<NW, NS, 4, H16>(b, P, mode, cfg, trk_off_host, s);
     }
 }
 
@@ -1182,6 +1329,9 @@ hipError_t launch_count(const DevBatch &b, const KParams *P, int n_hits_window, 
     if (n_sides == 2) {
         if (n_hits_window <= 32) hipLaunchKernelGGL((k_grid<32, 2, 2, true>), g, blk, 0, s, b, P);
         else hipLaunchKernelGGL((k_grid<64, 2, 2, true>), g, blk, 0, s, b, P);
+    } else if (n_sides == 3) {
+        if (n_hits_window <= 32) hipLaunchKernelGGL((k_grid<32, 1, 2, true, true>), g, blk, 0, s, b, P);
+        else hipLaunchKernelGGL((k_grid<64, 1, 2, true, true>), g, blk, 0, s, b, P);
     } else {
         if (n_hits_window <= 32) hipLaunchKernelGGL((k_grid<32, 1, 2, true>), g, blk, 0, s, b, P);
         else hipLaunchKernelGGL((k_grid<64, 1, 2, true>), g, blk, 0, s, b, P);
@@ -1209,30 +1359,36 @@ hipError_t launch_find(const DevBatch &b, const KParams *P, int n_hits_window, i
         if (n_hits_window <= 32) return launch_nw<32, 2>(b, P, mode, cfg, trk_off_host, s);
         return launch_nw<64, 2>(b, P, mode, cfg, trk_off_host, s);
     }
+    if (n_sides == 3) {
+        if (n_hits_window <= 32) return launch_nw<32, 1, true>(b, P, mode, cfg, trk_off_host, s);
+        return launch_nw<64, 1, true>(b, P, mode, cfg, trk_off_host, s);
+    }
     if (n_hits_window <= 32) return launch_nw<32, 1>(b, P, mode, cfg, trk_off_host, s);
     return launch_nw<64, 1>(b, P, mode, cfg, trk_off_host, s);
 }
 
 namespace {
-template <int NW, int NS, int WPB>
+template <int NW, int NS, int WPB, bool H16>
 int occ() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_persistent<NW, NS, WPB>),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_persistent<NW, NS, WPB, H16>),
                                                      WPB * WAVE, 0) != hipSuccess)
         return 0;
     return n;
 }
 }  // namespace
 
-template <int NW, int NS>
+template <int NW, int NS, bool H16 = false>
 int occ_wpb(int waves_per_block) {
-    if (waves_per_block == 1) return occ<NW, NS, 1>();
-    if (waves_per_block == 2) return occ<NW, NS, 2>();
-    return occ<NW, NS, 4>();
+    if (waves_per_block == 1) return occ<NW, NS, 1, H16>();
+    if (waves_per_block == 2) return occ<NW, NS, 2, H16>();
+    return occ<NW, NS, 4, H16>();
 }
 
 int persistent_blocks_per_cu(int n_hits_window, int n_sides, int waves_per_block) {
     if (n_sides == 2) return n_hits_window <= 32 ? occ_wpb<32, 2>(waves_per_block) : occ_wpb<64, 2>(waves_per_block);
+    if (n_sides == 3)
+        return n_hits_window <= 32 ? occ_wpb<32, 1, true>(waves_per_block) : occ_wpb<64, 1, true>(waves_per_block);
     return n_hits_window <= 32 ? occ_wpb<32, 1>(waves_per_block) : occ_wpb<64, 1>(waves_per_block);
 }
 

@@ -57,7 +57,7 @@ class lf_params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_float) for n in _PARAM_FLOATS] + [
         ("C_nhits", ctypes.c_float * 4), ("n_hits_window", ctypes.c_int32), ("n_triplets", ctypes.c_int32),
         ("velo_only", ctypes.c_int32), ("noUT_c", ctypes.c_float * 8), ("noUT_p_min", ctypes.c_float),
-        ("noUT_pt_min", ctypes.c_float), ("noUT_overlap", ctypes.c_float)]
+        ("noUT_pt_min", ctypes.c_float), ("noUT_overlap", ctypes.c_float), ("seed_fp16", ctypes.c_int32)]
 
 
 _PARAM_ARRAYS = ("C_nhits", "noUT_c")
