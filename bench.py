@@ -62,8 +62,8 @@ BYTES_PER_TRACK_OUT = 78
 # HBM traffic of the batched kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (per launch, scaled by the counters' reading of a known-size copy), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha256": "3ced7ba079ac12a16b5fb3ad4facf85ee504ad8c3d6c881d0e538b9968661f31",
-           "bytes_per_launch": 80151882}
+TRAFFIC = {"kernel_sha256": "ac931af8691de43d037a5a3a780f25816971b1f8f752e9888798143074c8e231",
+           "bytes_per_launch": 80156011}
 WORKLOADS = {
     "nominal": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",
     "uneven": "uneven: 20000 events, Poisson(7.6) x 50 particles, 0-13k hits and 0-600 tracks/event",
