@@ -141,6 +141,20 @@ __device__ __forceinline__ float field_c_lane(const KParams *__restrict__ P, flo
 // entry before p + s still satisfies the (monotone) predicate, so p ends as
 // the number of leading entries that satisfy it.  Only entries < n are read.
 
+// Number of leading indices j < n for which pred(j) holds, for a predicate
+// that holds on a prefix; two predicates searched together.
+template <int NMAX, class P1, class P2>
+__device__ __forceinline__ void prefix2(int n, P1 p1, P2 p2, int &c1, int &c2) {
+    int p = 0, q = 0;
+#pragma unroll
+    for (int s = NMAX; s > 0; s >>= 1) {
+        if (p + s <= n && p1(p + s - 1)) p += s;
+        if (q + s <= n && p2(q + s - 1)) q += s;
+    }
+    c1 = p;
+    c2 = q;
+}
+
 // Lower bound (v < klo) and upper bound (v <= khi) of one non-decreasing LDS
 // array, searched together.
 template <int NMAX>
@@ -709,11 +723,36 @@ struct Track {
                     }
                 }
             }
-            // binary16 sets test every pair of their windows
+            // binary16 sets: the pairs whose |M| is below the largest
+            // tolerance.  M(h2) = (E0 + X0) + ((X2 - X0) + C02) RZ L0 is
+            // monotone in x2 (every rounding step is), so they form one index
+            // range of the sorted window, found by searches with the same
+            // binary16 arithmetic; every passing pair lies in it.
             const bool h16 = seed16 && item < items_total && sel(hon, s);
             if (h16) {
                 jlo = 0;
                 jhi = n2;
+                const _Float16 RZ = sel(hRZ, s), L0 = sel(hL0, s), C02 = sel(hC02, s);
+                const _Float16 m1 = sel(hE0, s) + (_Float16)(x0 - sel(hc0, s));
+                const _Float16 X0 = (_Float16)(x0 - sel(hc0, s));
+                const float c2 = sel(hc2, s);
+                const float *wx2 = L.wx[0][l2];
+                const _Float16 lim = hTMAX, nlim = -hTMAX;
+                auto M = [&](int j) {
+                    const _Float16 X2 = (_Float16)(wx2[j] - c2);
+                    const _Float16 u = X2 - X0;
+                    const _Float16 v = u + C02;
+                    const _Float16 t = v * RZ;
+                    const _Float16 m2 = t * L0;
+                    return m1 + m2;
+                };
+                const float rzl = (float)RZ * (float)L0;
+                if (rzl > 0.0f && rzl < INFINITY) {          // M non-decreasing in x2
+                    prefix2<NW>(n2, [&](int j) { return M(j) <= nlim; }, [&](int j) { return M(j) < lim; }, jlo, jhi);
+                } else if (rzl < 0.0f && rzl > -INFINITY) {  // M non-increasing in x2
+                    prefix2<NW>(n2, [&](int j) { return M(j) >= lim; }, [&](int j) { return M(j) > nlim; }, jlo, jhi);
+                }
+                if (jhi < jlo) jhi = jlo;
             }
             int span = jhi - jlo;
 #pragma unroll
