@@ -62,7 +62,7 @@ BYTES_PER_TRACK_OUT = 78
 # HBM traffic of the batched kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (per launch, scaled by the counters' reading of a known-size copy), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha256": "4590449a2e5b8d8314057f87fa0d7e0a6d3ec12200772d9a9095a04e91369601",
+TRAFFIC = {"kernel_sha256": "5362ad2e6a99ac53d20a790fc8d76156543c7b1edd72c8d25886daba0c14324e",
            "bytes_per_launch": 80156011}
 WORKLOADS = {
     "nominal": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",

@@ -375,15 +375,23 @@ struct Track {
                 const float *wx1 = L.wx[0][l1];
                 const int n1 = L.wlen[0][l1];
                 const float c1 = sel(hc1, s);
+                // The window's Y_j = h(x_j - c1) are sorted, so d_j = |h(Y_j - X1e)|
+                // falls up to p = #{Y_j < X1e} and rises from p.  The first
+                // minimum of a scan is p, or the first index of the plateau
+                // ending at p - 1 when d_(p-1) <= d_p.
+                auto Y = [&](int j) { return (_Float16)(wx1[j] - c1); };
+                auto D = [&](int j) { return habs(Y(j) - X1e); };
                 _Float16 hb = (_Float16)INFINITY;
-                const half2v e2 = {X1e, X1e};
-                for (int j = 0; j < n1; j += 2) {
-                    const int jb = j + 1 < n1 ? j + 1 : j;
-                    const half2v xv = {(_Float16)(wx1[j] - c1), (_Float16)(wx1[jb] - c1)};
-                    const half2v dv = xv - e2;
-                    const _Float16 da = habs(dv.x), db = habs(dv.y);
-                    if (da < hb) { hb = da; best = j; }
-                    if (j + 1 < n1 && db < hb) { hb = db; best = j + 1; }
+                int pp = 0, qq = 0, unused = 0;
+                prefix2<NW>(n1, [&](int j) { return Y(j) < X1e; }, [](int) { return false; }, pp, unused);
+                if (pp < n1) { hb = D(pp); best = pp; }
+                if (pp > 0) {
+                    const _Float16 dl = D(pp - 1);
+                    if (!(dl > hb)) {
+                        prefix2<NW>(pp, [&](int j) { return D(j) > dl; }, [](int) { return false; }, qq, unused);
+                        hb = dl;
+                        best = qq;
+                    }
                 }
                 if (best >= 0) {
                     const _Float16 c2h = hb * hb;
