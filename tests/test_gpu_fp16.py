@@ -69,3 +69,17 @@ def test_fp16_rejected_with_velo_only():
     with pytest.raises(lf.LFError) as e:
         lf.lf_create(W, {"seed_fp16": 1, "velo_only": 1})
     assert e.value.code == lf.LF_ERR_INVALID
+
+
+@pytest.mark.parametrize("step", [0.25, 4.0])
+def test_fp16_equal_x_runs_and_duplicates(step):
+    """Runs of equal x (and so of equal binary16 offsets and distances) and
+    duplicated hits: the middle-hit searches must return the first minimum
+    of a scan, as the oracle's linear scan does."""
+    ev = lfgen.generate("nominal", n_events=4)
+    x = (np.round(ev.hit_x.astype(np.float64) / step) * step).astype(np.float32)
+    _check(lfgen.Events(**{**ev.__dict__, "hit_x": x}), f"nominal[4] x in {step} mm steps", modes=("batched",))
+    idx = np.repeat(np.arange(ev.n_hits), 2)
+    d = {k: getattr(ev, k)[idx] for k in ("hit_x", "hit_z", "hit_dxdy", "hit_pid")}
+    dup = lfgen.Events(**{**ev.__dict__, **d, "hit_off": (ev.hit_off.astype(np.int64) * 2).astype(np.uint32)})
+    _check(dup, "nominal[4] duplicated hits", modes=("batched",))
