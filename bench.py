@@ -378,7 +378,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); events are "
-              f"independent, so N GPUs would each take their own batches -- see DESIGN.md", file=sys.stderr)
+              f"independent, so N GPUs would each take their own batches of events", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
