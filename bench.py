@@ -377,7 +377,7 @@ def scan_window(lf, world, ev, stream, steps, warmup, workload):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); events are "
+        print(f"bench.py: measures one GPU only (--gpus {args.gpus} requested); events are "
               f"independent, so N GPUs would each take their own batches of events", file=sys.stderr)
         sys.exit(2)
     import numpy as np
