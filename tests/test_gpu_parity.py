@@ -385,3 +385,40 @@ def test_autotuner_keeps_results():
         lf.lf_destroy(ctx)
     rows = np.arange(int(ev.trk_off[40]))
     compare(ref, got, rows=rows, label="autotuned")
+
+
+@pytest.mark.parametrize("variant", ["no_ut", "paper", "fp16"])
+def test_variant_builds_in_graphs_and_counting(variant):
+    """The no-UT, paper-form and binary16 builds replayed from a captured
+    graph (persistent mode, whose queue words reset themselves) match the
+    oracle on every replay, and their counting builds rewrite identical
+    results with consistent totals."""
+    from paper_2402_14670_amd import lf
+    field = "paper" if variant == "paper" else "toy"
+    world = lfgen.world(field)
+    params = {"no_ut": {"velo_only": 1}, "paper": None, "fp16": {"seed_fp16": 1}}[variant]
+    parts = [lfgen.generate("nominal", field=field, n_events=8, first_event=8 * i) for i in range(2)]
+    refs = [oracle.run(p, world, params) for p in parts]
+    ctx = lf.lf_create(world, params)
+    try:
+        ids = [lf.lf_upload_events(ctx, p) for p in parts]
+        say(f"[gpu] {variant}: graph of {len(ids)} batches, persistent mode")
+        g = lf.lf_graph_create(ctx, ids, "persistent")
+        try:
+            for rep in range(2):
+                for i in ids:
+                    lf.lf_poison_tracks(ctx, i)
+                lf.lf_graph_launch(ctx, g)
+                for i, p, r in zip(ids, parts, refs):
+                    compare(r, lf.lf_copy_tracks(ctx, i, p.n_tracks), label=f"{variant}/graph/replay{rep}")
+        finally:
+            lf.lf_graph_destroy(g)
+        say(f"[gpu] {variant}: counting build")
+        wc = lf.lf_work_counts(ctx, ids[0])
+        compare(refs[0], lf.lf_copy_tracks(ctx, ids[0], parts[0].n_tracks), label=f"{variant}/counting")
+        assert wc["tracks"] == parts[0].n_tracks
+        assert wc["found"] == int(refs[0]["found"].sum())
+        assert wc["doublets"] <= wc["pairs_tested"] and wc["kept"] <= wc["triplets"]
+        assert wc["accepted"] <= wc["fitted"] <= wc["kept"]
+    finally:
+        lf.lf_destroy(ctx)
