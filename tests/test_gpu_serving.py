@@ -78,14 +78,14 @@ def test_backpressure_under_small_budget(pool):
         lf.lf_destroy(ctx)
 
 
-def test_paper_field_and_no_ut_served():
+def test_paper_field_no_ut_and_fp16_served():
     """The serving loop under the paper-form field (kick solved per track,
-    q/p from F) and under the no-UT tuning gives each request the oracle's
-    result for its event alone."""
+    q/p from F), under the no-UT tuning and with binary16 seeding gives each
+    request the oracle's result for its event alone."""
     from paper_2402_14670_amd import lf
     ev = lfgen.generate("nominal", field="paper", n_events=30)
     world = lfgen.world("paper")
-    for params in (None, {"velo_only": 1}):
+    for params in (None, {"velo_only": 1}, {"seed_fp16": 1}):
         ref = event_digests(oracle.run(ev, world, params), ev.trk_off)
         req, arr = _stream(ev.n_events, 600, 20000.0, seed=41)
         ctx = lf.lf_create(world, params)
