@@ -149,7 +149,7 @@ int validate(const lf_batch *b, std::string &why) {
 
 // Device layout of a batch: one allocation, every array 256-byte aligned.
 struct Layout {
-    size_t hit_off, hx, hz, hd, trk_off, trk_ev, tx, ty, ttx, tty, tqop;
+    size_t hit_off, hx, hz, hd, trk_off, trk_ev, tx, ty, ttx, tty, tqop, uni;
     size_t found, nhits, hit_idx, a, b, c, y0, ty_o, qop, Q, counter, stats, total;
 };
 
@@ -163,6 +163,7 @@ Layout layout(uint32_t E, uint32_t H, uint32_t T) {
     L.trk_ev = put((size_t)T * 4);
     L.tx = put((size_t)T * 4); L.ty = put((size_t)T * 4); L.ttx = put((size_t)T * 4);
     L.tty = put((size_t)T * 4); L.tqop = put((size_t)T * 4);
+    L.uni = put(E);
     L.found = put(T); L.nhits = put(T); L.hit_idx = put((size_t)T * 48);
     L.a = put((size_t)T * 4); L.b = put((size_t)T * 4); L.c = put((size_t)T * 4);
     L.y0 = put((size_t)T * 4); L.ty_o = put((size_t)T * 4); L.qop = put((size_t)T * 4); L.Q = put((size_t)T * 4);
@@ -349,6 +350,7 @@ int lf_upload_events(lf_ctx *c, const lf_batch *b, void *hip_stream, uint64_t *b
     d.ttx = reinterpret_cast<const float *>(base + L.ttx);
     d.tty = reinterpret_cast<const float *>(base + L.tty);
     d.tqop = reinterpret_cast<const float *>(base + L.tqop);
+    d.uni = reinterpret_cast<const uint8_t *>(base + L.uni);
     d.found = reinterpret_cast<uint8_t *>(base + L.found);
     d.nhits = reinterpret_cast<uint8_t *>(base + L.nhits);
     d.hit_idx = reinterpret_cast<int32_t *>(base + L.hit_idx);
@@ -377,6 +379,7 @@ int lf_upload_events(lf_ctx *c, const lf_batch *b, void *hip_stream, uint64_t *b
     }
     if (e == hipSuccess) e = hipMemsetAsync(d.counter, 0, 1024, s);
     if (e == hipSuccess) e = lfk::launch_track_event(d, s);
+    if (e == hipSuccess) e = lfk::launch_event_uniform(d, reinterpret_cast<uint8_t *>(base + L.uni), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipFree(bt.dmem);

@@ -40,6 +40,7 @@ struct DevBatch {
     const uint32_t *trk_off;   // [E+1]
     const uint32_t *trk_ev;    // [T] event of each track
     const float *tx_, *ty_, *ttx, *tty, *tqop;  // [T]
+    const uint8_t *uni;        // [E] 1: in every bucket of the event all hits share one z and one dxdy (bit for bit)
     uint8_t *found, *nhits;    // [T]
     int32_t *hit_idx;          // [12*T]
     float *a, *b, *c, *y0, *ty, *qop, *Q;  // [T]
@@ -86,6 +87,9 @@ hipError_t launch_track_event(const DevBatch &b, hipStream_t s);
 // layer), 3 for VELO-UT input with the binary16 seeding build.
 hipError_t launch_find(const DevBatch &b, const KParams *P, int n_hits_window, int n_sides, int mode,
                        const ExecCfg &cfg, const uint32_t *trk_off_host, hipStream_t s);
+// Writes the per-event flag of DevBatch::uni into uni[E] (one block per
+// event; the batch's hits must be in place).
+hipError_t launch_event_uniform(const DevBatch &b, uint8_t *uni, hipStream_t s);
 // Counting launch: one wavefront per track, adds the work counters of every
 // track into b.stats (which must be zeroed first).
 hipError_t launch_count(const DevBatch &b, const KParams *P, int n_hits_window, int n_sides, hipStream_t s);

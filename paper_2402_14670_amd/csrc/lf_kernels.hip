@@ -281,6 +281,9 @@ struct Track {
     // bit NL * side + layer: the window's hits do not all share one z
     // (zvar) or one stereo tangent (dvar); ebase: the event's first hit
     uint32_t zvar = 0, dvar = 0, ebase = 0;
+    // the event's hits share one z and one dxdy per bucket (DevBatch::uni):
+    // only x is staged per hit, each window keeps its first hit's values
+    bool uni = false;
     // Binary16 seeding: per seed set, whether it runs in half precision
     // (seed_fp16, both outer windows non-empty with one z each), the window
     // centres and its constants; then the ones shared by both sets.
@@ -297,12 +300,12 @@ struct Track {
     // window's one value, or from HBM for a mixed window
     static constexpr bool XO = WaveLds<NW, NS>::XO;
     __device__ __forceinline__ float zat(int sd, int l, int i) const {
-        if constexpr (!XO) return L.wz[sd][l][i];
+        if constexpr (!XO) return L.wz[sd][l][uni ? 0 : i];
         if ((zvar >> (NL * sd + l)) & 1u) return ld32(B.hz, ebase + (uint32_t)(L.wfirst[sd][l] + i));
         return L.wz[sd][l][0];
     }
     __device__ __forceinline__ float dat(int sd, int l, int i) const {
-        if constexpr (!XO) return L.wd[sd][uv_index(l)][i];
+        if constexpr (!XO) return L.wd[sd][uv_index(l)][uni ? 0 : i];
         if ((dvar >> (NL * sd + l)) & 1u) return ld32(B.hd, ebase + (uint32_t)(L.wfirst[sd][l] + i));
         return L.wd[sd][uv_index(l)][0];
     }
@@ -491,6 +494,7 @@ struct Track {
         const float T = tx_in + dtx;
         const float kd = P->kappa * dtx;
         ebase = (uint32_t)__builtin_amdgcn_readlane((int)ho, 0);
+        if constexpr (!XO) uni = B.uni[ev] != 0;
         // x tolerance of the x-layer windows
         float xtol;
         if constexpr (NS == 2) {
@@ -575,6 +579,12 @@ struct Track {
                     wl[sd] = len;
                     L.wfirst[sd][lane] = first;
                     L.wlen[sd][lane] = len;
+                    if (!XO && uni && len > 0) {
+                        // the window's (and the bucket's) one z and stereo tangent
+                        const uint32_t g = ebase + (uint32_t)first;
+                        L.wz[sd][lane][0] = ld32(B.hz, g);
+                        if (is_uv(lane)) L.wd[sd][uv_index(lane)][0] = ld32(B.hd, g);
+                    }
                 }
             }
         }
@@ -607,8 +617,10 @@ struct Track {
                 if (j < n) {
                     const uint32_t g = ebase + (uint32_t)(f + j);
                     sx[u] = ld32(B.hx, g);
-                    sz[u] = ld32(B.hz, g);
-                    if (is_uv(l)) sd_[u] = ld32(B.hd, g);
+                    if (!uni) {
+                        sz[u] = ld32(B.hz, g);
+                        if (is_uv(l)) sd_[u] = ld32(B.hd, g);
+                    }
                     smask |= 1u << u;
                 }
             }
@@ -619,11 +631,12 @@ struct Track {
                 const bool in = (smask >> u) & 1u;
                 if (in) {
                     L.wx[sd][l][j] = sx[u];
-                    if (!XO || j == 0) {
+                    if (!uni && (!XO || j == 0)) {
                         L.wz[sd][l][XO ? 0 : j] = sz[u];
                         if (is_uv(l)) L.wd[sd][uv_index(l)][XO ? 0 : j] = sd_[u];
                     }
                 }
+                if (uni) continue;
                 // slot 0 of layer la sits in lane la NW - 64 u, that of lb in lane lb NW - 64 u
                 const float za = bcast_f(sz[u], la * NW - WAVE * u), zb = bcast_f(sz[u], lb * NW - WAVE * u);
                 const float da = bcast_f(sd_[u], la * NW - WAVE * u), db = bcast_f(sd_[u], lb * NW - WAVE * u);
@@ -1277,6 +1290,32 @@ __global__ void k_track_event(const uint32_t *__restrict__ trk_off, uint32_t n_e
     trk_ev[t] = lo - 1;
 }
 
+// One block per event: uni[e] = 1 when, in each of the event's 24 buckets,
+// every hit has the z and the stereo tangent of the bucket's first hit (bit
+// for bit).  Such events need only x staged per hit.  The event's hits are
+// streamed once, each compared with its predecessor; a difference is allowed
+// only where a bucket starts.
+__global__ void __launch_bounds__(1024) k_event_uniform(const uint32_t *__restrict__ hit_off,
+                                                        const float *__restrict__ hz,
+                                                        const float *__restrict__ hd, uint8_t *__restrict__ uni) {
+    __shared__ uint32_t off[2 * NL + 1];
+    const uint32_t e = blockIdx.x;
+    if (threadIdx.x <= 2 * NL) off[threadIdx.x] = hit_off[2 * NL * e + threadIdx.x];
+    __syncthreads();
+    const uint32_t f = off[0], n = off[2 * NL];
+    int odd = 0;
+    for (uint32_t i = f + 1 + threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t dz = __float_as_uint(hz[i]) ^ __float_as_uint(hz[i - 1]);
+        const uint32_t dd = __float_as_uint(hd[i]) ^ __float_as_uint(hd[i - 1]);
+        if ((dz | dd) == 0) continue;
+        bool start = false;
+        for (int k = 1; k < 2 * NL; ++k) start |= off[k] == i;
+        odd |= !start;
+    }
+    odd = __syncthreads_or(odd);
+    if (threadIdx.x == 0) uni[e] = odd ? 0 : 1;
+}
+
 template <int NW, int NS, int WPB, bool H16>
 hipError_t launch_nw_wpb(const DevBatch &b, const KParams *P, int mode, const ExecCfg &cfg,
                          const uint32_t *trk_off_host, hipStream_t s) {
@@ -1396,6 +1435,12 @@ hipError_t launch_track_event(const DevBatch &b, hipStream_t s) {
     if (b.n_tracks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_track_event, dim3((b.n_tracks + 255) / 256), dim3(256), 0, s, b.trk_off, b.n_events,
                        b.n_tracks, const_cast<uint32_t *>(b.trk_ev));
+    return hipGetLastError();
+}
+
+hipError_t launch_event_uniform(const DevBatch &b, uint8_t *uni, hipStream_t s) {
+    if (b.n_events == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_event_uniform, dim3(b.n_events), dim3(1024), 0, s, b.hit_off, b.hz, b.hd, uni);
     return hipGetLastError();
 }
 

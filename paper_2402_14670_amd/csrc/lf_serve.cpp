@@ -58,7 +58,7 @@ struct Pool {
 
 // Byte layout of one batch region (device ring and pinned staging share it).
 struct BatchLayout {
-    size_t desc, hit_off, hx, hz, hd, trk_off, trk_ev, tx, ty, ttx, tty, tqop, in_bytes;
+    size_t desc, hit_off, hx, hz, hd, trk_off, trk_ev, tx, ty, ttx, tty, tqop, uni, in_bytes;
     size_t dig, found, nhits, hit_idx, fl, out_bytes, total;
     uint32_t E, H, T;
 };
@@ -74,6 +74,7 @@ BatchLayout batch_layout(uint32_t E, uint32_t H, uint32_t T) {
     L.trk_off = put(((size_t)E + 1) * 4); L.trk_ev = put((size_t)T * 4);
     L.tx = put((size_t)T * 4); L.ty = put((size_t)T * 4); L.ttx = put((size_t)T * 4);
     L.tty = put((size_t)T * 4); L.tqop = put((size_t)T * 4);
+    L.uni = put(E);
     L.in_bytes = o;
     // outputs: one contiguous block so a single copy brings them back
     const size_t ob = o;
@@ -286,6 +287,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
         d.ttx = in.ttx;
         d.tty = in.tty;
         d.tqop = in.tqop;
+        d.uni = reinterpret_cast<const uint8_t *>(dr + lay.uni);
         d.found = reinterpret_cast<uint8_t *>(dr + lay.found);
         d.nhits = reinterpret_cast<uint8_t *>(dr + lay.nhits);
         d.hit_idx = reinterpret_cast<int32_t *>(dr + lay.hit_idx);
@@ -300,6 +302,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
         hipError_t e = hipMemcpyAsync(dr + lay.desc, s.stage, (size_t)E * sizeof(lfk::GatherDesc),
                                       hipMemcpyHostToDevice, s.stream);
         if (e == hipSuccess) e = lfk::launch_gather(ddesc, E, in, s.stream);
+        if (e == hipSuccess) e = lfk::launch_event_uniform(d, reinterpret_cast<uint8_t *>(dr + lay.uni), s.stream);
         if (e == hipSuccess) e = lfk::launch_find(d, P, nhw, n_sides, 1, exec, nullptr, s.stream);
         if (e == hipSuccess)
             e = lfk::launch_digest(d, d.trk_off, E, reinterpret_cast<unsigned long long *>(dr + lay.dig), s.stream);

@@ -118,6 +118,43 @@ def _jitter_layers(ev, layers, z_mm, slope_rel, seed):
     return lfgen.Events(**{**ev.__dict__, "hit_z": hz.astype(np.float32), "hit_dxdy": hd.astype(np.float32)})
 
 
+def _per_bucket(ev, e, fn):
+    """Applies fn(bucket_slice_z, bucket_slice_dxdy) in place to each bucket of event e."""
+    hz, hd = ev.hit_z.copy(), ev.hit_dxdy.copy()
+    for k in range(24):
+        f, n = int(ev.hit_off[24 * e + k]), int(ev.hit_off[24 * e + k + 1])
+        if n > f:
+            fn(k, hz[f:n], hd[f:n])
+    return lfgen.Events(**{**ev.__dict__, "hit_z": hz, "hit_dxdy": hd})
+
+
+def test_uniform_and_non_uniform_events_in_one_batch():
+    """Events whose buckets each hold one z and one stereo slope stage only x
+    per hit; the others read per-hit values.  One batch mixes: untouched
+    events, one shifted per bucket (still uniform), ones where every hit but
+    a bucket's first is moved (z, then slope), one with a single-ulp change
+    on each bucket's last hit, and one fully jittered."""
+    ev = lfgen.generate("nominal", n_events=6, seed=21)
+
+    def shift(k, z, d):
+        z += np.float32(0.25 * (k + 1))
+
+    def tail_z(k, z, d):
+        z[1:] += np.float32(2.0)
+
+    def tail_slope(k, z, d):
+        d[1:] *= np.float32(1.03)
+
+    def last_ulp(k, z, d):
+        z[-1] = np.nextafter(z[-1], np.float32(np.inf))
+
+    for e, fn in ((1, shift), (2, tail_z), (3, tail_slope), (4, last_ulp)):
+        ev = _per_bucket(ev, e, fn)
+    jit = _jitter(lfgen.select_events(ev, [5]), 1.5, 0.02, seed=22)
+    ev = lfgen.concat([lfgen.select_events(ev, range(5)), jit])
+    _check_all_modes(ev, "nominal[6] uniform and non-uniform events")
+
+
 @pytest.mark.parametrize("n_hits_window", [64, 48, 32])
 def test_per_hit_geometry_with_x_only_staging(n_hits_window):
     """Windows of more than 32 hits stage only x and read a mixed window's z
