@@ -290,7 +290,10 @@ struct Track {
     bool hon[2] = {false, false};
     float hc0[2] = {0.0f, 0.0f}, hc1[2] = {0.0f, 0.0f}, hc2[2] = {0.0f, 0.0f};
     _Float16 hRZ[2], hC02[2], hE0[2], hL0[2], hA[2], hKK[2], hB[2];
-    _Float16 hTX, hQP, hTC, hTXS, hTMIN, hTMAX, hT3;
+    _Float16 hTMAX, hT3;
+    // (tx, q/p), (tx scale, constant) and (min, max) of the magnet
+    // tolerance as binary16 pairs, wave-uniform (kept in scalar registers)
+    uint32_t kTXQP, kTXSTC, kTMINMAX;
     // element s of a per-set pair, without indexing (a lane-dependent index
     // would put the arrays in scratch memory)
     template <class T>
@@ -666,11 +669,13 @@ struct Track {
         if constexpr (H16) {
             // binary16 seeding: coordinates relative to the window centres,
             // constants rounded once from binary32
-            hTX = (_Float16)tx_in;
-            hQP = (_Float16)qop;
-            hTC = (_Float16)tolc;
-            hTXS = (_Float16)P->magtol_txscale;
-            hTMIN = (_Float16)P->magtol_min;
+            auto pack2 = [](float lo, float hi) {
+                const half2v v = {(_Float16)lo, (_Float16)hi};
+                return (uint32_t)__builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v));
+            };
+            kTXQP = pack2(tx_in, qop);
+            kTXSTC = pack2(P->magtol_txscale, tolc);
+            kTMINMAX = pack2(P->magtol_min, P->magtol_max);
             hTMAX = (_Float16)P->magtol_max;
             hT3 = (_Float16)P->T_triplet;
 #pragma unroll
@@ -828,6 +833,10 @@ struct Track {
                 // evaluation, or two binary32 ones on sets that stay binary32
                 const int s_ = s;
                 const _Float16 X0 = h16 ? (_Float16)(x0 - sel(hc0, s_)) : (_Float16)0.0f;
+                const half2v TXQP = __builtin_bit_cast(half2v, kTXQP), TXSTC = __builtin_bit_cast(half2v, kTXSTC);
+                const half2v MM = __builtin_bit_cast(half2v, kTMINMAX);
+                const half2v TX = TXQP.xx, QP = TXQP.yy, TXS = TXSTC.xx, TC = TXSTC.yy;
+                const _Float16 tmin = MM.x, tmax = MM.y;
                 for (int k = 0; k < span; k += 2) {
                     const int ia = jlo + k, ib = ia + 1;
                     const bool ta = ia < jhi, tb = ib < jhi;
@@ -843,7 +852,6 @@ struct Track {
                         const half2v t = v * RZ;
                         bool ca = true, cb = true;
                         if (low_p) {
-                            const half2v TX = {hTX, hTX}, QP = {hQP, hQP};
                             const half2v w1 = t - TX;
                             const half2v w2 = w1 * QP;
                             ca = w2.x > (_Float16)0.0f;
@@ -854,14 +862,13 @@ struct Track {
                         const half2v m2 = t * L0;
                         const half2v M = m1 + m2;
                         const half2v at = {habs(t.x), habs(t.y)};
-                        const half2v TXS = {hTXS, hTXS}, TC = {hTC, hTC};
                         const half2v r1 = TXS * at;
                         const half2v tol = TC + r1;
                         _Float16 tola = tol.x, tolb = tol.y;
-                        if (tola < hTMIN) tola = hTMIN;
-                        if (tola > hTMAX) tola = hTMAX;
-                        if (tolb < hTMIN) tolb = hTMIN;
-                        if (tolb > hTMAX) tolb = hTMAX;
+                        if (tola < tmin) tola = tmin;
+                        if (tola > tmax) tola = tmax;
+                        if (tolb < tmin) tolb = tmin;
+                        if (tolb > tmax) tolb = tmax;
                         pa = ta && ca && habs(M.x) < tola;
                         pb = tb && cb && habs(M.y) < tolb;
                     } else {
