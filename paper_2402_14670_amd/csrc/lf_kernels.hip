@@ -516,6 +516,7 @@ struct Track {
 #pragma unroll
         for (int sd = 0; sd < NS; ++sd) {
             int pos = 0;
+            float zb = 0.0f, db = 0.0f;   // lane 3 l, uniform event: z and stereo tangent of the bucket
             {
                 const int l = lane < 3 * NL ? lane / 3 : 0;
                 const uint32_t b0 = (uint32_t)__shfl((int)ho, 2 * l + zone);
@@ -550,6 +551,11 @@ struct Track {
                     }
                     const float key = k == 0 ? xmin : (k == 1 ? xc : xmax);
                     xcl = xc;
+                    if (!XO && uni && k == 0 && b1 > b0) {
+                        // every hit of the bucket has these: loaded while the searches run
+                        zb = ld32(B.hz, b0);
+                        if (is_uv(l)) db = ld32(B.hd, b0);
+                    }
                     uint32_t lo = b0;
                     uint32_t n = b1 - b0;
                     // lower bound (x < key) for x_min and the centre, upper bound (x <= key) for x_max
@@ -567,6 +573,11 @@ struct Track {
             {
                 const int src = lane < NL ? 3 * lane : 0;
                 const int lo = __shfl(pos, src), c0 = __shfl(pos, src + 1), hi0 = __shfl(pos, src + 2);
+                float zl = 0.0f, dl = 0.0f;
+                if (!XO && uni) {
+                    zl = __shfl(zb, src);
+                    dl = __shfl(db, src);
+                }
                 if (lane < NL) {
                     int hi = hi0 < lo ? lo : hi0;
                     int c = c0 < lo ? lo : (c0 > hi ? hi : c0);
@@ -584,9 +595,8 @@ struct Track {
                     L.wlen[sd][lane] = len;
                     if (!XO && uni && len > 0) {
                         // the window's (and the bucket's) one z and stereo tangent
-                        const uint32_t g = ebase + (uint32_t)first;
-                        L.wz[sd][lane][0] = ld32(B.hz, g);
-                        if (is_uv(lane)) L.wd[sd][uv_index(lane)][0] = ld32(B.hd, g);
+                        L.wz[sd][lane][0] = zl;
+                        if (is_uv(lane)) L.wd[sd][uv_index(lane)][0] = dl;
                     }
                 }
             }
