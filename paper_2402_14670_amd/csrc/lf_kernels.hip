@@ -8,8 +8,9 @@
 //              binary searches over the x-sorted bucket in HBM; 12 lanes
 //              apply the symmetric cap ("Defining the search windows").
 //   staging    the <= 12 x n_hits_window window hits are read coalesced from
-//              HBM into this wave's LDS slice: x, z and dxdy per hit, or x
-//              only where LDS bounds the occupancy.
+//              HBM into this wave's LDS slice: x, z and dxdy per hit; x only
+//              where LDS bounds the occupancy, and in events whose buckets
+//              each hold one z and one dxdy (flagged by k_event_uniform).
 //   doublets   one first-layer hit of a seed set per lane; the range of
 //              third-layer hits that can pass the magnet filter is
 //              bracketed by a sorted search, each pair in it tested with the
