@@ -303,6 +303,9 @@ struct Track {
     // z and stereo tangent of hit i of a window: from LDS, or (XO) the
     // window's one value, or from HBM for a mixed window
     static constexpr bool XO = WaveLds<NW, NS>::XO;
+    // builds that take the uniform-event path (not the two-window build,
+    // whose occupancy it would lower)
+    static constexpr bool UNI = !XO || NS == 1;
     __device__ __forceinline__ float zat(int sd, int l, int i) const {
         if constexpr (!XO) return L.wz[sd][l][uni ? 0 : i];
         if ((zvar >> (NL * sd + l)) & 1u) return ld32(B.hz, ebase + (uint32_t)(L.wfirst[sd][l] + i));
@@ -498,7 +501,7 @@ struct Track {
         const float T = tx_in + dtx;
         const float kd = P->kappa * dtx;
         ebase = (uint32_t)__builtin_amdgcn_readlane((int)ho, 0);
-        if constexpr (!XO) uni = B.uni[ev] != 0;
+        if constexpr (UNI) uni = B.uni[ev] != 0;
         // x tolerance of the x-layer windows
         float xtol;
         if constexpr (NS == 2) {
@@ -552,7 +555,7 @@ struct Track {
                     }
                     const float key = k == 0 ? xmin : (k == 1 ? xc : xmax);
                     xcl = xc;
-                    if (!XO && uni && k == 0 && b1 > b0) {
+                    if (UNI && uni && k == 0 && b1 > b0) {
                         // every hit of the bucket has these: loaded while the searches run
                         zb = ld32(B.hz, b0);
                         if (is_uv(l)) db = ld32(B.hd, b0);
@@ -575,7 +578,7 @@ struct Track {
                 const int src = lane < NL ? 3 * lane : 0;
                 const int lo = __shfl(pos, src), c0 = __shfl(pos, src + 1), hi0 = __shfl(pos, src + 2);
                 float zl = 0.0f, dl = 0.0f;
-                if (!XO && uni) {
+                if (UNI && uni) {
                     zl = __shfl(zb, src);
                     dl = __shfl(db, src);
                 }
@@ -594,7 +597,7 @@ struct Track {
                     wl[sd] = len;
                     L.wfirst[sd][lane] = first;
                     L.wlen[sd][lane] = len;
-                    if (!XO && uni && len > 0) {
+                    if (UNI && uni && len > 0) {
                         // the window's (and the bucket's) one z and stereo tangent
                         L.wz[sd][lane][0] = zl;
                         if (is_uv(lane)) L.wd[sd][uv_index(lane)][0] = dl;
