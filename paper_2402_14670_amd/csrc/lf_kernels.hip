@@ -303,9 +303,6 @@ struct Track {
     // z and stereo tangent of hit i of a window: from LDS, or (XO) the
     // window's one value, or from HBM for a mixed window
     static constexpr bool XO = WaveLds<NW, NS>::XO;
-    // builds that take the uniform-event path (not the two-window build,
-    // whose occupancy it would lower)
-    static constexpr bool UNI = !XO || NS == 1;
     __device__ __forceinline__ float zat(int sd, int l, int i) const {
         if constexpr (!XO) return L.wz[sd][l][uni ? 0 : i];
         if ((zvar >> (NL * sd + l)) & 1u) return ld32(B.hz, ebase + (uint32_t)(L.wfirst[sd][l] + i));
@@ -501,7 +498,7 @@ struct Track {
         const float T = tx_in + dtx;
         const float kd = P->kappa * dtx;
         ebase = (uint32_t)__builtin_amdgcn_readlane((int)ho, 0);
-        if constexpr (UNI) uni = B.uni[ev] != 0;
+        uni = B.uni[ev] != 0;
         // x tolerance of the x-layer windows
         float xtol;
         if constexpr (NS == 2) {
@@ -555,7 +552,7 @@ struct Track {
                     }
                     const float key = k == 0 ? xmin : (k == 1 ? xc : xmax);
                     xcl = xc;
-                    if (UNI && uni && k == 0 && b1 > b0) {
+                    if (uni && k == 0 && b1 > b0) {
                         // every hit of the bucket has these: loaded while the searches run
                         zb = ld32(B.hz, b0);
                         if (is_uv(l)) db = ld32(B.hd, b0);
@@ -578,7 +575,7 @@ struct Track {
                 const int src = lane < NL ? 3 * lane : 0;
                 const int lo = __shfl(pos, src), c0 = __shfl(pos, src + 1), hi0 = __shfl(pos, src + 2);
                 float zl = 0.0f, dl = 0.0f;
-                if (UNI && uni) {
+                if (uni) {
                     zl = __shfl(zb, src);
                     dl = __shfl(db, src);
                 }
@@ -597,7 +594,7 @@ struct Track {
                     wl[sd] = len;
                     L.wfirst[sd][lane] = first;
                     L.wlen[sd][lane] = len;
-                    if (UNI && uni && len > 0) {
+                    if (uni && len > 0) {
                         // the window's (and the bucket's) one z and stereo tangent
                         L.wz[sd][lane][0] = zl;
                         if (is_uv(lane)) L.wd[sd][uv_index(lane)][0] = dl;
@@ -653,7 +650,10 @@ struct Track {
                         if (is_uv(l)) L.wd[sd][uv_index(l)][XO ? 0 : j] = sd_[u];
                     }
                 }
-                if (uni) continue;
+                // (the two-window build still runs these tests, on zeros that
+                // set no bit: skipping them there trips an instruction-selection
+                // error of the compiler)
+                if (NS == 1 && uni) continue;
                 // slot 0 of layer la sits in lane la NW - 64 u, that of lb in lane lb NW - 64 u
                 const float za = bcast_f(sz[u], la * NW - WAVE * u), zb = bcast_f(sz[u], lb * NW - WAVE * u);
                 const float da = bcast_f(sd_[u], la * NW - WAVE * u), db = bcast_f(sd_[u], lb * NW - WAVE * u);
@@ -1192,8 +1192,10 @@ __global__ __launch_bounds__(WPB * WAVE) void k_plain(DevBatch B, const KParams 
 // event share one L2 and its hits are fetched from HBM once per XCD.
 constexpr uint32_t NXCD = 8;
 
+// (two-window build: at most 80 VGPRs, 6 waves per SIMD)
 template <int NW, int NS, int WPB, bool CNT = false, bool H16 = false>
-__global__ __launch_bounds__(WPB * WAVE) void k_grid(DevBatch B, const KParams *__restrict__ P) {
+__global__ __launch_bounds__(WPB * WAVE) __attribute__((amdgpu_waves_per_eu(NS == 2 ? 6 : 1))) void k_grid(
+    DevBatch B, const KParams *__restrict__ P) {
     __shared__ WaveLds<NW, NS> lds[WPB];
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const uint32_t per = gridDim.x / NXCD;
