@@ -62,8 +62,8 @@ BYTES_PER_TRACK_OUT = 78
 # HBM traffic of the batched kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (per launch, scaled by the counters' reading of a known-size copy), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha256": "29b347f772533ac93d504f4096c92f406a5886f75f162ca82d426e4a2af49f1b",
-           "bytes_per_launch": 51836153}
+TRAFFIC = {"kernel_sha256": "aed55003994d826579b2bd7418ca90ffc8d56f85edf0c5331ecddf0f6bb2f465",
+           "bytes_per_launch": 51819394}
 WORKLOADS = {
     "nominal": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",
     "uneven": "uneven: 20000 events, Poisson(7.6) x 50 particles, 0-13k hits and 0-600 tracks/event",

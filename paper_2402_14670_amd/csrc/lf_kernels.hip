@@ -1192,9 +1192,10 @@ __global__ __launch_bounds__(WPB * WAVE) void k_plain(DevBatch B, const KParams 
 // event share one L2 and its hits are fetched from HBM once per XCD.
 constexpr uint32_t NXCD = 8;
 
-// (two-window build: at most 80 VGPRs, 6 waves per SIMD)
+// (two-window build: at most 80 VGPRs, 6 waves per SIMD; 32-slot binary16
+// build: at most 64 VGPRs, 8 waves per SIMD, a few registers spilled)
 template <int NW, int NS, int WPB, bool CNT = false, bool H16 = false>
-__global__ __launch_bounds__(WPB * WAVE) __attribute__((amdgpu_waves_per_eu(NS == 2 ? 6 : 1))) void k_grid(
+__global__ __launch_bounds__(WPB * WAVE) __attribute__((amdgpu_waves_per_eu(NS == 2 ? 6 : (H16 && NW == 32 ? 8 : 1)))) void k_grid(
     DevBatch B, const KParams *__restrict__ P) {
     __shared__ WaveLds<NW, NS> lds[WPB];
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
