@@ -199,17 +199,6 @@ static int kick_tx(float sf, float ty, float *txf) {
     return 1;
 }
 
-/* Sum of the fit terms of one candidate.  Term l belongs to layer l (slots
- * 12..15 and layers without a hit hold +0) and the 16 slots are added
- * pairwise: (t0+t1), (t2+t3), ..., then pairs of those, and so on [R19]. */
-static float pairsum16(const float t[16]) {
-    float a[16];
-    memcpy(a, t, sizeof(a));
-    for (int w = 1; w < 16; w *= 2)
-        for (int i = 0; i < 16; i += 2 * w) a[i] = a[i] + a[i + w];
-    return a[0];
-}
-
 static void track_one(const lfo_geometry *G, const lfo_params *P, const event_view *ev,
                       float x_in, float y_in, float tx_in, float ty_in, float qop,
                       uint8_t *found, uint8_t *n_out, int32_t *hit_out, float *par_out,
@@ -513,10 +502,12 @@ static void track_one(const lfo_geometry *G, const lfo_params *P, const event_vi
         if (n < 9 || !st_ok) continue;
 
         /* ---- x least-squares fit over all hits [R19]: corrections (da, db, dc)
-         * to the triplet model, basis {1, s, s^2 (1 + dRatio u)}, s = u/1024. ---- */
+         * to the triplet model, basis {1, s, s^2 (1 + dRatio u)}, s = u/1024.
+         * Every sum starts at +0 and adds the hits' terms in ascending layer
+         * order. ---- */
         float su[LFO_NL], sh[LFO_NL], rho[LFO_NL];
-        float t0[16] = {0}, t1[16] = {0}, t2[16] = {0}, t11[16] = {0}, t12[16] = {0}, t22[16] = {0};
-        float tr0[16] = {0}, tr1[16] = {0}, tr2[16] = {0};
+        float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, S11 = 0.0f, S12 = 0.0f, S22 = 0.0f;
+        float R0 = 0.0f, R1 = 0.0f, R2 = 0.0f;
         for (int l = 0; l < LFO_NL; ++l) {
             su[l] = 0.0f; sh[l] = 0.0f; rho[l] = 0.0f;
             int i = hits[l];
@@ -533,19 +524,16 @@ static void track_one(const lfo_geometry *G, const lfo_params *P, const event_vi
             float h = s * s * (1.0f + G->dRatio * u);
             float r = xm - (a + b * u + c * g_of(u, G->dRatio));
             su[l] = s; sh[l] = h; rho[l] = r;
-            t0[l] = 1.0f;
-            t1[l] = s;
-            t2[l] = h;
-            t11[l] = s * s;
-            t12[l] = s * h;
-            t22[l] = h * h;
-            tr0[l] = r;
-            tr1[l] = s * r;
-            tr2[l] = h * r;
+            S0 = S0 + 1.0f;
+            S1 = S1 + s;
+            S2 = S2 + h;
+            S11 = S11 + s * s;
+            S12 = S12 + s * h;
+            S22 = S22 + h * h;
+            R0 = R0 + r;
+            R1 = R1 + s * r;
+            R2 = R2 + h * r;
         }
-        float S0 = pairsum16(t0), S1 = pairsum16(t1), S2 = pairsum16(t2);
-        float S11 = pairsum16(t11), S12 = pairsum16(t12), S22 = pairsum16(t22);
-        float R0 = pairsum16(tr0), R1 = pairsum16(tr1), R2 = pairsum16(tr2);
         /* normal equations M (da db dc)^T = (R0 R1 R2)^T solved by Cramer's rule */
         float m00 = S11 * S22 - S12 * S12;
         float m01 = S1 * S22 - S12 * S2;
@@ -558,46 +546,42 @@ static void track_one(const lfo_geometry *G, const lfo_params *P, const event_vi
 
         /* residuals to the fitted model; Q_x [R21] */
         float res[LFO_NL];
-        float tq[16] = {0};
+        float Qx = 0.0f;
         for (int l = 0; l < LFO_NL; ++l) {
             res[l] = 0.0f;
             if (hits[l] < 0) continue;
             res[l] = rho[l] - (da + db * su[l] + dc * sh[l]);
-            tq[l] = res[l] * res[l] / (is_uv(l) ? T_uv : P->T_x);
+            Qx = Qx + res[l] * res[l] / (is_uv(l) ? T_uv : P->T_x);
         }
-        float Qx = pairsum16(tq);
 
         /* ---- y least-squares line over the u/v hits [R20]: each hit's y is
          * where its fibre meets the fitted x, y = y_ext - res/dxdy, so the
          * offsets from the input line are eta = -res/dxdy. ---- */
         float eta[LFO_NL];
-        float ty0[16] = {0}, ty1[16] = {0}, ty11[16] = {0}, te0[16] = {0}, te1[16] = {0};
+        float Y_S0 = 0.0f, Y_S1 = 0.0f, Y_S11 = 0.0f, Y0 = 0.0f, Y1 = 0.0f;
         for (int l = 0; l < LFO_NL; ++l) {
             eta[l] = 0.0f;
             int i = hits[l];
             if (i < 0 || !is_uv(l)) continue;
             eta[l] = -res[l] / ev->dxdy[i];
-            ty0[l] = 1.0f;
-            ty1[l] = su[l];
-            ty11[l] = su[l] * su[l];
-            te0[l] = eta[l];
-            te1[l] = su[l] * eta[l];
+            Y_S0 = Y_S0 + 1.0f;
+            Y_S1 = Y_S1 + su[l];
+            Y_S11 = Y_S11 + su[l] * su[l];
+            Y0 = Y0 + eta[l];
+            Y1 = Y1 + su[l] * eta[l];
         }
-        float Y_S0 = pairsum16(ty0), Y_S1 = pairsum16(ty1), Y_S11 = pairsum16(ty11);
-        float Y0 = pairsum16(te0), Y1 = pairsum16(te1);
         float D = Y_S0 * Y_S11 - Y_S1 * Y_S1;
         if (!(fabsf(D) > 0.0f)) continue;
         float dy0 = (Y0 * Y_S11 - Y_S1 * Y1) / D;
         float dty = (Y_S0 * Y1 - Y_S1 * Y0) / D;
         float dslope = dty * 0.0009765625f;
         if (!(fabsf(dslope) < P->T_ty)) continue;              /* [R22] */
-        float tqy[16] = {0};
+        float Qy = 0.0f;
         for (int l = 0; l < LFO_NL; ++l) {
             if (hits[l] < 0 || !is_uv(l)) continue;
             float ry = eta[l] - (dy0 + dty * su[l]);
-            tqy[l] = ry * ry / P->T_y;
+            Qy = Qy + ry * ry / P->T_y;
         }
-        float Qy = pairsum16(tqy);
         /* ---- quality factor [R21] ---- */
         float Q = (Qx / (float)(n - 3) + Qy / (float)(n_uv - 2)) * P->C_nhits[n - 9];
         if (dbg_candQ) dbg_candQ[r] = Q;

@@ -54,7 +54,12 @@ MUTANTS = [
     ("uv_x_uncorrected", "xm = ev->x[i] + ev->dxdy[i] * yv;", "xm = ev->x[i];"),
     ("ndof_x", "(Qx / (float)(n - 3)", "(Qx / (float)(n - 2)"),
     ("C_index", "P->C_nhits[n - 9]", "P->C_nhits[n > 9 ? n - 10 : 0]"),
-    ("Qy_tolerance", "tqy[l] = ry * ry / P->T_y;", "tqy[l] = ry * ry / P->T_x;"),
+    ("Qy_tolerance", "Qy = Qy + ry * ry / P->T_y;", "Qy = Qy + ry * ry / P->T_x;"),
+    ("fit_S12_term", "S12 = S12 + s * h;", "S12 = S12 + s * s;"),
+    ("fit_R2_term", "R2 = R2 + h * r;", "R2 = R2 + s * r;"),
+    ("fit_S0_count", "S0 = S0 + 1.0f;", "S0 = S0 + 1.0f + (l == 0 ? 1.0f : 0.0f);"),
+    ("y_fit_Y1_term", "Y1 = Y1 + su[l] * eta[l];", "Y1 = Y1 + eta[l];"),
+    ("Qx_uv_as_x", "Qx = Qx + res[l] * res[l] / (is_uv(l) ? T_uv : P->T_x);", "Qx = Qx + res[l] * res[l] / P->T_x;"),
     ("T_uv_floor_ignored", "if (T_uv < P->T_uv_floor) T_uv = P->T_uv_floor;", ""),
     ("ty_cut_scale", "float dslope = dty * 0.0009765625f;", "float dslope = dty;"),
     ("qop_curvature_term", "float txT = bb + 2.0f * cc * uT", "float txT = bb + cc * uT"),
