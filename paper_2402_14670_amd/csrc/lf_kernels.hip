@@ -22,7 +22,9 @@
 //   extension  lanes = (candidate, missing layer): closest hit to the
 //              triplet's x(z) model ("Extending triplets to other layers").
 //   fit        16 lanes per candidate (lane = layer slot), four candidates
-//              per pass: x and y least squares, Q, cuts ("Quality Filter");
+//              per pass: x and y least squares with every sum taken
+//              serially in layer order by a DPP chain, Q, cuts ("Quality
+//              Filter");
 //              the argmin over (Q, rank) picks the track; q/p from the slope
 //              change ("Calculation of momentum and track states").
 //
@@ -62,22 +64,31 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Pairwise sum over each aligned group of 16 lanes: lane j adds lane j^1,
-// then j^2, j^4, j^8 (the last two as mirrors, equal to the xor partner once
-// the quads, resp. halves, hold equal values).  Every lane of the group ends
-// with ((v0+v1)+(v2+v3)) + ... in the same association; float addition is
-// commutative, so both partners of a step compute the same bits.
-template <int CTRL>
+template <int CTRL, bool BOUND_ZERO>
 __device__ __forceinline__ float dpp(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, BOUND_ZERO));
 }
-__device__ __forceinline__ float sum16(float v) {
-    v = v + dpp<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
-    v = v + dpp<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
-    v = v + dpp<0x141>(v);   // row_half_mirror: lane 7 - j within 8
-    v = v + dpp<0x140>(v);   // row_mirror: lane 15 - j within 16
-    return v;
+
+// Serial sums over the layer slots of each 16-lane row (slot = lane % 16):
+// afterwards lane 11 of a row holds ((+0 + t_0) + t_1) + ... + t_11 of that
+// row's lanes 0..11, for each of the N sums; the other lanes hold partial
+// sums.  Step k adds each lane's term to the partial sum moved over from the
+// lane before it (row_shr:1, which reads 0 in a row's lane 0), so the partial
+// sum in lane l after step k covers slots l-k..l in ascending order.  The N
+// chains advance together and fill each other's DPP read hazards.
+template <int N>
+__device__ __forceinline__ void chain12(const float (&t)[N], float (&s)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) s[i] = 0.0f + t[i];
+#pragma unroll
+    for (int k = 1; k < NL; ++k) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) s[i] = dpp<0x111, true>(s[i]) + t[i];   // row_shr:1
+    }
 }
+
+// Lane 11 of each row's value, broadcast over the row (row_newbcast:11).
+__device__ __forceinline__ float row_lane11(float v) { return dpp<0x15B, false>(v); }
 
 // Lane i's float, broadcast (i uniform).
 __device__ __forceinline__ float bcast_f(float v, int i) {
@@ -1027,10 +1038,12 @@ struct Track {
         mark(C_CY_EXTEND);
         // ---- fits and quality: 16 lanes per candidate, 4 candidates per pass ----
         // Lane (g, j) = (lane / 16, lane % 16) holds layer j of the g-th
-        // candidate of the pass; each fit sum is the pairwise sum over the 16
-        // slots (absent hits and slots 12..15 add +0), formed by four DPP
-        // exchange steps, so every lane of the group ends with the same sums
-        // and solves the normal equations itself.
+        // candidate of the pass.  Every fit sum is the serial sum over the
+        // candidate's hits in ascending layer order (absent layers add +0,
+        // which leaves a running sum that started at +0 unchanged), formed by
+        // a DPP chain over the row whose result sits in lane 11; the solves
+        // run in every lane, the ones of lane 11 are broadcast over the row
+        // where the per-hit residuals need them, and lane 11 decides.
         uint64_t fitm = 0;   // candidates passing the candidate rule, in rank order
         {
             bool rule = false;
@@ -1052,6 +1065,7 @@ struct Track {
         const int g = lane >> 4, j = lane & 15;
         const bool uvj = j < NL && is_uv(j);
         const float Tj = uvj ? T_uv : P->T_x;
+        constexpr int LR = NL - 1;   // the row lane that holds the chained sums
         while (fitm) {
             int r = -1;
             int rq[4];
@@ -1087,9 +1101,18 @@ struct Track {
                 h = sv * sv * (1.0f + dR * u);
                 rr = xm - (a + b * u + c * g_of(u, dR));
             }
-            const float S0 = sum16(pres ? 1.0f : 0.0f), S1 = sum16(sv), S2 = sum16(h);
-            const float S11 = sum16(sv * sv), S12 = sum16(sv * h), S22 = sum16(h * h);
-            const float R0 = sum16(rr), R1 = sum16(sv * rr), R2 = sum16(h * rr);
+            // hit counts: integers, the same in any order
+            const uint32_t row_bits = 16u * (uint32_t)g;
+            const int n = __popc((uint32_t)(__ballot(pres) >> row_bits) & 0xFFFFu);
+            const int n_uv = __popc((uint32_t)(__ballot(pres_uv) >> row_bits) & 0xFFFFu);
+            const float S0 = (float)n, YS0 = (float)n_uv;
+            // x normal equations, and the slot sums of the y line
+            const float t1[10] = {sv, h, sv * sv, sv * h, h * h, rr, sv * rr, h * rr,
+                                  pres_uv ? sv : 0.0f, pres_uv ? sv * sv : 0.0f};
+            float s1[10];
+            chain12(t1, s1);
+            const float S1 = s1[0], S2 = s1[1], S11 = s1[2], S12 = s1[3], S22 = s1[4];
+            const float R0 = s1[5], R1 = s1[6], R2 = s1[7], YS1 = s1[8], YS11 = s1[9];
             const float m00 = S11 * S22 - S12 * S12;
             const float m01 = S1 * S22 - S12 * S2;
             const float m02 = S1 * S12 - S11 * S2;
@@ -1099,40 +1122,46 @@ struct Track {
             const float da = (R0 * m00 - S1 * (R1 * S22 - S12 * R2) + S2 * (R1 * S12 - S11 * R2)) / det_s;
             const float db = (S0 * (R1 * S22 - S12 * R2) - R0 * m01 + S2 * (S1 * R2 - R1 * S2)) / det_s;
             const float dc = (S0 * (S11 * R2 - R1 * S12) - S1 * (S1 * R2 - R1 * S2) + R0 * m02) / det_s;
-            const float res = pres ? rr - (da + db * sv + dc * h) : 0.0f;
-            const float Qx = sum16(pres ? res * res / Tj : 0.0f);
+            const float da_r = row_lane11(da), db_r = row_lane11(db), dc_r = row_lane11(dc);
+            const float res = pres ? rr - (da_r + db_r * sv + dc_r * h) : 0.0f;
             const float eta = pres_uv ? -res / dxy : 0.0f;
-            const float YS0 = sum16(pres_uv ? 1.0f : 0.0f), YS1 = sum16(pres_uv ? sv : 0.0f);
-            const float YS11 = sum16(pres_uv ? sv * sv : 0.0f);
-            const float Y0 = sum16(eta), Y1 = sum16(pres_uv ? sv * eta : 0.0f);
+            // Q_x, and the y line's residual sums
+            const float t2[3] = {pres ? res * res / Tj : 0.0f, eta, pres_uv ? sv * eta : 0.0f};
+            float s2[3];
+            chain12(t2, s2);
+            const float Qx = s2[0], Y0 = s2[1], Y1 = s2[2];
             const float D = YS0 * YS11 - YS1 * YS1;
             const bool ok_y = fabsf(D) > 0.0f;
             const float D_s = ok_y ? D : 1.0f;
             const float dy0 = (Y0 * YS11 - YS1 * Y1) / D_s;
             const float dty = (YS0 * Y1 - YS1 * Y0) / D_s;
             const float dslope = dty * INV1024;
-            const float ry = pres_uv ? eta - (dy0 + dty * sv) : 0.0f;
-            const float Qy = sum16(pres_uv ? ry * ry / P->T_y : 0.0f);
-            const int n = (int)S0, n_uv = (int)YS0;   // exact counts
+            const float dy0_r = row_lane11(dy0), dty_r = row_lane11(dty);
+            const float ry = pres_uv ? eta - (dy0_r + dty_r * sv) : 0.0f;
+            const float t3[1] = {pres_uv ? ry * ry / P->T_y : 0.0f};
+            float s3[1];
+            chain12(t3, s3);
+            const float Qy = s3[0];
             const float Q = (Qx / (float)(n - 3) + Qy / (float)(n_uv - 2)) * P->C_nhits[n - 9 < 0 ? 0 : (n - 9 > 3 ? 3 : n - 9)];
             const bool acc = r >= 0 && ok_x && ok_y && fabsf(dslope) < P->T_ty && Q < P->T_Q;
             // candidates of this pass in rank order: the first strict minimum wins ties
-            const uint64_t accm = __ballot(acc && j == 0);
+            const uint64_t accm = __ballot(acc && j == LR);
             if constexpr (CNT) cnt[C_ACCEPTED] += (uint32_t)__popcll(accm);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (!((accm >> (16 * k)) & 1ull)) continue;
-                const float qk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Q), 16 * k));
+                if (!((accm >> (16 * k + LR)) & 1ull)) continue;
+                const int src = 16 * k + LR;
+                const float qk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Q), src));
                 if (best_r >= 0 && !(qk < best_Q)) continue;
                 best_r = rq[k];
                 best_Q = qk;
-                best_n = __builtin_amdgcn_readlane(n, 16 * k);
-                bfa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a + da), 16 * k));
-                bfb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b + db * INV1024), 16 * k));
-                bfc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c + dc * INV1024SQ), 16 * k));
+                best_n = __builtin_amdgcn_readlane(n, src);
+                bfa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a + da), src));
+                bfb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b + db * INV1024), src));
+                bfc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c + dc * INV1024SQ), src));
                 bfy0 = __int_as_float(__builtin_amdgcn_readlane(
-                    __float_as_int((y_in + ty_in * (P->z_ref - P->z_in)) + dy0), 16 * k));
-                bfty = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ty_in + dslope), 16 * k));
+                    __float_as_int((y_in + ty_in * (P->z_ref - P->z_in)) + dy0), src));
+                bfty = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ty_in + dslope), src));
             }
         }
 

@@ -54,6 +54,30 @@ def compare(ref: dict, got: dict, rows=None, label: str = "") -> dict:
     return dict(bit_exact_params=exact, params=total, found=int(ref["found"][sel].sum()))
 
 
+def host_threads() -> int:
+    """Threads for the oracle on this host (at most 16, one GPU's share)."""
+    import os
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def oracle_parallel(ev, params=None, world=None):
+    """The oracle over a whole batch, its events split into one contiguous
+    slice per host thread (the oracle's C call releases the GIL); the same
+    results as one oracle.run over the batch, in the batch's track order."""
+    import concurrent.futures as cf
+    n = host_threads()
+    bounds = [(ev.n_events * k // n, ev.n_events * (k + 1) // n) for k in range(n)]
+    parts = [lfgen.select_events(ev, range(a, b)) for a, b in bounds if b > a]
+    w = W if world is None else world
+    with cf.ThreadPoolExecutor(max_workers=n) as pool:
+        outs = list(pool.map(lambda part: oracle.run(part, w, params), parts))
+    return {k: np.concatenate([o[k] for o in outs]) for k in outs[0]}
+
+
 def oracle_rows(ev, events):
     """Global track rows of the given events."""
     rows = [np.arange(int(ev.trk_off[e]), int(ev.trk_off[e + 1])) for e in events]

@@ -197,20 +197,6 @@ def test_full_nominal_batch():
     say(f"    found={st['found']} bit-exact params {st['bit_exact_params']}/{st['params']}")
 
 
-def test_large_batches_sampled():
-    """Uneven (2,000 events) and stress (400 events) batches in one launch;
-    the oracle checks a sample of events."""
-    rng = np.random.default_rng(1)
-    for name, n, k in (("uneven", 2000, 120), ("stress", 400, 12)):
-        ev = lfgen.generate(name, n_events=n)
-        say(f"[gpu] {name}[{n}] batched, oracle on {k} sampled events")
-        got = run_gpu(ev, "batched")
-        events = np.sort(rng.choice(n, size=k, replace=False))
-        ref, rows = oracle_on_events(ev, events)
-        st = compare(ref, got, rows=rows, label=f"{name}[{n}]")
-        say(f"    found={st['found']} bit-exact params {st['bit_exact_params']}/{st['params']}")
-
-
 def test_work_counters_match_oracle():
     """The counting build's per-stage totals equal the oracle's intermediate counts."""
     from paper_2402_14670_amd import lf

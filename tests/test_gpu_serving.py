@@ -16,11 +16,12 @@ pytestmark = pytest.mark.gpu
 def pool():
     nom = lfgen.generate("nominal", n_events=40)
     une = lfgen.generate("uneven", n_events=40)
+    stress = lfgen.generate("stress", n_events=6)
     z = np.zeros(0, np.float32)
     empty = lfgen.Events(**{**lfgen.select_events(une, [0]).__dict__, "trk_off": np.zeros(2, np.uint32),
                             "trk_x": z, "trk_y": z, "trk_tx": z, "trk_ty": z, "trk_qop": z,
                             "trk_pid": np.zeros(0, np.int32)})
-    ev = lfgen.concat([nom, empty, une])
+    ev = lfgen.concat([nom, empty, une, stress])
     ref = oracle.run(ev, W)
     return ev, event_digests(ref, ev.trk_off)
 
