@@ -223,7 +223,9 @@ void lf_default_params(lf_params *p);
  * run VELO-only input, as the paper's 2022 trigger did. */
 void lf_default_params_no_ut(lf_params *p);
 
-/* Creates a context on the current HIP device.  Geometry and parameters are
+/* Creates a context on the current HIP device (the detector of the Context
+ * section; tolerances of the Table of parameters and tolerances and the
+ * C(n_hits) table of the Quality Filter section).  Geometry and parameters are
  * copied.  device_budget_bytes bounds the device memory of all resident
  * batches (0 = no bound).  Errors: LF_ERR_INVALID (NULL pointers, parameters
  * out of range), LF_ERR_DEVICE, LF_ERR_NOMEM. */
@@ -238,15 +240,18 @@ int lf_create(const lf_geometry *geom, const lf_params *params, size_t device_bu
  * lf_upload_events runs the same checks. */
 int lf_check_batch(const lf_batch *batch);
 
-/* Validates a host batch, copies it to device memory (on hip_stream) and
- * returns its id.  Input and output buffers of the batch stay resident until
+/* The step's input (Algorithm logic: upstream track states and the SciFi
+ * hits of each event).  Validates a host batch, copies it to device memory
+ * (on hip_stream) and returns its id.  Input and output buffers of the batch stay resident until
  * lf_fetch_tracks or lf_release_batch.  Errors: LF_ERR_INVALID (malformed
  * batch; nothing is copied), LF_ERR_TOO_LARGE (over budget), LF_ERR_NOMEM,
  * LF_ERR_DEVICE. */
 int lf_upload_events(lf_ctx *ctx, const lf_batch *batch, void *hip_stream, uint64_t *batch_id);
 
-/* Enqueues the whole hot path for a resident batch on hip_stream and
- * returns without waiting.  mode is LF_MODE_PLAIN, LF_MODE_BATCHED or
+/* The whole step of Algorithm logic: search windows (Defining the search
+ * windows), Triplet Seeding, Extending triplets to other layers, Quality
+ * Filter and Calculation of momentum and track states.  Enqueues it for a
+ * resident batch on hip_stream and returns without waiting.  mode is LF_MODE_PLAIN, LF_MODE_BATCHED or
  * LF_MODE_PERSISTENT; all modes write identical results.  May be called again on
  * the same batch (results are rewritten).  Errors: LF_ERR_STATE (unknown
  * batch), LF_ERR_INVALID (mode), LF_ERR_DEVICE. */
@@ -259,7 +264,10 @@ int lf_find_tracks(lf_ctx *ctx, uint64_t batch_id, int mode, void *hip_stream);
  * Errors: LF_ERR_STATE, LF_ERR_INVALID (NULL counts), LF_ERR_DEVICE. */
 int lf_work_counts(lf_ctx *ctx, uint64_t batch_id, void *hip_stream, int64_t *counts, size_t n_counts);
 
-/* Copies the results of a batch into caller buffers holding at least
+/* The step's output: at most one forward track per input track, the best
+ * candidate of the Quality Filter section, with its fitted x(z) and y(z)
+ * parameters and the q/p of Calculation of momentum and track states.
+ * Copies the results of a batch into caller buffers holding at least
  * cap_tracks >= number of input tracks slots, waits for completion and
  * frees the batch.  Errors: LF_ERR_STATE, LF_ERR_INVALID (NULL buffer or
  * cap_tracks too small; the batch stays resident), LF_ERR_DEVICE. */

@@ -51,6 +51,16 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// The lane index, opaque to the optimiser: a kernel that loops over tracks
+// hands this to each track, so that values derived from the lane are not
+// hoisted out of the loop (they would stay live in registers across the
+// whole loop body).
+__device__ __forceinline__ int opaque_lane_id() {
+    int l = (int)__lane_id();
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
 // Element i of a device array of less than 4 GiB (the host checks the batch
 // sizes): a 32-bit byte offset from a wave-uniform base, so the load takes
 // the scalar-base form with one 32-bit address register.
@@ -296,6 +306,8 @@ struct Track {
     // the event's hits share one z and one dxdy per bucket (DevBatch::uni):
     // only x is staged per hit, each window keeps its first hit's values
     bool uni = false;
+    // this wave's lane index (opaque_lane_id() in kernels that loop over tracks)
+    int ln = lane_id();
     // Binary16 seeding: per seed set, whether it runs in half precision
     // (seed_fp16, both outer windows non-empty with one z each), the window
     // centres and its constants; then the ones shared by both sets.
@@ -339,7 +351,7 @@ struct Track {
     // list (sorted, lane i < nL holds entry i) and this pass's keys, counted
     // against broadcast keys; keys are distinct, so the ranks are too.
     __device__ void merge(bool valid, uint64_t key, int h1) {
-        const int lane = lane_id();
+        const int lane = ln;
         const uint64_t bal = __ballot(valid);
         const int nb = __popcll(bal);
         if (nb == 0) return;
@@ -368,7 +380,7 @@ struct Track {
 
     // Complete the first `count` queued doublets with their closest middle hit.
     __device__ void flush(int count) {
-        const int lane = lane_id();
+        const int lane = ln;
         bool tri = false, valid = false;
         uint64_t key = 0;
         int best = -1;
@@ -446,7 +458,7 @@ struct Track {
     }
 
     __device__ void run(uint32_t t, uint32_t ev) {
-        const int lane = lane_id();
+        const int lane = ln;
         if constexpr (CNT) {
             for (int k = 0; k < C_N; ++k) cnt[k] = 0;
             cnt[C_TRACKS] = 1;
@@ -1195,7 +1207,7 @@ struct Track {
     }
 
     __device__ void write_none(uint32_t t, size_t o12) {
-        const int lane = lane_id();
+        const int lane = ln;
         if (lane < NL) B.hit_idx[o12 + lane] = -1;
         if (lane == 0) {
             B.found[t] = 0;
@@ -1277,6 +1289,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_persistent(DevBatch B, const KPa
             // costs ~30 VGPRs of loop-carried state and two waves per SIMD
             asm volatile("" ::: "memory");
             Track<NW, NS, false, H16> tr{B, P, lds[w], 0, {}, 0};
+            tr.ln = opaque_lane_id();
             tr.run(t, B.trk_ev[t]);
         }
     }
