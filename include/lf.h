@@ -257,6 +257,32 @@ int lf_upload_events(lf_ctx *ctx, const lf_batch *batch, void *hip_stream, uint6
  * batch), LF_ERR_INVALID (mode), LF_ERR_DEVICE. */
 int lf_find_tracks(lf_ctx *ctx, uint64_t batch_id, int mode, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the hot
+ * path of lf_find_tracks over a batch that already sits in device memory,
+ * writing into caller-allocated device outputs, with no allocation of any
+ * kind.  in holds DEVICE pointers in the lf_batch layout (in->n_events is a
+ * host value; the batch must be well formed as lf_check_batch defines it:
+ * it is not validated, since that would need a copy to the host);
+ * n_hits = hit_off[24*n_events] and n_tracks = trk_off[n_events] are passed
+ * by the caller; out holds DEVICE pointers in the lf_tracks_out layout, at
+ * least n_tracks slots.  The caller owns all of these and keeps them valid
+ * until the work completes.  mode is LF_MODE_BATCHED or LF_MODE_PERSISTENT
+ * (the per-event mode needs host offsets).  Results equal those of
+ * lf_upload_events + lf_find_tracks on the same batch.  Enqueues kernels on
+ * hip_stream and returns without waiting.
+ * Scratch: one fixed device array per GPU, part of the library's code
+ * object (17 MiB, held until the process ends): the persistent queue words
+ * (cleared by a kernel at every call), one byte per event and one word per
+ * track.  Limits: at most 2^20 events and 2^22 tracks per call
+ * (LF_ERR_TOO_LARGE beyond, nothing launched), fewer than 2^30 hits.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams, or from several contexts or threads) race and must be
+ * serialised by the caller.  Errors: LF_ERR_INVALID (NULL pointer, mode,
+ * hit count), LF_ERR_TOO_LARGE, LF_ERR_STATE, LF_ERR_DEVICE. */
+int lf_find_tracks_noalloc(lf_ctx *ctx, const lf_batch *in, uint32_t n_hits, uint32_t n_tracks,
+                           const lf_tracks_out *out, int mode, void *hip_stream);
+
 /* Runs the hot path once more over a resident batch in a counting build of
  * the kernel and writes the total work counters (LF_WC_*) to counts[0..n):
  * the units the roofline's algorithmic operation count is built from.

@@ -38,6 +38,7 @@ struct lf_ctx {
     size_t used = 0;
     int device = 0;
     hipStream_t stream = nullptr;
+    void *fixed = nullptr;             // this device's fixed scratch (lf_find_tracks_noalloc)
     lfk::ExecCfg exec{2, 4, 0, 0};
     std::map<uint64_t, Batch> batches;
     uint64_t next_id = 1;
@@ -274,6 +275,7 @@ int lf_create(const lf_geometry *geom, const lf_params *params, size_t device_bu
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     int ncu = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (e == hipSuccess) e = lfk::fixed_scratch(&c->fixed);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&c->d_params), sizeof(lfk::KParams));
     if (e == hipSuccess) {
         const lfk::KParams k = to_kparams(*geom, *params);
@@ -403,6 +405,52 @@ int lf_find_tracks(lf_ctx *c, uint64_t batch_id, int mode, void *hip_stream) {
                                           mode, c->exec,
                                           bt.trk_off.data(), pick(c, hip_stream));
     if (e != hipSuccess) return hip_fail(c, e, "lf_find_tracks");
+    return LF_OK;
+}
+
+int lf_find_tracks_noalloc(lf_ctx *c, const lf_batch *in, uint32_t n_hits, uint32_t n_tracks,
+                           const lf_tracks_out *out, int mode, void *hip_stream) {
+    if (!c) return LF_ERR_INVALID;
+    if (!in || !out) return fail(c, LF_ERR_INVALID, "lf_find_tracks_noalloc: NULL argument");
+    if (mode != LF_MODE_BATCHED && mode != LF_MODE_PERSISTENT)
+        return fail(c, LF_ERR_INVALID, "lf_find_tracks_noalloc: mode must be LF_MODE_BATCHED or LF_MODE_PERSISTENT");
+    const uint32_t E = in->n_events;
+    if (E > lfk::FIXED_MAX_EVENTS || n_tracks > lfk::FIXED_MAX_TRACKS)
+        return fail(c, LF_ERR_TOO_LARGE, "lf_find_tracks_noalloc: " + std::to_string(E) + " events and " +
+                                             std::to_string(n_tracks) + " tracks exceed the fixed scratch (at most " +
+                                             std::to_string(lfk::FIXED_MAX_EVENTS) + " events and " +
+                                             std::to_string(lfk::FIXED_MAX_TRACKS) + " tracks)");
+    if (n_hits >= (1u << 30)) return fail(c, LF_ERR_INVALID, "lf_find_tracks_noalloc: 2^30 or more hits");
+    if (!in->hit_off || !in->trk_off) return fail(c, LF_ERR_INVALID, "lf_find_tracks_noalloc: NULL offset array");
+    if (n_hits && (!in->hit_x || !in->hit_z || !in->hit_dxdy))
+        return fail(c, LF_ERR_INVALID, "lf_find_tracks_noalloc: NULL hit array");
+    if (n_tracks && (!in->trk_x || !in->trk_y || !in->trk_tx || !in->trk_ty || !in->trk_qop || !out->found ||
+                     !out->n_hits || !out->hit_idx || !out->a || !out->b || !out->c || !out->y0 || !out->ty ||
+                     !out->qop || !out->Q))
+        return fail(c, LF_ERR_INVALID, "lf_find_tracks_noalloc: NULL track or output array");
+    if (!c->fixed) return fail(c, LF_ERR_STATE, "lf_find_tracks_noalloc: no fixed scratch on this context");
+    if (n_tracks == 0) return LF_OK;
+    char *fx = static_cast<char *>(c->fixed);
+    lfk::DevBatch d{};
+    d.hit_off = in->hit_off;
+    d.hx = in->hit_x; d.hz = in->hit_z; d.hd = in->hit_dxdy;
+    d.trk_off = in->trk_off;
+    d.trk_ev = reinterpret_cast<const uint32_t *>(fx + lfk::FIXED_TRK_EV_OFF);
+    d.tx_ = in->trk_x; d.ty_ = in->trk_y; d.ttx = in->trk_tx; d.tty = in->trk_ty; d.tqop = in->trk_qop;
+    d.uni = reinterpret_cast<const uint8_t *>(fx + lfk::FIXED_UNI_OFF);
+    d.found = out->found; d.nhits = out->n_hits; d.hit_idx = out->hit_idx;
+    d.a = out->a; d.b = out->b; d.c = out->c; d.y0 = out->y0; d.ty = out->ty; d.qop = out->qop; d.Q = out->Q;
+    d.counter = reinterpret_cast<uint32_t *>(fx + lfk::FIXED_QUEUE_OFF);
+    d.stats = nullptr;
+    d.n_events = E;
+    d.n_tracks = n_tracks;
+    hipStream_t s = pick(c, hip_stream);
+    hipError_t e = lfk::launch_zero_words(d.counter, 256, s);
+    if (e == hipSuccess) e = lfk::launch_track_event(d, s);
+    if (e == hipSuccess) e = lfk::launch_event_uniform(d, reinterpret_cast<uint8_t *>(fx + lfk::FIXED_UNI_OFF), s);
+    if (e == hipSuccess)
+        e = lfk::launch_find(d, c->d_params, c->params.n_hits_window, lfapi::ctx_sides(c), mode, c->exec, nullptr, s);
+    if (e != hipSuccess) return hip_fail(c, e, "lf_find_tracks_noalloc");
     return LF_OK;
 }
 

@@ -98,4 +98,19 @@ hipError_t launch_poison(const DevBatch &b, hipStream_t s);
 // Resident blocks per compute unit of the persistent kernel (0 on error).
 int persistent_blocks_per_cu(int n_hits_window, int n_sides, int waves_per_block);
 
+// Fixed scratch of the non-allocating entry point: one array in the code
+// object's device memory per GPU, holding the persistent mode's queue words,
+// the per-event uniform flags and the event of each track.
+constexpr uint32_t FIXED_MAX_EVENTS = 1u << 20;
+constexpr uint32_t FIXED_MAX_TRACKS = 1u << 22;
+constexpr size_t FIXED_QUEUE_OFF = 0;                       // 256 x u32
+constexpr size_t FIXED_UNI_OFF = 1024;                      // FIXED_MAX_EVENTS x u8
+constexpr size_t FIXED_TRK_EV_OFF = FIXED_UNI_OFF + FIXED_MAX_EVENTS;   // FIXED_MAX_TRACKS x u32
+constexpr size_t FIXED_BYTES = FIXED_TRK_EV_OFF + 4 * (size_t)FIXED_MAX_TRACKS;
+// Device address of the current device's copy of the fixed scratch, looked
+// up once per device (the first call on a device must run with it current).
+hipError_t fixed_scratch(void **out);
+// Writes zeros to n words with a kernel (no memset node under capture).
+hipError_t launch_zero_words(uint32_t *p, uint32_t n, hipStream_t s);
+
 }  // namespace lfk

@@ -31,7 +31,11 @@
 // The arithmetic is binary32 in a fixed order (the library is built with
 // -ffp-contract=off, correctly rounded division, no fast-math), so every
 // decision is identical to a serial evaluation of the same expressions.
-// Nothing in this file allocates; all scratch is LDS.
+// Nothing in this file allocates; the kernels' scratch is LDS, apart from
+// the fixed device array that the non-allocating entry point uses for its
+// queue words and per-event and per-track indexes.
+#include <mutex>
+
 #include "lf_internal.h"
 
 namespace lfk {
@@ -1459,6 +1463,44 @@ __global__ __launch_bounds__(256) void k_poison(DevBatch B) {
 }
 
 }  // namespace
+
+// Fixed scratch of the non-allocating entry point (layout: FIXED_* in
+// lf_internal.h).  Host code never passes this name to a kernel: it holds
+// the address fixed_scratch() looked up for the current device.
+static __device__ __align__(256) uint8_t scratch[FIXED_BYTES];
+
+hipError_t fixed_scratch(void **out) {
+    constexpr int MAXDEV = 64;
+    static std::mutex mu;
+    static void *addr[MAXDEV] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAXDEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
+namespace {
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t *__restrict__ p, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+}  // namespace
+
+hipError_t launch_zero_words(uint32_t *p, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_words, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_poison(const DevBatch &b, hipStream_t s) {
     if (b.n_tracks == 0) return hipSuccess;

@@ -98,7 +98,7 @@ class lf_exec(ctypes.Structure):
 EXPORTS = ("lf_default_params", "lf_default_params_no_ut", "lf_check_batch", "lf_create", "lf_upload_events", "lf_find_tracks",
            "lf_work_counts", "lf_fetch_tracks", "lf_copy_tracks", "lf_poison_tracks", "lf_release_batch", "lf_set_exec", "lf_batch_info",
            "lf_device_bytes_in_use", "lf_serve_run", "lf_graph_create", "lf_graph_launch", "lf_graph_destroy",
-           "lf_destroy", "lf_last_error")
+           "lf_destroy", "lf_last_error", "lf_find_tracks_noalloc")
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -122,6 +122,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lf_upload_events.argtypes = [vp, P(lf_batch), vp, P(u64)]
     lib.lf_find_tracks.argtypes = [vp, u64, i32, vp]
     lib.lf_fetch_tracks.argtypes = [vp, u64, P(lf_tracks_out), sz, vp]
+    lib.lf_find_tracks_noalloc.argtypes = [vp, P(lf_batch), ctypes.c_uint32, ctypes.c_uint32, P(lf_tracks_out), i32,
+                                           vp]
     lib.lf_work_counts.argtypes = [vp, u64, vp, P(ctypes.c_int64), sz]
     lib.lf_copy_tracks.argtypes = [vp, u64, P(lf_tracks_out), sz, vp]
     lib.lf_poison_tracks.argtypes = [vp, u64, vp]
@@ -142,7 +144,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lf_last_error.restype = ctypes.c_char_p
     for name in ("lf_check_batch", "lf_create", "lf_upload_events", "lf_find_tracks", "lf_work_counts",
                  "lf_fetch_tracks", "lf_release_batch", "lf_set_exec", "lf_batch_info", "lf_serve_run",
-                 "lf_graph_create", "lf_graph_launch", "lf_copy_tracks", "lf_poison_tracks"):
+                 "lf_graph_create", "lf_graph_launch", "lf_copy_tracks", "lf_poison_tracks",
+                 "lf_find_tracks_noalloc"):
         getattr(lib, name).restype = i32
     return lib
 
@@ -278,6 +281,34 @@ def lf_find_tracks(ctx, batch_id: int, mode=LF_MODE_BATCHED, stream=None) -> Non
     if isinstance(mode, str):
         mode = MODES[mode]
     _check(lib().lf_find_tracks(ctx, ctypes.c_uint64(batch_id), int(mode), _stream(stream)), ctx)
+
+
+_IN_FIELDS = ("hit_off", "hit_x", "hit_z", "hit_dxdy", "trk_off", "trk_x", "trk_y", "trk_tx", "trk_ty", "trk_qop")
+_OUT_FIELDS = ("found", "n_hits", "hit_idx", "a", "b", "c", "y0", "ty", "qop", "Q")
+
+
+def lf_find_tracks_noalloc(ctx, dev_in: dict, dev_out: dict, mode=LF_MODE_BATCHED, stream=None) -> None:
+    """Hot path over a batch already in device memory, into device outputs,
+    with no allocation (the library's fixed scratch).  dev_in maps the
+    lf_batch array names to contiguous device tensors (u32 offsets, f32
+    values); dev_out maps the lf_tracks_out names to contiguous device
+    tensors of at least n_tracks slots (hit_idx n_tracks x 12)."""
+    if isinstance(mode, str):
+        mode = MODES[mode]
+    for k in _IN_FIELDS:
+        if not dev_in[k].is_contiguous():
+            raise ValueError(f"dev_in[{k!r}] is not contiguous")
+    for k in _OUT_FIELDS:
+        if not dev_out[k].is_contiguous():
+            raise ValueError(f"dev_out[{k!r}] is not contiguous")
+    b = lf_batch()
+    b.n_events = int(dev_in["trk_off"].numel()) - 1
+    for k in _IN_FIELDS:
+        setattr(b, k, dev_in[k].data_ptr())
+    o = lf_tracks_out(*[dev_out[k].data_ptr() for k in _OUT_FIELDS])
+    _check(lib().lf_find_tracks_noalloc(ctx, ctypes.byref(b), int(dev_in["hit_x"].numel()),
+                                        int(dev_in["trk_x"].numel()), ctypes.byref(o), int(mode),
+                                        _stream(stream)), ctx)
 
 
 def lf_work_counts(ctx, batch_id: int, stream=None) -> dict:
