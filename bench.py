@@ -132,37 +132,90 @@ def time_mode(lf, ctx, bid, mode, steps, warmup, stream):
     return start.elapsed_time(end) / steps, wall
 
 
-def serving(lf, ctx, ev, batched_out, n_requests, seed=40):
-    """Serving loop on the nominal events as a request pool: first saturated
-    (every request arrives at t = 0: the transfer-inclusive batched rate),
-    then open-loop Poisson arrivals at 50%, 80% and 95% of that rate.  Every
+def pinned_copy_peak(mib=256, reps=5):
+    """Host-link copy rates of plain pinned-memory copies (torch, one stream):
+    host to device and device to host, best of reps, GB/s."""
+    import torch
+    n = mib * (1 << 20)
+    h = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    d = torch.empty(n, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    res = {}
+    for name, dst, src in (("h2d", d, h), ("d2h", h, d)):
+        best = None
+        for _ in range(reps):
+            st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            st.record(s)
+            with torch.cuda.stream(s):
+                dst.copy_(src, non_blocking=True)
+            en.record(s)
+            torch.cuda.synchronize()
+            ms = st.elapsed_time(en)
+            best = ms if best is None else min(best, ms)
+        res[name + "_GBs"] = round(n / (best * 1e-3) / 1e9, 2)
+    res["bytes"] = n
+    del h, d
+    return res
+
+
+def _serve_runs(lf, ctx, ev, ref, req, cfg, base_rate, fracs, rng, label):
+    """One saturated run (every request arrives at t = 0), then open-loop
+    Poisson arrivals at the given fractions of base_rate (None: of the
+    saturated rate); each request's digest is compared with the batched run's."""
+    import numpy as np
+    n = len(req)
+    dig, lat, st = lf.lf_serve_run(ctx, ev, req, np.zeros(n), cfg)
+    ok = bool(np.array_equal(dig, ref[req]))
+    sat = st["events_per_s"]
+    base = sat if base_rate is None else base_rate
+    print(f"bench: serving {label} saturated {sat:12.0f} events/s, mean batch {st['mean_batch_events']:.0f}",
+          file=sys.stderr, flush=True)
+    link = {"bytes_in_per_event": round(st["bytes_in"] / n, 1), "bytes_out_per_event": round(st["bytes_out"] / n, 1),
+            "link_in_GBs": round(st["bytes_in"] / st["wall_s"] / 1e9, 2),
+            "link_out_GBs": round(st["bytes_out"] / st["wall_s"] / 1e9, 2)}
+    rates = []
+    for frac in fracs:
+        arr = np.cumsum(rng.exponential(1.0 / (frac * base), size=n))
+        dig, lat, s2 = lf.lf_serve_run(ctx, ev, req, arr, cfg)
+        ok = ok and bool(np.array_equal(dig, ref[req]))
+        rates.append({"frac": frac, "offered_events_per_s": round(frac * base, 1),
+                      "events_per_s": round(s2["events_per_s"], 1),
+                      "p50_ms": round(s2["lat_p50_s"] * 1e3, 4), "p99_ms": round(s2["lat_p99_s"] * 1e3, 4),
+                      "p999_ms": round(s2["lat_p999_s"] * 1e3, 4), "max_ms": round(s2["lat_max_s"] * 1e3, 4),
+                      "mean_batch_events": round(s2["mean_batch_events"], 1), "max_queue": s2["max_queue"]})
+        print(f"bench: serving {label} {frac:4.2f}  {s2['events_per_s']:12.0f} events/s  p50 "
+              f"{s2['lat_p50_s']*1e3:.3f} ms  p99 {s2['lat_p99_s']*1e3:.3f} ms  p99.9 {s2['lat_p999_s']*1e3:.3f} ms"
+              f"  mean batch {s2['mean_batch_events']:.0f}", file=sys.stderr, flush=True)
+    return {"config": cfg, "saturated_events_per_s": round(sat, 1), "saturated_mean_batch_events":
+            round(st["mean_batch_events"], 1), "host_link_at_saturation": link, "rates": rates,
+            "results_equal_batched": ok}
+
+
+def serving(lf, ctx, ev, batched_out, n_requests, batched_eps, seed=40):
+    """Serving loop on the workload's events as a request pool.  Two pools:
+    on the device (events already in HBM, as upstream GPU stages leave them;
+    arrivals at 50%, 80% and 95% of the batched throughput), and in pinned
+    host memory (every event read over the host link; arrivals at fractions
+    of its own saturated rate, with the link's bytes and rates).  Every
     request's result digest is checked against the batched run's result."""
     import numpy as np
     ref = lf.result_digests(batched_out, ev.trk_off)
     rng = np.random.default_rng(seed)
     req = rng.integers(0, ev.n_events, size=n_requests).astype(np.uint32)
-    cfg = {"max_batch_events": 256, "n_slots": 2, "device_budget_bytes": 8 << 30}
-    dig, lat, st = lf.lf_serve_run(ctx, ev, req, np.zeros(n_requests), cfg)
-    ok = bool(np.array_equal(dig, ref[req]))
-    sat = st["events_per_s"]
-    print(f"bench: serving saturated {sat:12.0f} events/s, mean batch {st['mean_batch_events']:.0f}",
-          file=sys.stderr, flush=True)
-    rates = []
-    for frac in (0.5, 0.8, 0.95):
-        arr = np.cumsum(rng.exponential(1.0 / (frac * sat), size=n_requests))
-        dig, lat, s2 = lf.lf_serve_run(ctx, ev, req, arr, cfg)
-        ok = ok and bool(np.array_equal(dig, ref[req]))
-        rates.append({"frac": frac, "offered_events_per_s": round(frac * sat, 1),
-                      "events_per_s": round(s2["events_per_s"], 1),
-                      "p50_ms": round(s2["lat_p50_s"] * 1e3, 4), "p99_ms": round(s2["lat_p99_s"] * 1e3, 4),
-                      "p999_ms": round(s2["lat_p999_s"] * 1e3, 4), "max_ms": round(s2["lat_max_s"] * 1e3, 4),
-                      "mean_batch_events": round(s2["mean_batch_events"], 1), "max_queue": s2["max_queue"]})
-        print(f"bench: serving {frac:4.2f}  {s2['events_per_s']:12.0f} events/s  p50 {s2['lat_p50_s']*1e3:.3f} ms"
-              f"  p99 {s2['lat_p99_s']*1e3:.3f} ms  mean batch {s2['mean_batch_events']:.0f}",
-              file=sys.stderr, flush=True)
-    return {"requests_per_run": n_requests, "pool_events": ev.n_events, "config": cfg,
-            "saturated_events_per_s": round(sat, 1), "rates": rates, "results_equal_batched": ok,
-            "latency": "arrival to results in host memory; uploads and downloads included"}
+    dev_cfg = {"max_batch_events": 1024, "n_slots": 4, "device_budget_bytes": 8 << 30, "pool_on_device": 1}
+    host_cfg = {"max_batch_events": 256, "n_slots": 2, "device_budget_bytes": 8 << 30}
+    dev = _serve_runs(lf, ctx, ev, ref, req, dev_cfg, batched_eps, (0.5, 0.8, 0.95), rng, "device pool")
+    host = _serve_runs(lf, ctx, ev, ref, req, host_cfg, None, (0.5, 0.8, 0.95), rng, "host pool")
+    peak = pinned_copy_peak()
+    host["pinned_copy_peak"] = peak
+    sat_link = host["host_link_at_saturation"]
+    host["link_frac_of_h2d_peak"] = round(sat_link["link_in_GBs"] / peak["h2d_GBs"], 3)
+    return {"requests_per_run": n_requests, "pool_events": ev.n_events,
+            "device_pool": dict(dev, rate_basis="fractions of the batched throughput "
+                                                "(%.1f events/s)" % batched_eps),
+            "host_pool": dict(host, rate_basis="fractions of the host-pool saturated rate"),
+            "latency": "arrival to results in host memory (digests and every track slot downloaded)"}
 
 
 def host_cores() -> int:
@@ -528,11 +581,11 @@ def main():
                if "general" in variants else None)
     print(f"bench: end to end {e2e['ms_per_batch']:8.3f} ms/batch  {e2e['events_per_s']:12.0f} events/s",
           file=sys.stderr, flush=True)
-    serve = serving(lf, ctx, ev, out, args.serve_requests) if args.serve_requests else None
-    lf.lf_destroy(ctx)
-
     ms = res["batched"]
     value = ev.n_events / (ms * 1e-3)
+    serve = serving(lf, ctx, ev, out, args.serve_requests, value) if args.serve_requests else None
+    lf.lf_destroy(ctx)
+
     ops = model_ops(work)
     achieved = ops / (ms * 1e-3) / 1e12
     ops_ex = sum(OPS_PER_UNIT[k] * work[k] for k in OPS_PER_UNIT)
@@ -582,8 +635,10 @@ def main():
                      "hbm": {"algorithmic_bytes": nbytes, "achieved_GBs": round(nbytes / (ms * 1e-3) / 1e9, 1),
                              "peak_GBs": HBM_PEAK_GBS,
                              "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}},
-        "latency_ms": ({"p50": serve["rates"][1]["p50_ms"], "p99": serve["rates"][1]["p99_ms"],
-                        "p999": serve["rates"][1]["p999_ms"], "at": "serving, 80% of saturated throughput"}
+        "latency_ms": ({"p50": serve["device_pool"]["rates"][1]["p50_ms"],
+                        "p99": serve["device_pool"]["rates"][1]["p99_ms"],
+                        "p999": serve["device_pool"]["rates"][1]["p999_ms"],
+                        "at": "serving from a device-resident pool at 80% of the batched throughput"}
                        if serve else None),
         "serving": serve,
         "end_to_end": e2e,

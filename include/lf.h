@@ -347,7 +347,10 @@ typedef struct {
     uint32_t max_wait_us;        /* ... unless the oldest has waited this long [0] */
     uint32_t n_slots;            /* batches in flight, one stream each, 1..16 [4] */
     uint32_t n_pack_threads;     /* unused (0..64): batches are assembled on the device */
-    uint32_t reserved;
+    uint32_t pool_on_device;     /* 0: the pool sits in pinned host memory and every batch reads its
+                                    events over the host link [0]; 1: the pool is copied to device
+                                    memory before the clock starts (events left in HBM by earlier
+                                    GPU stages, as in a GPU trigger), and batches gather from there */
     size_t device_budget_bytes;  /* admission budget for resident events [8 GiB] */
 } lf_serve_config;
 
@@ -359,6 +362,10 @@ typedef struct {
     double events_per_s;         /* n_requests / wall_s */
     double lat_p50_s, lat_p99_s, lat_p999_s, lat_max_s;  /* arrival to results in host memory */
     double mean_batch_events;
+    uint64_t bytes_in;           /* bytes over the host link into the device: the event blobs the gather
+                                    reads from the pinned pool (offsets, hits, states; none with
+                                    pool_on_device) and the batch descriptors */
+    uint64_t bytes_out;          /* bytes over the host link out: digests and track slots */
 } lf_serve_stats;
 
 /* Runs a stream of requests through the serving loop and returns when all
@@ -379,6 +386,9 @@ typedef struct {
  * indices, bits of a b c y0 ty qop Q -- summed as splitmix64(h ^ index *
  * 0x9E3779B97F4A7C15) over the event's tracks); req_latency_s[i]
  * (optional) its arrival-to-results-on-host latency.
+ * With pool_on_device the gather reads the pool from device memory instead
+ * (the pool's device copy is made before the clock and is not charged to
+ * the budget).
  * Errors: LF_ERR_INVALID, LF_ERR_TOO_LARGE (an event exceeds the budget),
  * LF_ERR_NOMEM, LF_ERR_DEVICE. */
 int lf_serve_run(lf_ctx *ctx, const lf_batch *pool, uint32_t n_requests, const uint32_t *req_event,

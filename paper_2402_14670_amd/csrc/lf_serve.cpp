@@ -136,7 +136,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
     if (cfg.max_batch_events == 0) cfg.max_batch_events = 1024;
     if (cfg.n_slots == 0) cfg.n_slots = 4;
     if (cfg.device_budget_bytes == 0) cfg.device_budget_bytes = size_t(8) << 30;
-    if (cfg.n_slots > 16 || cfg.n_pack_threads > 64 || cfg.max_batch_events > (1u << 20))
+    if (cfg.n_slots > 16 || cfg.n_pack_threads > 64 || cfg.max_batch_events > (1u << 20) || cfg.pool_on_device > 1)
         return lfapi::ctx_fail(ctx, LF_ERR_INVALID, "lf_serve_run: configuration out of range");
     const uint32_t PE = pool_b->n_events;
     for (uint32_t i = 0; i < n_requests; ++i) {
@@ -167,6 +167,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
 
     std::vector<Slot> slots(cfg.n_slots);
     void *ring_mem = nullptr;
+    char *pool_hbm = nullptr;   // pool_on_device: the pool's copy in device memory
     hipError_t err = hipHostMalloc(reinterpret_cast<void **>(&pool.blob), pbytes ? pbytes : 1, hipHostMallocDefault);
     if (err != hipSuccess) return lfapi::ctx_fail(ctx, LF_ERR_NOMEM, "lf_serve_run: pinned pool allocation failed");
     pool.bytes = pbytes;
@@ -179,6 +180,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
             if (s.out) (void)hipHostFree(s.out);
         }
         if (ring_mem) (void)hipFree(ring_mem);
+        if (pool_hbm) (void)hipFree(pool_hbm);
         if (pool.blob) (void)hipHostFree(pool.blob);
     };
     for (uint32_t e = 0; e < PE; ++e) {
@@ -235,9 +237,20 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
         s.stage_cap = cfg.max_batch_events;
         s.out_cap = biggest.out_bytes;
     }
-    // device address of the pinned pool (the gather kernel reads it directly)
+    // where the gather kernel reads the pool: the pinned blob over the host
+    // link, or (pool_on_device) its copy in device memory
     char *pool_dev = nullptr;
-    err = hipHostGetDevicePointer(reinterpret_cast<void **>(&pool_dev), pool.blob, 0);
+    if (cfg.pool_on_device) {
+        err = hipMalloc(reinterpret_cast<void **>(&pool_hbm), pbytes ? pbytes : 1);
+        if (err != hipSuccess) {
+            cleanup();
+            return lfapi::ctx_fail(ctx, LF_ERR_NOMEM, "lf_serve_run: device pool allocation failed");
+        }
+        err = hipMemcpy(pool_hbm, pool.blob, pbytes, hipMemcpyHostToDevice);
+        pool_dev = pool_hbm;
+    } else {
+        err = hipHostGetDevicePointer(reinterpret_cast<void **>(&pool_dev), pool.blob, 0);
+    }
     if (err != hipSuccess) {
         cleanup();
         return lfapi::ctx_fail(ctx, LF_ERR_DEVICE, std::string("lf_serve_run: ") + hipGetErrorString(err));
@@ -342,7 +355,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
     std::deque<uint32_t> queue;       // arrived, not yet in a batch
     std::deque<uint32_t> inflight;    // slot indices in submission order
     uint32_t next_arrival = 0, completed = 0;
-    uint64_t n_batches = 0, batched_events = 0, max_queue = 0;
+    uint64_t n_batches = 0, batched_events = 0, max_queue = 0, bytes_in = 0, bytes_out = 0;
     size_t max_dev = 0;
     int rc = LF_OK;
     const Clock::time_point t0 = Clock::now();
@@ -420,6 +433,11 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
                     inflight.push_back((uint32_t)free_slot);
                     ++n_batches;
                     batched_events += E;
+                    if (!cfg.pool_on_device)
+                        for (uint32_t k = 0; k < E; ++k)
+                            bytes_in += 25 * 4 + (uint64_t)pool.nh[evs[k]] * 12 + (uint64_t)pool.nt[evs[k]] * 20;
+                    bytes_in += (uint64_t)E * sizeof(lfk::GatherDesc);
+                    bytes_out += lay.out_bytes;
                     progress = true;
                 }
             }
@@ -452,6 +470,8 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
         stats->mean_batch_events = n_batches ? (double)batched_events / n_batches : 0.0;
         stats->max_device_bytes = max_dev;
         stats->max_queue = max_queue;
+        stats->bytes_in = bytes_in;
+        stats->bytes_out = bytes_out;
     }
     return LF_OK;
 }

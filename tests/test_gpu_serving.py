@@ -39,7 +39,10 @@ def _stream(n_pool, n, rate, seed=40):
     ({"n_slots": 1, "max_batch_events": 1}, 5000.0),
     ({"n_slots": 2, "max_batch_events": 7, "n_pack_threads": 3}, None),
     ({"min_batch_events": 64, "max_wait_us": 2000}, 50000.0),
-], ids=["poisson", "saturated", "one-by-one", "small-batches", "wait-to-fill"])
+    ({"pool_on_device": 1}, 20000.0),
+    ({"pool_on_device": 1, "max_batch_events": 1024, "n_slots": 4}, None),
+], ids=["poisson", "saturated", "one-by-one", "small-batches", "wait-to-fill", "device-pool-poisson",
+        "device-pool-saturated"])
 def test_results_same_alone_and_in_the_mix(pool, cfg, rate):
     from paper_2402_14670_amd import lf
     ev, ref = pool
@@ -56,6 +59,12 @@ def test_results_same_alone_and_in_the_mix(pool, cfg, rate):
     assert np.all(lat > 0) and st["n_requests"] == len(req)
     if cfg.get("max_batch_events") == 1:
         assert st["n_batches"] == len(req)
+    # host-link bytes: descriptors always, event blobs only from a host pool
+    nh = np.diff(ev.hit_off[::24].astype(np.int64))[req]
+    nt = np.diff(ev.trk_off.astype(np.int64))[req]
+    blobs = int((100 + 12 * nh + 20 * nt).sum())
+    assert st["bytes_in"] == 24 * len(req) + (0 if cfg.get("pool_on_device") else blobs)
+    assert st["bytes_out"] >= 8 * len(req) + 78 * int(nt.sum())
 
 
 def test_backpressure_under_small_budget(pool):
