@@ -155,6 +155,30 @@ def test_uniform_and_non_uniform_events_in_one_batch():
     _check_all_modes(ev, "nominal[6] uniform and non-uniform events")
 
 
+def test_events_of_every_kind_in_one_batch():
+    """One batch mixes nominal events, a stress event (41k hits, every window
+    capped), an event with a single input track, a fully jittered event
+    (per-hit z and stereo slopes), an event without tracks and a repeated
+    nominal event, in both window sizes: every track's result equals the
+    oracle's whatever its neighbours."""
+    nom = lfgen.generate("nominal", n_events=5, seed=31)
+    one = lfgen.select_events(lfgen.generate("nominal", n_events=1, seed=32), [0])
+    keep = np.zeros(one.n_tracks, bool)
+    keep[7] = True
+    one = lfgen.Events(**{**one.__dict__, "trk_off": np.array([0, 1], np.uint32),
+                          **{k: getattr(one, k)[keep] for k in ("trk_x", "trk_y", "trk_tx", "trk_ty", "trk_qop",
+                                                               "trk_pid")}})
+    z = np.zeros(0, np.float32)
+    empty = lfgen.Events(**{**lfgen.select_events(nom, [0]).__dict__, "trk_off": np.zeros(2, np.uint32),
+                            "trk_x": z, "trk_y": z, "trk_tx": z, "trk_ty": z, "trk_qop": z,
+                            "trk_pid": np.zeros(0, np.int32)})
+    stress = lfgen.generate("stress", n_events=1, seed=33)
+    jit = _jitter(lfgen.generate("nominal", n_events=1, seed=34), 1.5, 0.02, seed=35)
+    ev = lfgen.concat([nom, stress, one, jit, empty, lfgen.select_events(nom, [2])])
+    for params in (None, {"n_hits_window": 64}):
+        _check_all_modes(ev, "events of every kind", params)
+
+
 @pytest.mark.parametrize("n_hits_window", [64, 48, 32])
 def test_per_hit_geometry_with_x_only_staging(n_hits_window):
     """Windows of more than 32 hits stage only x and read a mixed window's z
