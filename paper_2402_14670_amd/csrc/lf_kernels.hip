@@ -104,6 +104,15 @@ __device__ __forceinline__ void chain12(const float (&t)[N], float (&s)[N]) {
 // Lane 11 of each row's value, broadcast over the row (row_newbcast:11).
 __device__ __forceinline__ float row_lane11(float v) { return dpp<0x15B, false>(v); }
 
+// The least float above x (NaN and +inf map to themselves, +-0 to the least
+// positive subnormal): for every finite v, v <= x exactly when v < next_up(x).
+__device__ __forceinline__ float next_up(float x) {
+    const int b = __float_as_int(x);
+    if (!(x < INFINITY)) return x;                 // NaN, +inf
+    if ((b & 0x7fffffff) == 0) return __int_as_float(1);
+    return __int_as_float(x > 0.0f ? b + 1 : b - 1);
+}
+
 // Lane i's float, broadcast (i uniform).
 __device__ __forceinline__ float bcast_f(float v, int i) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
@@ -276,6 +285,7 @@ struct WaveLds {
     float wd[NS][6][ZW];       //              stereo tangent (stereo layers; XO: first hit only)
     int32_t wfirst[NS][NL];    // event-local index of each window's first hit
     int32_t wlen[NS][NL];
+    float gz[NL];              // z of each layer plane
     uint64_t tk[MAX_TRIPLETS];      // top-n keys, sorted
     uint8_t th1[MAX_TRIPLETS];      // middle hit of each kept triplet
     union {
@@ -284,7 +294,10 @@ struct WaveLds {
         };
         struct {               // candidates (after seeding)
             float ca[MAX_TRIPLETS], cb[MAX_TRIPLETS], cc[MAX_TRIPLETS];  // triplet x(z) models
-            int8_t ch[MAX_TRIPLETS][NL];    // candidate hits, window-relative, -1 = none
+            union {
+                int8_t ch[MAX_TRIPLETS][NL];    // candidate hits, window-relative, -1 = none
+                uint32_t chw[MAX_TRIPLETS][NL / 4];   // the same, four layers per word
+            };
         };
     };
 };
@@ -312,6 +325,8 @@ struct Track {
     bool uni = false;
     // this wave's lane index (opaque_lane_id() in kernels that loop over tracks)
     int ln = lane_id();
+    // z of the middle-layer planes of the two seed sets (layers 4 and 7)
+    float z4 = 0.0f, z7 = 0.0f;
     // Binary16 seeding: per seed set, whether it runs in half precision
     // (seed_fp16, both outer windows non-empty with one z each), the window
     // centres and its constants; then the ones shared by both sets.
@@ -363,7 +378,7 @@ struct Track {
         const uint64_t mine = lane < nL ? L.tk[lane] : 0ull;
         const int mh1 = lane < nL ? L.th1[lane] : 0;
         int r_new = 0, r_old = lane;
-        for (int i = 0; i < nL; ++i) r_new += bcast64(mine, i) < key ? 1 : 0;
+        for (int i = 0; i < nL; ++i) r_new += L.tk[i] < key ? 1 : 0;
         for (uint64_t m = bal; m; m &= m - 1) {
             const uint64_t k = bcast64(key, __builtin_ctzll(m));
             r_new += k < key ? 1 : 0;
@@ -441,7 +456,7 @@ struct Track {
             const float K = s ? P->K_last : P->K_first;
             const float x0 = L.wx[sd][l0][i0], z0 = zat(sd, l0, i0);
             const float txd = (L.wx[sd][l2][i2] - x0) / (zat(sd, l2, i2) - z0);   // the doublet's slope, as queued
-            const float x1e = P->z[l1] * txd + (x0 - txd * z0) * K;
+            const float x1e = (s ? z7 : z4) * txd + (x0 - txd * z0) * K;
             const float *wx1 = L.wx[sd][l1];
             best = closest_sorted<NW>([wx1](int j) { return wx1[j]; }, L.wlen[sd][l1], x1e, bd);
             if (best >= 0) {
@@ -473,6 +488,11 @@ struct Track {
         const float x_in = B.tx_[t], y_in = B.ty_[t], tx_in = B.ttx[t], ty_in = B.tty[t];
         const float qop = B.tqop[t];
         const float dR = P->dRatio;
+        // lane l < 12: the z and stereo tangent of layer plane l (fetched by
+        // the lanes that need them with a cross-lane read)
+        const float gz = lane < NL ? P->z[lane] : 0.0f, gd = lane < NL ? P->dxdy[lane] : 0.0f;
+        z4 = bcast_f(gz, 4);
+        z7 = bcast_f(gz, 7);
 
         // ---- kinematics ----
         // VELO-UT input: p and q from q/p.  VELO-only input: the assumed
@@ -549,24 +569,25 @@ struct Track {
                 const int l = lane < 3 * NL ? lane / 3 : 0;
                 const uint32_t b0 = (uint32_t)__shfl((int)ho, 2 * l + zone);
                 const uint32_t b1 = (uint32_t)__shfl((int)ho, 2 * l + zone + 1);
+                const float zl = __shfl(gz, l), dxl = __shfl(gd, l);
                 if (lane < 3 * NL) {
                     const int k = lane - 3 * l;
-                    const float ye = y_in + ty_in * (P->z[l] - P->z_in);
+                    const float ye = y_in + ty_in * (zl - P->z_in);
                     float xc, xmin, xmax;
                     if constexpr (NS == 2) {
                         // straight line; two windows per layer sharing an overlap
-                        const float xe = x_in + tx_in * (P->z[l] - P->z_in);
-                        const float x0 = is_uv(l) ? xe - P->dxdy[l] * ye : xe;
+                        const float xe = x_in + tx_in * (zl - P->z_in);
+                        const float x0 = is_uv(l) ? xe - dxl * ye : xe;
                         const float tol = is_uv(l) ? P->uv_halfwidth : xtol;
                         if (sd == 0) { xmin = x0 - tol; xmax = x0 + P->noUT_overlap; }
                         else { xmin = x0 - P->noUT_overlap; xmax = x0 + tol; }
                         xc = 0.5f * (xmin + xmax);
                     } else {
-                        const float dz = P->z[l] - P->z_mag;
-                        const float dzT = P->z[l] - P->z_T;
+                        const float dz = zl - P->z_mag;
+                        const float dzT = zl - P->z_T;
                         const float xe = x_mag + T * dz + kd * dzT * dzT * (1.0f + dR * dzT);
                         if (is_uv(l)) {
-                            xc = xe - P->dxdy[l] * ye;
+                            xc = xe - dxl * ye;
                             xmin = xc - P->uv_halfwidth;
                             xmax = xc + P->uv_halfwidth;
                         } else {
@@ -586,12 +607,13 @@ struct Track {
                     }
                     uint32_t lo = b0;
                     uint32_t n = b1 - b0;
-                    // lower bound (x < key) for x_min and the centre, upper bound (x <= key) for x_max
+                    // lower bound (x < key) for x_min and the centre, upper bound
+                    // (x <= key) for x_max, which for finite x is x < next_up(key)
+                    const float kk = k == 2 ? next_up(key) : key;
                     while (n > 0) {
                         const uint32_t half = n >> 1;
                         const float v = ld32(B.hx, lo + half);
-                        const bool right = k == 2 ? (v <= key) : (v < key);
-                        if (right) { lo += half + 1; n -= half + 1; } else { n = half; }
+                        if (v < kk) { lo += half + 1; n -= half + 1; } else { n = half; }
                     }
                     pos = (int)(lo - ebase);
                 }
@@ -621,6 +643,7 @@ struct Track {
                     wl[sd] = len;
                     L.wfirst[sd][lane] = first;
                     L.wlen[sd][lane] = len;
+                    if (sd == 0) L.gz[lane] = gz;
                     if (uni && len > 0) {
                         // the window's (and the bucket's) one z and stereo tangent
                         L.wz[sd][lane][0] = zl;
@@ -640,8 +663,33 @@ struct Track {
         // HBM and take the general paths below.
         constexpr int SU = NL * NW / WAVE;
         constexpr int SC = SU > 6 ? 6 : SU;   // rounds per chunk of loads in flight
+        // One window per layer in an event whose buckets each share one z
+        // and one stereo slope: x only, each lane's window bounds taken from
+        // the lane that holds them.
+        if (NS == 1 && uni) {
 #pragma unroll
-        for (int sd = 0; sd < NS; ++sd) {
+          for (int u0 = 0; u0 < SU; u0 += SC) {
+            float sx[SC];
+            uint32_t smask = 0;
+#pragma unroll
+            for (int v = 0; v < SC; ++v) {
+                const int it = lane + WAVE * (u0 + v), l = it / NW, j = it - NW * (it / NW);
+                const int f = __shfl(wf[0], l), n = __shfl(wl[0], l);
+                sx[v] = 0.0f;
+                if (j < n) {
+                    sx[v] = ld32(B.hx, ebase + (uint32_t)(f + j));
+                    smask |= 1u << v;
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < SC; ++v) {
+                const int it = lane + WAVE * (u0 + v), l = it / NW, j = it - NW * (it / NW);
+                if ((smask >> v) & 1u) L.wx[0][l][j] = sx[v];
+            }
+          }
+        }
+#pragma unroll
+        for (int sd = 0; sd < ((NS == 1 && uni) ? 0 : NS); ++sd) {
 #pragma unroll
           for (int u0 = 0; u0 < SU; u0 += SC) {
             float sx[SU], sz[SU], sd_[SU];
@@ -821,12 +869,18 @@ struct Track {
                 }
                 if (jhi < jlo) jhi = jlo;
             }
+            // the pair loop runs while any lane has pairs left (the two-window
+            // build takes the wave's largest span first, which keeps its
+            // register count within its occupancy bound)
             int span = jhi - jlo;
+            if constexpr (NS == 2) {
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const int o = __shfl_xor(span, off);
-                span = o > span ? o : span;
+                for (int off = 32; off > 0; off >>= 1) {
+                    const int o = __shfl_xor(span, off);
+                    span = o > span ? o : span;
+                }
             }
+            auto more = [&](int k) { return NS == 2 ? k < span : __ballot(k < span) != 0; };
             // the binary32 filter of pair (i0, i2)
             auto test32 = [&](int i2) {
                 const float x2 = L.wx[sd][l2][i2], z2 = zat(sd, l2, i2);
@@ -864,7 +918,7 @@ struct Track {
                 }
             };
             if constexpr (!H16) {
-                for (int k = 0; k < span; ++k) {
+                for (int k = 0; more(k); ++k) {
                     const int i2 = jlo + k;
                     const bool tested = i2 < jhi;
                     push(tested && test32(i2), tested, i2);
@@ -878,7 +932,7 @@ struct Track {
                 const half2v MM = __builtin_bit_cast(half2v, kTMINMAX);
                 const half2v TX = TXQP.xx, QP = TXQP.yy, TXS = TXSTC.xx, TC = TXSTC.yy;
                 const _Float16 tmin = MM.x, tmax = MM.y;
-                for (int k = 0; k < span; k += 2) {
+                for (int k = 0; more(k); k += 2) {
                     const int ia = jlo + k, ib = ia + 1;
                     const bool ta = ia < jhi, tb = ib < jhi;
                     bool pa = false, pb = false;
@@ -985,7 +1039,8 @@ struct Track {
             e.sd = NS > 1 ? (int)((kr >> 13) & 1u) : 0;
             if (slot < 3) e.l = s ? 4 * slot : 4 * slot + 3;
             else e.l = 4 * ((slot - 3) >> 1) + 1 + ((slot - 3) & 1);
-            const float u = P->z[e.l] - P->z_ref;
+            const float zl = L.gz[e.l];
+            const float u = zl - P->z_ref;
             e.xe = L.ca[e.r] + L.cb[e.r] * u + L.cc[e.r] * g_of(u, dR);
             e.n = L.wlen[e.sd][e.l];
             e.wx = L.wx[e.sd][e.l];
@@ -994,7 +1049,7 @@ struct Track {
             // changes no distance and no comparison.  With a common stereo slope
             // in the window the values stay sorted.
             e.uv = slot >= 3;
-            e.yp = e.uv ? y_in + ty_in * (P->z[e.l] - P->z_in) : 0.0f;
+            e.yp = e.uv ? y_in + ty_in * (zl - P->z_in) : 0.0f;
             e.scan = e.uv && ((dvar >> (NL * e.sd + e.l)) & 1u);
             e.wd1 = e.uv ? L.wd[e.sd][uv_index(e.l)][0] : 0.0f;
             e.wdv = L.wd[e.sd][e.uv ? uv_index(e.l) : 0];
@@ -1064,13 +1119,16 @@ struct Track {
         {
             bool rule = false;
             if (lane < nL) {
+                // a layer's byte is a hit index (sign bit clear) or -1; word st
+                // holds station st, its stereo layers in bytes 1 and 2
                 int n = 0;
                 bool st_ok = true;
 #pragma unroll
-                for (int l = 0; l < NL; ++l) n += L.ch[lane][l] >= 0 ? 1 : 0;
-#pragma unroll
-                for (int st = 0; st < 3; ++st)
-                    if (L.ch[lane][4 * st + 1] < 0 && L.ch[lane][4 * st + 2] < 0) st_ok = false;
+                for (int st = 0; st < 3; ++st) {
+                    const uint32_t pres = ~L.chw[lane][st] & 0x80808080u;
+                    n += __popc(pres);
+                    st_ok = st_ok && (pres & 0x00808000u) != 0u;
+                }
                 rule = n >= 9 && st_ok;
             }
             fitm = __ballot(rule);
