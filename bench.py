@@ -192,30 +192,42 @@ def _serve_runs(lf, ctx, ev, ref, req, cfg, base_rate, fracs, rng, label):
             "results_equal_batched": ok}
 
 
+SERVE_DEVICE_CFG = {"max_batch_events": 1024, "n_slots": 2, "device_budget_bytes": 8 << 30, "pool_on_device": 1}
+SERVE_HOST_CFG = {"max_batch_events": 256, "n_slots": 2, "device_budget_bytes": 8 << 30}
+
+
 def serving(lf, ctx, ev, batched_out, n_requests, batched_eps, seed=40):
-    """Serving loop on the workload's events as a request pool.  Two pools:
-    on the device (events already in HBM, as upstream GPU stages leave them;
-    arrivals at 50%, 80% and 95% of the batched throughput), and in pinned
-    host memory (every event read over the host link; arrivals at fractions
-    of its own saturated rate, with the link's bytes and rates).  Every
-    request's result digest is checked against the batched run's result."""
+    """Serving loop on the workload's events as a request pool.  A pool
+    resident on the device (events already in HBM, as upstream GPU stages
+    leave them; arrivals at 50%, 80% and 95% of the batched throughput),
+    first with every result copied to host memory, then with the results
+    kept on the device for later GPU stages (digests to the host); and a
+    pool in pinned host memory (every event read over the host link;
+    arrivals at fractions of its own saturated rate, with the link's bytes
+    and rates).  Every request's result digest is checked against the
+    batched run's result."""
     import numpy as np
     ref = lf.result_digests(batched_out, ev.trk_off)
     rng = np.random.default_rng(seed)
     req = rng.integers(0, ev.n_events, size=n_requests).astype(np.uint32)
-    dev_cfg = {"max_batch_events": 1024, "n_slots": 4, "device_budget_bytes": 8 << 30, "pool_on_device": 1}
-    host_cfg = {"max_batch_events": 256, "n_slots": 2, "device_budget_bytes": 8 << 30}
-    dev = _serve_runs(lf, ctx, ev, ref, req, dev_cfg, batched_eps, (0.5, 0.8, 0.95), rng, "device pool")
-    host = _serve_runs(lf, ctx, ev, ref, req, host_cfg, None, (0.5, 0.8, 0.95), rng, "host pool")
+    fr = (0.5, 0.8, 0.95)
+    dev = _serve_runs(lf, ctx, ev, ref, req, SERVE_DEVICE_CFG, batched_eps, fr, rng, "device pool")
+    dev_keep = _serve_runs(lf, ctx, ev, ref, req, dict(SERVE_DEVICE_CFG, results_on_device=1), batched_eps, fr, rng,
+                           "device pool, results on device")
+    host = _serve_runs(lf, ctx, ev, ref, req, SERVE_HOST_CFG, None, fr, rng, "host pool")
     peak = pinned_copy_peak()
     host["pinned_copy_peak"] = peak
     sat_link = host["host_link_at_saturation"]
     host["link_frac_of_h2d_peak"] = round(sat_link["link_in_GBs"] / peak["h2d_GBs"], 3)
+    basis = "fractions of the batched throughput (%.1f events/s)" % batched_eps
     return {"requests_per_run": n_requests, "pool_events": ev.n_events,
-            "device_pool": dict(dev, rate_basis="fractions of the batched throughput "
-                                                "(%.1f events/s)" % batched_eps),
-            "host_pool": dict(host, rate_basis="fractions of the host-pool saturated rate"),
-            "latency": "arrival to results in host memory (digests and every track slot downloaded)"}
+            "device_pool": dict(dev, rate_basis=basis,
+                                latency="arrival to results in host memory (digests and every track slot)"),
+            "device_pool_results_on_device": dict(dev_keep, rate_basis=basis,
+                                                  latency="arrival to the digest in host memory; the results "
+                                                          "stay in device memory"),
+            "host_pool": dict(host, rate_basis="fractions of the host-pool saturated rate",
+                              latency="arrival to results in host memory (digests and every track slot)")}
 
 
 def host_cores() -> int:
@@ -638,7 +650,8 @@ def main():
         "latency_ms": ({"p50": serve["device_pool"]["rates"][1]["p50_ms"],
                         "p99": serve["device_pool"]["rates"][1]["p99_ms"],
                         "p999": serve["device_pool"]["rates"][1]["p999_ms"],
-                        "at": "serving from a device-resident pool at 80% of the batched throughput"}
+                        "at": "serving from a device-resident pool at 80% of the batched throughput, "
+                              "results to host memory"}
                        if serve else None),
         "serving": serve,
         "end_to_end": e2e,

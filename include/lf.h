@@ -350,7 +350,12 @@ typedef struct {
     uint32_t pool_on_device;     /* 0: the pool sits in pinned host memory and every batch reads its
                                     events over the host link [0]; 1: the pool is copied to device
                                     memory before the clock starts (events left in HBM by earlier
-                                    GPU stages, as in a GPU trigger), and batches gather from there */
+                                    GPU stages, as in a GPU trigger) and stays resident: a batch is a
+                                    list of pool events, read in place */
+    uint32_t results_on_device;  /* 0: every batch's results are copied to host memory [0]; 1: the
+                                    results stay in the batch's device region (for later GPU stages)
+                                    and only the per-event digests come back */
+    uint32_t reserved;           /* 0 */
     size_t device_budget_bytes;  /* admission budget for resident events [8 GiB] */
 } lf_serve_config;
 
@@ -386,9 +391,12 @@ typedef struct {
  * indices, bits of a b c y0 ty qop Q -- summed as splitmix64(h ^ index *
  * 0x9E3779B97F4A7C15) over the event's tracks); req_latency_s[i]
  * (optional) its arrival-to-results-on-host latency.
- * With pool_on_device the gather reads the pool from device memory instead
- * (the pool's device copy is made before the clock and is not charged to
- * the budget).
+ * With pool_on_device the pool is copied to device memory once, before the
+ * clock (not charged to the budget), and a batch is its list of pool
+ * events: the host uploads the list and the batch's result-slot offsets, a
+ * kernel maps each slot to its pool track, and the hot path reads the pool
+ * in place (no gather).  With results_on_device a request completes when its
+ * digest is in host memory; its results stay in device memory.
  * Errors: LF_ERR_INVALID, LF_ERR_TOO_LARGE (an event exceeds the budget),
  * LF_ERR_NOMEM, LF_ERR_DEVICE. */
 int lf_serve_run(lf_ctx *ctx, const lf_batch *pool, uint32_t n_requests, const uint32_t *req_event,

@@ -47,6 +47,10 @@ struct DevBatch {
     uint32_t *counter;         // [256] per-XCD queue heads and exited-wave count (batched mode), zero between launches
     unsigned long long *stats; // [32] work counters (counting launch only)
     uint32_t n_events, n_tracks;
+    // batched mode over slots of a resident pool: result slot t (< n_map)
+    // follows input track trk_map[t] (nullptr: slot t is track t)
+    const uint32_t *trk_map;
+    uint32_t n_map;
 };
 
 struct ExecCfg {
@@ -79,6 +83,11 @@ hipError_t launch_gather(const GatherDesc *desc, uint32_t n_events, const BatchI
 
 // Fills trk_ev from trk_off (one thread per track).
 hipError_t launch_track_event(const DevBatch &b, hipStream_t s);
+// Result slots of a batch of pool events evs[0..n_events) (slots [toff[e],
+// toff[e+1]) for event e, n_slots = toff[n_events], read on the device):
+// map[i] = the pool track slot i follows.  All arrays in device memory.
+hipError_t launch_track_map(const uint32_t *evs, const uint32_t *toff, uint32_t n_events, uint32_t n_slots,
+                            const uint32_t *pool_trk_off, uint32_t *map, hipStream_t s);
 // The hot path.  P points to a KParams in device memory.  mode: 0 plain
 // (per-event launches), 1 batched (one wavefront per track), 2 persistent
 // (resident wavefronts pulling from per-XCD work queues).

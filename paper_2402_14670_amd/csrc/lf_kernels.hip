@@ -476,7 +476,8 @@ struct Track {
         merge(valid, key, best);
     }
 
-    __device__ void run(uint32_t t, uint32_t ev) {
+    // Track tin of the batch (input state), result slot t, event ev.
+    __device__ void run(uint32_t t, uint32_t ev, uint32_t tin) {
         const int lane = ln;
         if constexpr (CNT) {
             for (int k = 0; k < C_N; ++k) cnt[k] = 0;
@@ -485,8 +486,8 @@ struct Track {
         }
         // bucket offsets of this event (both zones), fetched with the track state
         const uint32_t ho = lane <= 2 * NL ? ld32(B.hit_off, ev * 24u + (uint32_t)lane) : 0u;
-        const float x_in = B.tx_[t], y_in = B.ty_[t], tx_in = B.ttx[t], ty_in = B.tty[t];
-        const float qop = B.tqop[t];
+        const float x_in = B.tx_[tin], y_in = B.ty_[tin], tx_in = B.ttx[tin], ty_in = B.tty[tin];
+        const float qop = B.tqop[tin];
         const float dR = P->dRatio;
         // lane l < 12: the z and stereo tangent of layer plane l (fetched by
         // the lanes that need them with a cross-lane read)
@@ -1287,7 +1288,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_plain(DevBatch B, const KParams 
     const uint32_t t = B.trk_off[ev] + blockIdx.x * WPB + w;
     if (t >= B.trk_off[ev + 1]) return;
     Track<NW, NS, false, H16> tr{B, P, lds[w], 0, {}, 0};
-    tr.run(t, ev);
+    tr.run(t, ev, t);
 }
 
 // Blocks are dispatched to the 8 XCDs round-robin (block b -> XCD b % 8);
@@ -1305,9 +1306,16 @@ __global__ __launch_bounds__(WPB * WAVE) __attribute__((amdgpu_waves_per_eu(NS =
     const uint32_t per = gridDim.x / NXCD;
     const uint32_t lb = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
     const uint32_t t = lb * WPB + w;
-    if (t >= B.n_tracks) return;
+    // result slot t; its input track t, or trk_map[t] when a map is given
+    uint32_t tin = t;
+    if (B.trk_map) {
+        if (t >= B.n_map) return;
+        tin = B.trk_map[t];
+    } else if (t >= B.n_tracks) {
+        return;
+    }
     Track<NW, NS, CNT, H16> tr{B, P, lds[w], 0, {}, 0};
-    tr.run(t, B.trk_ev[t]);
+    tr.run(t, B.trk_ev[tin], tin);
     if constexpr (CNT) {
         if (lane_id() == 0)
             for (int k = 0; k < C_N; ++k) atomicAdd(&B.stats[k], (unsigned long long)tr.cnt[k]);
@@ -1352,7 +1360,7 @@ __global__ __launch_bounds__(WPB * WAVE) void k_persistent(DevBatch B, const KPa
             asm volatile("" ::: "memory");
             Track<NW, NS, false, H16> tr{B, P, lds[w], 0, {}, 0};
             tr.ln = opaque_lane_id();
-            tr.run(t, B.trk_ev[t]);
+            tr.run(t, B.trk_ev[t], t);
         }
     }
     if (lane_id() == 0) {
@@ -1403,6 +1411,22 @@ __global__ __launch_bounds__(256) void k_gather(const GatherDesc *__restrict__ d
         out.tqop[g] = st[4 * T + i];
         out.trk_ev[g] = k;
     }
+}
+
+// Slot i of a batch of pool events (evs[0..E), result slots [toff[e],
+// toff[e+1]) for event e): map[i] = the pool track it reads.
+__global__ void k_track_map(const uint32_t *__restrict__ evs, const uint32_t *__restrict__ toff, uint32_t n_events,
+                            const uint32_t *__restrict__ pool_trk_off, uint32_t *__restrict__ map) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= toff[n_events]) return;
+    // last batch event e with toff[e] <= i
+    uint32_t lo = 0, n = n_events + 1;
+    while (n > 0) {
+        const uint32_t half = n >> 1;
+        if (toff[lo + half] <= i) { lo += half + 1; n -= half + 1; } else { n = half; }
+    }
+    const uint32_t e = lo - 1;
+    map[i] = pool_trk_off[evs[e]] + (i - toff[e]);
 }
 
 __global__ void k_track_event(const uint32_t *__restrict__ trk_off, uint32_t n_events, uint32_t n_tracks,
@@ -1461,8 +1485,8 @@ hipError_t launch_nw_wpb(const DevBatch &b, const KParams *P, int mode, const Ex
         if (grid == 0) grid = 1;
         hipLaunchKernelGGL((k_persistent<NW, NS, WPB, H16>), dim3(grid), block, 0, s, b, P,
                            (uint32_t)cfg.items_per_grab);
-    } else {   // batched: one launch, one wavefront per track, XCD-ordered
-        const uint32_t need = (b.n_tracks + WPB - 1) / WPB;
+    } else {   // batched: one launch, one wavefront per track (or per mapped slot), XCD-ordered
+        const uint32_t need = ((b.trk_map ? b.n_map : b.n_tracks) + WPB - 1) / WPB;
         const uint32_t grid = (need + NXCD - 1) / NXCD * NXCD;
         if (grid) hipLaunchKernelGGL((k_grid<NW, NS, WPB, false, H16>), dim3(grid), block, 0, s, b, P);
     }
@@ -1594,6 +1618,14 @@ hipError_t launch_count(const DevBatch &b, const KParams *P, int n_hits_window, 
 hipError_t launch_gather(const GatherDesc *desc, uint32_t n_events, const BatchIn &out, hipStream_t s) {
     if (n_events == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather, dim3(n_events, GATHER_CHUNKS), dim3(256), 0, s, desc, n_events, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_track_map(const uint32_t *evs, const uint32_t *toff, uint32_t n_events, uint32_t n_slots,
+                            const uint32_t *pool_trk_off, uint32_t *map, hipStream_t s) {
+    if (n_slots == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_track_map, dim3((n_slots + 255) / 256), dim3(256), 0, s, evs, toff, n_events, pool_trk_off,
+                       map);
     return hipGetLastError();
 }
 

@@ -7,11 +7,16 @@
 // free (continuous batching: requests arriving while others run on the GPU
 // join the next batch), and runs upload -> hot path -> digest -> download on
 // that slot's stream, so copies and kernels of consecutive batches overlap.
-// A request completes when its results are in host memory.  Batches are
-// assembled on the device: the host writes one 24-byte descriptor per event,
-// and a gather kernel reads the events' blobs from pinned host memory over
-// the host link straight into the batch's device arrays, so no host thread
-// copies event data on the request path.
+// A request completes when its results (or, with results_on_device, their
+// digests) are in host memory.  Two kinds of pool:
+//  - in pinned host memory: batches are assembled on the device, the host
+//    writing one 24-byte descriptor per event and a gather kernel reading the
+//    events' blobs over the host link straight into the batch's arrays, so
+//    no host thread copies event data on the request path;
+//  - in device memory (pool_on_device, as earlier GPU stages leave events):
+//    the pool stays resident as one batch, and a batch is a list of pool
+//    events whose result slots a small kernel maps to pool tracks; the hot
+//    path reads the pool in place.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -56,10 +61,13 @@ struct Pool {
     std::vector<uint32_t> nh, nt;  // hits, tracks per event
 };
 
-// Byte layout of one batch region (device ring and pinned staging share it).
+// Byte layout of one batch region in the device ring.  Host pool: the
+// gathered events and the outputs.  Device pool (ref): the event list and
+// slot offsets, the slot map, and the outputs.
 struct BatchLayout {
     size_t desc, hit_off, hx, hz, hd, trk_off, trk_ev, tx, ty, ttx, tty, tqop, uni, in_bytes;
     size_t dig, found, nhits, hit_idx, fl, out_bytes, total;
+    size_t evs, toff, map;   // device pool only
     uint32_t E, H, T;
 };
 
@@ -77,6 +85,24 @@ BatchLayout batch_layout(uint32_t E, uint32_t H, uint32_t T) {
     L.uni = put(E);
     L.in_bytes = o;
     // outputs: one contiguous block so a single copy brings them back
+    const size_t ob = o;
+    L.dig = put((size_t)E * 8);
+    L.found = put(T); L.nhits = put(T); L.hit_idx = put((size_t)T * 48);
+    L.fl = put((size_t)T * 28);
+    L.out_bytes = o - ob;
+    L.total = o;
+    return L;
+}
+
+BatchLayout ref_layout(uint32_t E, uint32_t T) {
+    BatchLayout L{};
+    L.E = E; L.T = T;
+    size_t o = 0;
+    auto put = [&](size_t n) { size_t at = o; o += a256(n ? n : 1); return at; };
+    L.evs = put((size_t)(2 * E + 1) * 4);   // event list, then the E + 1 slot offsets
+    L.toff = L.evs + (size_t)E * 4;
+    L.map = put((size_t)T * 4);
+    L.in_bytes = o;
     const size_t ob = o;
     L.dig = put((size_t)E * 8);
     L.found = put(T); L.nhits = put(T); L.hit_idx = put((size_t)T * 48);
@@ -136,7 +162,8 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
     if (cfg.max_batch_events == 0) cfg.max_batch_events = 1024;
     if (cfg.n_slots == 0) cfg.n_slots = 4;
     if (cfg.device_budget_bytes == 0) cfg.device_budget_bytes = size_t(8) << 30;
-    if (cfg.n_slots > 16 || cfg.n_pack_threads > 64 || cfg.max_batch_events > (1u << 20) || cfg.pool_on_device > 1)
+    if (cfg.n_slots > 16 || cfg.n_pack_threads > 64 || cfg.max_batch_events > (1u << 20) || cfg.pool_on_device > 1 ||
+        cfg.results_on_device > 1)
         return lfapi::ctx_fail(ctx, LF_ERR_INVALID, "lf_serve_run: configuration out of range");
     const uint32_t PE = pool_b->n_events;
     for (uint32_t i = 0; i < n_requests; ++i) {
@@ -145,7 +172,12 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
             return lfapi::ctx_fail(ctx, LF_ERR_INVALID, "lf_serve_run: arrival times must be >= 0 and non-decreasing");
     }
 
-    // ---- pool blobs in pinned memory (the events as delivered to the host) ----
+    const bool dev_pool = cfg.pool_on_device != 0;
+    // the layout of a batch region in the ring
+    auto layout_of = [&](uint32_t E, uint32_t H, uint32_t T) {
+        return dev_pool ? ref_layout(E, T) : batch_layout(E, H, T);
+    };
+    // ---- pool sizes; pinned blobs for a host pool (the events as delivered to the host) ----
     Pool pool;
     pool.off.resize(PE);
     pool.nh.resize(PE);
@@ -155,11 +187,11 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
         pool.nh[e] = pool_b->hit_off[24 * (size_t)e + 24] - pool_b->hit_off[24 * (size_t)e];
         pool.nt[e] = pool_b->trk_off[e + 1] - pool_b->trk_off[e];
         pool.off[e] = pbytes;
-        pbytes += a256(25 * 4 + (size_t)pool.nh[e] * 12 + (size_t)pool.nt[e] * 20);
+        if (!dev_pool) pbytes += a256(25 * 4 + (size_t)pool.nh[e] * 12 + (size_t)pool.nt[e] * 20);
     }
     size_t max_event_bytes = 0;
     for (uint32_t e = 0; e < PE; ++e) {
-        const BatchLayout one = batch_layout(1, pool.nh[e], pool.nt[e]);
+        const BatchLayout one = layout_of(1, pool.nh[e], pool.nt[e]);
         max_event_bytes = std::max(max_event_bytes, one.total);
     }
     if (max_event_bytes > cfg.device_budget_bytes)
@@ -167,7 +199,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
 
     std::vector<Slot> slots(cfg.n_slots);
     void *ring_mem = nullptr;
-    char *pool_hbm = nullptr;   // pool_on_device: the pool's copy in device memory
+    char *pool_hbm = nullptr;   // pool_on_device: the pool, resident as one batch in device memory
     hipError_t err = hipHostMalloc(reinterpret_cast<void **>(&pool.blob), pbytes ? pbytes : 1, hipHostMallocDefault);
     if (err != hipSuccess) return lfapi::ctx_fail(ctx, LF_ERR_NOMEM, "lf_serve_run: pinned pool allocation failed");
     pool.bytes = pbytes;
@@ -183,7 +215,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
         if (pool_hbm) (void)hipFree(pool_hbm);
         if (pool.blob) (void)hipHostFree(pool.blob);
     };
-    for (uint32_t e = 0; e < PE; ++e) {
+    for (uint32_t e = 0; e < (dev_pool ? 0u : PE); ++e) {
         char *p = pool.blob + pool.off[e];
         const uint32_t h0 = pool_b->hit_off[24 * (size_t)e], t0 = pool_b->trk_off[e];
         uint32_t *ho = reinterpret_cast<uint32_t *>(p);
@@ -222,7 +254,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
         cleanup();
         return lfapi::ctx_fail(ctx, LF_ERR_INVALID, "lf_serve_run: max_batch_events allows batches over 2^30 hits or 2^26 tracks");
     }
-    const BatchLayout biggest = batch_layout(cfg.max_batch_events, (uint32_t)big_h, (uint32_t)big_t);
+    const BatchLayout biggest = layout_of(cfg.max_batch_events, (uint32_t)big_h, (uint32_t)big_t);
     for (auto &s : slots) {
         err = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
         if (err == hipSuccess) err = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
@@ -237,17 +269,51 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
         s.stage_cap = cfg.max_batch_events;
         s.out_cap = biggest.out_bytes;
     }
-    // where the gather kernel reads the pool: the pinned blob over the host
-    // link, or (pool_on_device) its copy in device memory
+    // A host pool: the gather kernel reads the pinned blobs over the host
+    // link.  A device pool: copied once (before the clock) as one resident
+    // batch, with each track's event and each event's uniform flag.
     char *pool_dev = nullptr;
-    if (cfg.pool_on_device) {
-        err = hipMalloc(reinterpret_cast<void **>(&pool_hbm), pbytes ? pbytes : 1);
+    lfk::DevBatch pool_d{};
+    const uint32_t PH = pool_b->hit_off[24 * (size_t)PE], PT = pool_b->trk_off[PE];
+    if (dev_pool) {
+        size_t o = 0;
+        auto put = [&](size_t n) { size_t at = o; o += a256(n ? n : 1); return at; };
+        const size_t o_ho = put(((size_t)PE * 24 + 1) * 4), o_hx = put((size_t)PH * 4), o_hz = put((size_t)PH * 4),
+                     o_hd = put((size_t)PH * 4), o_to = put(((size_t)PE + 1) * 4), o_te = put((size_t)PT * 4),
+                     o_tr = put((size_t)PT * 20), o_uni = put(PE);
+        err = hipMalloc(reinterpret_cast<void **>(&pool_hbm), o);
         if (err != hipSuccess) {
             cleanup();
             return lfapi::ctx_fail(ctx, LF_ERR_NOMEM, "lf_serve_run: device pool allocation failed");
         }
-        err = hipMemcpy(pool_hbm, pool.blob, pbytes, hipMemcpyHostToDevice);
-        pool_dev = pool_hbm;
+        char *b = pool_hbm;
+        struct { size_t off; const void *src; size_t n; } cp[] = {
+            {o_ho, pool_b->hit_off, ((size_t)PE * 24 + 1) * 4}, {o_hx, pool_b->hit_x, (size_t)PH * 4},
+            {o_hz, pool_b->hit_z, (size_t)PH * 4}, {o_hd, pool_b->hit_dxdy, (size_t)PH * 4},
+            {o_to, pool_b->trk_off, ((size_t)PE + 1) * 4}, {o_tr, pool_b->trk_x, (size_t)PT * 4},
+            {o_tr + (size_t)PT * 4, pool_b->trk_y, (size_t)PT * 4}, {o_tr + (size_t)PT * 8, pool_b->trk_tx, (size_t)PT * 4},
+            {o_tr + (size_t)PT * 12, pool_b->trk_ty, (size_t)PT * 4},
+            {o_tr + (size_t)PT * 16, pool_b->trk_qop, (size_t)PT * 4}};
+        for (auto &x : cp) {
+            if (err == hipSuccess && x.n) err = hipMemcpy(b + x.off, x.src, x.n, hipMemcpyHostToDevice);
+        }
+        pool_d.hit_off = reinterpret_cast<const uint32_t *>(b + o_ho);
+        pool_d.hx = reinterpret_cast<const float *>(b + o_hx);
+        pool_d.hz = reinterpret_cast<const float *>(b + o_hz);
+        pool_d.hd = reinterpret_cast<const float *>(b + o_hd);
+        pool_d.trk_off = reinterpret_cast<const uint32_t *>(b + o_to);
+        pool_d.trk_ev = reinterpret_cast<const uint32_t *>(b + o_te);
+        pool_d.tx_ = reinterpret_cast<const float *>(b + o_tr);
+        pool_d.ty_ = pool_d.tx_ + PT;
+        pool_d.ttx = pool_d.tx_ + 2 * (size_t)PT;
+        pool_d.tty = pool_d.tx_ + 3 * (size_t)PT;
+        pool_d.tqop = pool_d.tx_ + 4 * (size_t)PT;
+        pool_d.uni = reinterpret_cast<const uint8_t *>(b + o_uni);
+        pool_d.n_events = PE;
+        pool_d.n_tracks = PT;
+        if (err == hipSuccess) err = lfk::launch_track_event(pool_d, slots[0].stream);
+        if (err == hipSuccess) err = lfk::launch_event_uniform(pool_d, reinterpret_cast<uint8_t *>(b + o_uni), slots[0].stream);
+        if (err == hipSuccess) err = hipStreamSynchronize(slots[0].stream);
     } else {
         err = hipHostGetDevicePointer(reinterpret_cast<void **>(&pool_dev), pool.blob, 0);
     }
@@ -267,6 +333,41 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
                             size_t at) -> hipError_t {
         const uint32_t E = (uint32_t)evs.size();
         if (E > s.stage_cap) return hipErrorInvalidValue;   // descriptors must fit the slot
+        const size_t down = cfg.results_on_device ? (size_t)E * 8 : lay.out_bytes;   // the digests lead the outputs
+        char *dr = static_cast<char *>(ring_mem) + at;
+        if (dev_pool) {
+            // the event list and the slot offsets, the slot map, then the hot
+            // path reading the resident pool
+            uint32_t *ev_h = reinterpret_cast<uint32_t *>(s.stage), *to_h = ev_h + E;
+            uint32_t T = 0;
+            for (uint32_t k = 0; k < E; ++k) {
+                ev_h[k] = evs[k];
+                to_h[k] = T;
+                T += pool.nt[evs[k]];
+            }
+            to_h[E] = T;
+            const uint32_t *ev_d = reinterpret_cast<const uint32_t *>(dr + lay.evs);
+            const uint32_t *to_d = reinterpret_cast<const uint32_t *>(dr + lay.toff);
+            uint32_t *map_d = reinterpret_cast<uint32_t *>(dr + lay.map);
+            lfk::DevBatch d = pool_d;
+            d.trk_map = map_d;
+            d.n_map = T;
+            d.found = reinterpret_cast<uint8_t *>(dr + lay.found);
+            d.nhits = reinterpret_cast<uint8_t *>(dr + lay.nhits);
+            d.hit_idx = reinterpret_cast<int32_t *>(dr + lay.hit_idx);
+            float *fl = reinterpret_cast<float *>(dr + lay.fl);
+            d.a = fl; d.b = fl + T; d.c = fl + 2 * (size_t)T; d.y0 = fl + 3 * (size_t)T;
+            d.ty = fl + 4 * (size_t)T; d.qop = fl + 5 * (size_t)T; d.Q = fl + 6 * (size_t)T;
+            hipError_t e = hipMemcpyAsync(dr + lay.evs, s.stage, (size_t)(2 * E + 1) * 4, hipMemcpyHostToDevice,
+                                          s.stream);
+            if (e == hipSuccess) e = lfk::launch_track_map(ev_d, to_d, E, T, pool_d.trk_off, map_d, s.stream);
+            if (e == hipSuccess && T) e = lfk::launch_find(d, P, nhw, n_sides, 1, exec, nullptr, s.stream);
+            if (e == hipSuccess)
+                e = lfk::launch_digest(d, to_d, E, reinterpret_cast<unsigned long long *>(dr + lay.dig), s.stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(s.out, dr + lay.dig, down, hipMemcpyDeviceToHost, s.stream);
+            if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
+            return e;
+        }
         uint32_t H = 0, T = 0;
         for (uint32_t k = 0; k < E; ++k) {
             const uint32_t ev = evs[k];
@@ -275,7 +376,6 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
             H += pool.nh[ev];
             T += pool.nt[ev];
         }
-        char *dr = static_cast<char *>(ring_mem) + at;
         lfk::BatchIn in{};
         in.hit_off = reinterpret_cast<uint32_t *>(dr + lay.hit_off);
         in.hx = reinterpret_cast<float *>(dr + lay.hx);
@@ -319,7 +419,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
         if (e == hipSuccess) e = lfk::launch_find(d, P, nhw, n_sides, 1, exec, nullptr, s.stream);
         if (e == hipSuccess)
             e = lfk::launch_digest(d, d.trk_off, E, reinterpret_cast<unsigned long long *>(dr + lay.dig), s.stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(s.out, dr + lay.dig, lay.out_bytes, hipMemcpyDeviceToHost, s.stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(s.out, dr + lay.dig, down, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
         return e;
     };
@@ -329,8 +429,8 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
         std::vector<uint32_t> evs;
         uint64_t H = 0, T = 0;
         for (uint32_t e = 0; e < PE && evs.size() < std::min<uint32_t>(16, cfg.max_batch_events); ++e) {
-            const BatchLayout trial = batch_layout((uint32_t)evs.size() + 1, (uint32_t)(H + pool.nh[e]),
-                                                   (uint32_t)(T + pool.nt[e]));
+            const BatchLayout trial = layout_of((uint32_t)evs.size() + 1, (uint32_t)(H + pool.nh[e]),
+                                                (uint32_t)(T + pool.nt[e]));
             if (trial.total > ring.cap || trial.out_bytes > slots[0].out_cap)
                 break;
             evs.push_back(e);
@@ -338,7 +438,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
             T += pool.nt[e];
         }
         if (!evs.empty()) {
-            const BatchLayout lay = batch_layout((uint32_t)evs.size(), (uint32_t)H, (uint32_t)T);
+            const BatchLayout lay = layout_of((uint32_t)evs.size(), (uint32_t)H, (uint32_t)T);
             for (auto &s : slots) {
                 hipError_t e = launch_batch(s, evs, lay, 0);
                 if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
@@ -407,7 +507,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
                 BatchLayout lay{};
                 while (E < queue.size() && E < cfg.max_batch_events) {
                     const uint32_t ev = req_event[queue[E]];
-                    const BatchLayout trial = batch_layout(E + 1, (uint32_t)(H + pool.nh[ev]), (uint32_t)(T + pool.nt[ev]));
+                    const BatchLayout trial = layout_of(E + 1, (uint32_t)(H + pool.nh[ev]), (uint32_t)(T + pool.nt[ev]));
                     if (trial.out_bytes > s.out_cap) break;
                     if (ring.used + trial.total > ring.cap) break;   // admission: the budget is full
                     H += pool.nh[ev];
@@ -433,11 +533,14 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
                     inflight.push_back((uint32_t)free_slot);
                     ++n_batches;
                     batched_events += E;
-                    if (!cfg.pool_on_device)
+                    if (dev_pool) {
+                        bytes_in += (uint64_t)(2 * E + 1) * 4;   // event list and slot offsets
+                    } else {
                         for (uint32_t k = 0; k < E; ++k)
                             bytes_in += 25 * 4 + (uint64_t)pool.nh[evs[k]] * 12 + (uint64_t)pool.nt[evs[k]] * 20;
-                    bytes_in += (uint64_t)E * sizeof(lfk::GatherDesc);
-                    bytes_out += lay.out_bytes;
+                        bytes_in += (uint64_t)E * sizeof(lfk::GatherDesc);
+                    }
+                    bytes_out += cfg.results_on_device ? (uint64_t)E * 8 : lay.out_bytes;
                     progress = true;
                 }
             }

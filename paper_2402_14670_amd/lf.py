@@ -79,6 +79,7 @@ class lf_serve_config(ctypes.Structure):
     _fields_ = [("max_batch_events", ctypes.c_uint32), ("min_batch_events", ctypes.c_uint32),
                 ("max_wait_us", ctypes.c_uint32), ("n_slots", ctypes.c_uint32),
                 ("n_pack_threads", ctypes.c_uint32), ("pool_on_device", ctypes.c_uint32),
+                ("results_on_device", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("device_budget_bytes", ctypes.c_size_t)]
 
 

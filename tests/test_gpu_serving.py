@@ -41,8 +41,11 @@ def _stream(n_pool, n, rate, seed=40):
     ({"min_batch_events": 64, "max_wait_us": 2000}, 50000.0),
     ({"pool_on_device": 1}, 20000.0),
     ({"pool_on_device": 1, "max_batch_events": 1024, "n_slots": 4}, None),
+    ({"pool_on_device": 1, "n_slots": 1, "max_batch_events": 1}, 5000.0),
+    ({"pool_on_device": 1, "results_on_device": 1, "n_slots": 8, "max_batch_events": 64}, None),
+    ({"results_on_device": 1}, 20000.0),
 ], ids=["poisson", "saturated", "one-by-one", "small-batches", "wait-to-fill", "device-pool-poisson",
-        "device-pool-saturated"])
+        "device-pool-saturated", "device-pool-one-by-one", "device-pool-results-on-device", "results-on-device"])
 def test_results_same_alone_and_in_the_mix(pool, cfg, rate):
     from paper_2402_14670_amd import lf
     ev, ref = pool
@@ -63,8 +66,14 @@ def test_results_same_alone_and_in_the_mix(pool, cfg, rate):
     nh = np.diff(ev.hit_off[::24].astype(np.int64))[req]
     nt = np.diff(ev.trk_off.astype(np.int64))[req]
     blobs = int((100 + 12 * nh + 20 * nt).sum())
-    assert st["bytes_in"] == 24 * len(req) + (0 if cfg.get("pool_on_device") else blobs)
-    assert st["bytes_out"] >= 8 * len(req) + 78 * int(nt.sum())
+    if cfg.get("pool_on_device"):
+        assert st["bytes_in"] == 8 * len(req) + 4 * st["n_batches"]   # event lists and slot offsets
+    else:
+        assert st["bytes_in"] == 24 * len(req) + blobs
+    if cfg.get("results_on_device"):
+        assert st["bytes_out"] == 8 * len(req)
+    else:
+        assert st["bytes_out"] >= 8 * len(req) + 78 * int(nt.sum())
 
 
 def test_backpressure_under_small_budget(pool):
