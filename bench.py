@@ -192,7 +192,7 @@ def _serve_runs(lf, ctx, ev, ref, req, cfg, base_rate, fracs, rng, label):
             "results_equal_batched": ok}
 
 
-SERVE_DEVICE_CFG = {"max_batch_events": 1024, "n_slots": 2, "device_budget_bytes": 8 << 30, "pool_on_device": 1}
+SERVE_DEVICE_CFG = {"max_batch_events": 1024, "n_slots": 4, "device_budget_bytes": 8 << 30, "pool_on_device": 1}
 SERVE_HOST_CFG = {"max_batch_events": 256, "n_slots": 2, "device_budget_bytes": 8 << 30}
 
 
