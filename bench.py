@@ -192,7 +192,16 @@ def _serve_runs(lf, ctx, ev, ref, req, cfg, base_rate, fracs, rng, label):
             "results_equal_batched": ok}
 
 
+# Device pool, results to host memory: four slots, a batch as soon as a slot
+# is free.  The downloads (16.9 kB per nominal event) run as copy kernels on
+# the GPU beside the hot path; the rate they leave to it varies from run to
+# run, which no slot count or batching policy tried here removes.
 SERVE_DEVICE_CFG = {"max_batch_events": 1024, "n_slots": 4, "device_budget_bytes": 8 << 30, "pool_on_device": 1}
+# Device pool, results kept on the device: four slots, and a batch waits for
+# 384 events or until its oldest event has waited 150 us, which keeps
+# batches large enough to run near the batched rate at moderate load.
+SERVE_KEEP_CFG = {"max_batch_events": 1024, "n_slots": 4, "min_batch_events": 384, "max_wait_us": 150,
+                  "device_budget_bytes": 8 << 30, "pool_on_device": 1, "results_on_device": 1}
 SERVE_HOST_CFG = {"max_batch_events": 256, "n_slots": 2, "device_budget_bytes": 8 << 30}
 
 
@@ -212,7 +221,7 @@ def serving(lf, ctx, ev, batched_out, n_requests, batched_eps, seed=40):
     req = rng.integers(0, ev.n_events, size=n_requests).astype(np.uint32)
     fr = (0.5, 0.8, 0.95)
     dev = _serve_runs(lf, ctx, ev, ref, req, SERVE_DEVICE_CFG, batched_eps, fr, rng, "device pool")
-    dev_keep = _serve_runs(lf, ctx, ev, ref, req, dict(SERVE_DEVICE_CFG, results_on_device=1), batched_eps, fr, rng,
+    dev_keep = _serve_runs(lf, ctx, ev, ref, req, SERVE_KEEP_CFG, batched_eps, fr, rng,
                            "device pool, results on device")
     host = _serve_runs(lf, ctx, ev, ref, req, SERVE_HOST_CFG, None, fr, rng, "host pool")
     peak = pinned_copy_peak()
@@ -647,11 +656,13 @@ def main():
                      "hbm": {"algorithmic_bytes": nbytes, "achieved_GBs": round(nbytes / (ms * 1e-3) / 1e9, 1),
                              "peak_GBs": HBM_PEAK_GBS,
                              "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}},
-        "latency_ms": ({"p50": serve["device_pool"]["rates"][1]["p50_ms"],
-                        "p99": serve["device_pool"]["rates"][1]["p99_ms"],
-                        "p999": serve["device_pool"]["rates"][1]["p999_ms"],
-                        "at": "serving from a device-resident pool at 80% of the batched throughput, "
-                              "results to host memory"}
+        "latency_ms": ({"p50": serve["device_pool_results_on_device"]["rates"][1]["p50_ms"],
+                        "p99": serve["device_pool_results_on_device"]["rates"][1]["p99_ms"],
+                        "p999": serve["device_pool_results_on_device"]["rates"][1]["p999_ms"],
+                        "at": "serving from a device-resident pool at 80% of the batched throughput, results "
+                              "kept in device memory for the next GPU stage (digests to the host)",
+                        "results_to_host": {k: serve["device_pool"]["rates"][1][k + "_ms"]
+                                            for k in ("p50", "p99", "p999")}}
                        if serve else None),
         "serving": serve,
         "end_to_end": e2e,

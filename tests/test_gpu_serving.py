@@ -44,8 +44,11 @@ def _stream(n_pool, n, rate, seed=40):
     ({"pool_on_device": 1, "n_slots": 1, "max_batch_events": 1}, 5000.0),
     ({"pool_on_device": 1, "results_on_device": 1, "n_slots": 8, "max_batch_events": 64}, None),
     ({"results_on_device": 1}, 20000.0),
+    ({"pool_on_device": 1, "results_on_device": 1, "n_slots": 4, "min_batch_events": 384, "max_wait_us": 150},
+     2.0e6),
 ], ids=["poisson", "saturated", "one-by-one", "small-batches", "wait-to-fill", "device-pool-poisson",
-        "device-pool-saturated", "device-pool-one-by-one", "device-pool-results-on-device", "results-on-device"])
+        "device-pool-saturated", "device-pool-one-by-one", "device-pool-results-on-device", "results-on-device",
+        "device-pool-wait-to-fill-results-on-device"])
 def test_results_same_alone_and_in_the_mix(pool, cfg, rate):
     from paper_2402_14670_amd import lf
     ev, ref = pool
