@@ -193,7 +193,7 @@ def _serve_runs(lf, ctx, ev, ref, req, cfg, base_rate, fracs, rng, label):
 
 
 # Device pool, results to host memory: four slots, a batch as soon as a slot
-# is free.  The downloads (16.9 kB per nominal event) run as copy kernels on
+# is free.  The downloads (15.6 kB per nominal event) run as copy kernels on
 # the GPU beside the hot path; the rate they leave to it varies from run to
 # run, which no slot count or batching policy tried here removes.
 SERVE_DEVICE_CFG = {"max_batch_events": 1024, "n_slots": 4, "device_budget_bytes": 8 << 30, "pool_on_device": 1}
