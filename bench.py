@@ -70,8 +70,8 @@ BYTES_PER_TRACK_OUT = 78
 # HBM traffic of the batched kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (per launch, scaled by the counters' reading of a known-size copy), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha256": "be7a13f5b79a60aa0dc7a69c1c4e6410e229f9695e53fd5e2e0b5c699c6d50be",
-           "bytes_per_launch": 51952026}
+TRAFFIC = {"kernel_sha256": "fda28abee919cd44b00ee5e2f314fbf33171db7cd7698f2c64bfa8d1cd896314",
+           "bytes_per_launch": 51938157}
 WORKLOADS = {
     "nominal": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",
     "uneven": "uneven: 20000 events, Poisson(7.6) x 50 particles, 0-13k hits and 0-600 tracks/event",

@@ -4,8 +4,10 @@ Times every candidate configuration of the batched and persistent launches
 on a resident batch (HIP events on the given stream), applies the fastest
 with lf_set_exec and returns the whole table.  Candidates: wavefronts per
 workgroup (1, 2, 4); for the persistent launch also tracks per queue claim
-(1, 2, 4, 8, 16) and workgroups per compute unit (the occupancy limit, or
-2, 4, 8).  The window capacity of the kernels (LDS staging of 32 or 64 hits
+(1, 2, 4, 8, 16) and the grid: the occupancy limit the runtime reports, or
+16, 20, 24 or 28 wavefronts per compute unit (fewer resident wavefronts can
+be faster: the runtime's limit need not be what the hardware places, and
+the track loop's issue rate stops growing before it).  The window capacity of the kernels (LDS staging of 32 or 64 hits
 per layer) follows n_hits_window and is not a free choice.
 """
 from __future__ import annotations
@@ -20,7 +22,8 @@ def candidates(modes=("batched", "persistent")):
     for mode in modes:
         for wpb in (1, 2, 4):
             if mode == "persistent":
-                for items, bpc in itertools.product((1, 2, 4, 8, 16), (0, 2, 4, 8)):
+                grids = (0,) + tuple(w // wpb for w in (16, 20, 24, 28))
+                for items, bpc in itertools.product((1, 2, 4, 8, 16), grids):
                     out.append(dict(mode=mode, waves_per_block=wpb, items_per_grab=items, blocks_per_cu=bpc))
             else:
                 out.append(dict(mode=mode, waves_per_block=wpb, items_per_grab=1, blocks_per_cu=0))

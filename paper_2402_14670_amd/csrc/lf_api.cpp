@@ -168,7 +168,7 @@ Layout layout(uint32_t E, uint32_t H, uint32_t T) {
     L.found = put(T); L.nhits = put(T); L.hit_idx = put((size_t)T * 48);
     L.a = put((size_t)T * 4); L.b = put((size_t)T * 4); L.c = put((size_t)T * 4);
     L.y0 = put((size_t)T * 4); L.ty_o = put((size_t)T * 4); L.qop = put((size_t)T * 4); L.Q = put((size_t)T * 4);
-    L.counter = put(1024);
+    L.counter = put(4 * (size_t)lfk::QUEUE_WORDS);
     L.stats = put(32 * 8);
     L.total = o;
     return L;
@@ -379,7 +379,7 @@ int lf_upload_events(lf_ctx *c, const lf_batch *b, void *hip_stream, uint64_t *b
         e = hipMemcpyAsync(base + x.off, x.src, x.n, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) break;
     }
-    if (e == hipSuccess) e = hipMemsetAsync(d.counter, 0, 1024, s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.counter, 0, 4 * (size_t)lfk::QUEUE_WORDS, s);
     if (e == hipSuccess) e = lfk::launch_track_event(d, s);
     if (e == hipSuccess) e = lfk::launch_event_uniform(d, reinterpret_cast<uint8_t *>(base + L.uni), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -445,7 +445,7 @@ int lf_find_tracks_noalloc(lf_ctx *c, const lf_batch *in, uint32_t n_hits, uint3
     d.n_events = E;
     d.n_tracks = n_tracks;
     hipStream_t s = pick(c, hip_stream);
-    hipError_t e = lfk::launch_zero_words(d.counter, 256, s);
+    hipError_t e = lfk::launch_zero_words(d.counter, lfk::QUEUE_WORDS, s);
     if (e == hipSuccess) e = lfk::launch_track_event(d, s);
     if (e == hipSuccess) e = lfk::launch_event_uniform(d, reinterpret_cast<uint8_t *>(fx + lfk::FIXED_UNI_OFF), s);
     if (e == hipSuccess)

@@ -44,7 +44,7 @@ struct DevBatch {
     uint8_t *found, *nhits;    // [T]
     int32_t *hit_idx;          // [12*T]
     float *a, *b, *c, *y0, *ty, *qop, *Q;  // [T]
-    uint32_t *counter;         // [256] per-XCD queue heads and exited-wave count (batched mode), zero between launches
+    uint32_t *counter;         // [QUEUE_WORDS] persistent-mode queue heads and exited-wave count, zero between launches
     unsigned long long *stats; // [32] work counters (counting launch only)
     uint32_t n_events, n_tracks;
     // batched mode over slots of a resident pool: result slot t (< n_map)
@@ -52,6 +52,13 @@ struct DevBatch {
     const uint32_t *trk_map;
     uint32_t n_map;
 };
+
+// Work queues of the persistent mode: QUEUE_SUB per XCD (8 XCDs), heads
+// QUEUE_STRIDE words (256 bytes) apart, then the exited-wave count.
+constexpr uint32_t QUEUE_SUB = 16;
+constexpr uint32_t QUEUE_N = 8 * QUEUE_SUB;
+constexpr uint32_t QUEUE_STRIDE = 64;
+constexpr uint32_t QUEUE_WORDS = QUEUE_STRIDE * (QUEUE_N + 1);
 
 struct ExecCfg {
     int waves_per_block;
@@ -112,8 +119,8 @@ int persistent_blocks_per_cu(int n_hits_window, int n_sides, int waves_per_block
 // the per-event uniform flags and the event of each track.
 constexpr uint32_t FIXED_MAX_EVENTS = 1u << 20;
 constexpr uint32_t FIXED_MAX_TRACKS = 1u << 22;
-constexpr size_t FIXED_QUEUE_OFF = 0;                       // 256 x u32
-constexpr size_t FIXED_UNI_OFF = 1024;                      // FIXED_MAX_EVENTS x u8
+constexpr size_t FIXED_QUEUE_OFF = 0;                       // QUEUE_WORDS x u32
+constexpr size_t FIXED_UNI_OFF = 4 * (size_t)QUEUE_WORDS;   // FIXED_MAX_EVENTS x u8
 constexpr size_t FIXED_TRK_EV_OFF = FIXED_UNI_OFF + FIXED_MAX_EVENTS;   // FIXED_MAX_TRACKS x u32
 constexpr size_t FIXED_BYTES = FIXED_TRK_EV_OFF + 4 * (size_t)FIXED_MAX_TRACKS;
 // Device address of the current device's copy of the fixed scratch, looked

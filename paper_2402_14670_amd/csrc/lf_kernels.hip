@@ -1322,13 +1322,24 @@ __global__ __launch_bounds__(WPB * WAVE) __attribute__((amdgpu_waves_per_eu(NS =
     }
 }
 
-// Persistent: one work queue per XCD over a contiguous eighth of the
-// tracks.  Waves claim `items` consecutive tracks at a time from their own
-// XCD's queue, then help the other queues in turn; a wave exits once every
-// queue is drained.  Heads sit 64 bytes apart (q[16 k]); q[16 NXCD] counts
-// exited waves, and the last wave out puts every word back to zero, so the
-// next launch on the batch starts clean without a reset kernel (or a memset
-// node in a captured graph).
+// Persistent: QUEUE_N work queues, QUEUE_SUB per XCD.  XCD x owns a
+// contiguous eighth of the tracks, cut into chunks of `items` tracks; chunk j
+// belongs to the XCD's queue j % QUEUE_SUB, whose k-th claim is chunk
+// k QUEUE_SUB + j % QUEUE_SUB, so the XCD's waves move through its eighth
+// together (its events stay in its L2) while their atomics spread over
+// QUEUE_SUB words: device-scope atomics on one word are applied one after
+// another, and one word per XCD held one-track claims to ~8 per us.  A wave
+// claims its next chunk before it runs the current one, so the claim's round
+// trip overlaps the track's first loads.  A wave whose queue is drained reads
+// every head in one vector load (two words per lane), moves to a queue with
+// chunks left -- its own XCD's first -- and exits once all are drained.
+// Heads sit QUEUE_STRIDE words apart; word QUEUE_STRIDE QUEUE_N counts exited
+// waves, and the last wave out puts every word back to zero, so the next
+// launch on the batch starts clean without a reset kernel (or a memset node
+// in a captured graph).
+static_assert(QUEUE_N == 2 * WAVE, "the drained-queue scan reads two heads per lane");
+static_assert(QUEUE_N == NXCD * QUEUE_SUB, "QUEUE_SUB queues per XCD");
+
 template <int NW, int NS, int WPB, bool H16 = false>
 __global__ __launch_bounds__(WPB * WAVE) void k_persistent(DevBatch B, const KParams *__restrict__ P,
                                                             uint32_t items) {
@@ -1336,25 +1347,43 @@ __global__ __launch_bounds__(WPB * WAVE) void k_persistent(DevBatch B, const KPa
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     uint32_t *q = B.counter;
     const uint32_t T = B.n_tracks;
-    uint32_t qi = blockIdx.x % NXCD;
-    for (uint32_t tried = 0; tried < NXCD;) {
-        const uint32_t lo = (uint32_t)(((uint64_t)T * qi) / NXCD);
-        const uint32_t n = (uint32_t)(((uint64_t)T * (qi + 1)) / NXCD) - lo;
+    auto xlo = [&](uint32_t x) { return (uint32_t)(((uint64_t)T * x) / NXCD); };
+    // chunks of queue i
+    auto n_chunks = [&](uint32_t i) -> uint32_t {
+        const uint32_t x = i / QUEUE_SUB, sub = i % QUEUE_SUB;
+        const uint32_t cx = (xlo(x + 1) - xlo(x) + items - 1) / items;
+        return cx > sub ? (cx - sub + QUEUE_SUB - 1) / QUEUE_SUB : 0u;
+    };
+    auto claim = [&](uint32_t i) -> uint32_t {   // lane 0 claims; the value lives in its VGPR
         uint32_t c = 0;
-        if (lane_id() == 0) {
-            // skip the atomic once the queue is seen drained
-            uint32_t *head = &q[16 * qi];
-            c = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (c < n) c = atomicAdd(head, items);
-        }
-        c = __builtin_amdgcn_readfirstlane(c);
-        if (c >= n) {
-            qi = qi + 1 == NXCD ? 0 : qi + 1;
-            ++tried;
+        if (opaque_lane_id() == 0) c = atomicAdd(&q[QUEUE_STRIDE * i], 1u);
+        return c;
+    };
+    // home queue: this block's XCD, waves spread over its QUEUE_SUB queues
+    uint32_t qi = (blockIdx.x % NXCD) * QUEUE_SUB + ((blockIdx.x / NXCD) * WPB + w) % QUEUE_SUB;
+    uint32_t k = __builtin_amdgcn_readfirstlane(claim(qi));
+    for (;;) {
+        if (k >= n_chunks(qi)) {
+            // drained: find a queue with chunks left
+            const uint32_t lane = (uint32_t)opaque_lane_id();
+            const uint32_t h0 = __hip_atomic_load(&q[QUEUE_STRIDE * lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t h1 = __hip_atomic_load(&q[QUEUE_STRIDE * (lane + WAVE)], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t m0 = __ballot(h0 < n_chunks(lane)), m1 = __ballot(h1 < n_chunks(lane + WAVE));
+            const uint32_t xb = (qi / QUEUE_SUB) * QUEUE_SUB;   // own XCD's first queue
+            const uint64_t own = (xb < WAVE ? m0 >> xb : m1 >> (xb - WAVE)) & ((1ull << QUEUE_SUB) - 1);
+            if (own) qi = xb + (uint32_t)__builtin_ctzll(own);
+            else if (m0) qi = (uint32_t)__builtin_ctzll(m0);
+            else if (m1) qi = WAVE + (uint32_t)__builtin_ctzll(m1);
+            else break;
+            k = __builtin_amdgcn_readfirstlane(claim(qi));
             continue;
         }
-        const uint32_t e = c + items < n ? c + items : n;
-        for (uint32_t t = lo + c; t < lo + e; ++t) {
+        const uint32_t next = claim(qi);   // in flight while this chunk runs
+        const uint32_t x = qi / QUEUE_SUB, lo = xlo(x), hi = xlo(x + 1);
+        const uint32_t t0 = lo + (k * QUEUE_SUB + qi % QUEUE_SUB) * items;
+        const uint32_t t1 = t0 + items < hi ? t0 + items : hi;
+        for (uint32_t t = t0; t < t1; ++t) {
             // keep per-track loads inside the loop: hoisting them across tracks
             // costs ~30 VGPRs of loop-carried state and two waves per SIMD
             asm volatile("" ::: "memory");
@@ -1362,14 +1391,19 @@ __global__ __launch_bounds__(WPB * WAVE) void k_persistent(DevBatch B, const KPa
             tr.ln = opaque_lane_id();
             tr.run(t, B.trk_ev[t], t);
         }
+        k = __builtin_amdgcn_readfirstlane(next);
     }
-    if (lane_id() == 0) {
-        const uint32_t waves = gridDim.x * WPB;
+    const uint32_t waves = gridDim.x * WPB;
+    const uint32_t lane = (uint32_t)opaque_lane_id();
+    uint32_t last = 0;
+    if (lane == 0) {
         __threadfence();  // this wave's claims are performed before it counts itself out
-        if (atomicAdd(&q[16 * NXCD], 1u) == waves - 1u) {
-            for (uint32_t k = 0; k < NXCD; ++k) atomicExch(&q[16 * k], 0u);
-            atomicExch(&q[16 * NXCD], 0u);
-        }
+        last = atomicAdd(&q[QUEUE_STRIDE * QUEUE_N], 1u) == waves - 1u ? 1u : 0u;
+    }
+    if (__builtin_amdgcn_readfirstlane(last)) {
+        __hip_atomic_store(&q[QUEUE_STRIDE * lane], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&q[QUEUE_STRIDE * (lane + WAVE)], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) __hip_atomic_store(&q[QUEUE_STRIDE * QUEUE_N], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -1478,7 +1512,7 @@ hipError_t launch_nw_wpb(const DevBatch &b, const KParams *P, int mode, const Ex
             if (nt == 0) continue;
             hipLaunchKernelGGL((k_plain<NW, NS, WPB, H16>), dim3((nt + WPB - 1) / WPB), block, 0, s, b, P, e);
         }
-    } else if (mode == 2) {   // persistent: resident waves, per-XCD work queues
+    } else if (mode == 2) {   // persistent: resident waves, QUEUE_SUB work queues per XCD
         uint32_t grid = (uint32_t)(cfg.blocks_per_cu * cfg.n_cu);
         const uint32_t need = (b.n_tracks + WPB - 1) / WPB;
         if (grid > need) grid = need;
