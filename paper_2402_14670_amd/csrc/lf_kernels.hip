@@ -104,6 +104,23 @@ __device__ __forceinline__ void chain12(const float (&t)[N], float (&s)[N]) {
 // Lane 11 of each row's value, broadcast over the row (row_newbcast:11).
 __device__ __forceinline__ float row_lane11(float v) { return dpp<0x15B, false>(v); }
 
+// Lane k (0..9, a constant after unrolling) of each row's value, broadcast
+// over the row (row_newbcast:k).
+__device__ __forceinline__ float row_bcast_lane(float v, int k) {
+    switch (k) {
+        case 0: return dpp<0x150, false>(v);
+        case 1: return dpp<0x151, false>(v);
+        case 2: return dpp<0x152, false>(v);
+        case 3: return dpp<0x153, false>(v);
+        case 4: return dpp<0x154, false>(v);
+        case 5: return dpp<0x155, false>(v);
+        case 6: return dpp<0x156, false>(v);
+        case 7: return dpp<0x157, false>(v);
+        case 8: return dpp<0x158, false>(v);
+        default: return dpp<0x159, false>(v);
+    }
+}
+
 // The least float above x (NaN and +inf map to themselves, +-0 to the least
 // positive subnormal): for every finite v, v <= x exactly when v < next_up(x).
 __device__ __forceinline__ float next_up(float x) {
@@ -354,6 +371,57 @@ struct Track {
         if constexpr (!XO) return L.wd[sd][uv_index(l)][uni ? 0 : i];
         if ((dvar >> (NL * sd + l)) & 1u) return ld32(B.hd, ebase + (uint32_t)(L.wfirst[sd][l] + i));
         return L.wd[sd][uv_index(l)][0];
+    }
+
+    // The N (<= 10) serial sums of chain12 -- ((+0 + t_0) + t_1) + ... + t_11
+    // over a row's layer lanes 0..11 -- formed by a transpose through LDS
+    // instead: lane (g, j) writes its terms, lane (g, k) reads the 12 terms
+    // of sum k and adds them in layer order, and every lane of the row then
+    // receives each sum (row_newbcast).  The same operations in the same
+    // order as the chain, with 12 additions for all the sums instead of 12
+    // per sum.  The scratch is the per-hit z and stereo-slope area of the
+    // windows, which the fits of a uniform event do not read (they hold each
+    // window's common z and slope in registers): sum slot g N + k is 12
+    // floats at 48 (g N + k) bytes.  Only in builds that stage z per hit.
+    template <int N>
+    __device__ __forceinline__ void row_sums_lds(const float (&t)[N], float (&s)[N], int g, int j) {
+        using W = WaveLds<NW, NS>;
+        static_assert(!W::XO, "needs the per-hit z and slope rows");
+        static_assert(N <= 10 && 4 * N * 12 <= NS * (NL + 6) * W::ZW, "4 N slots of 12 floats");
+        float *base = &L.wz[0][0][0];   // wz, then wd: one run of floats
+        wave_sync();   // the previous use of the scratch has been read
+        if (j < NL) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) base[(g * N + k) * 12 + j] = t[k];
+        }
+        wave_sync();
+        float v = 0.0f;
+        if (j < N) {
+            const float4 *p = reinterpret_cast<const float4 *>(base + (g * N + j) * 12);
+            const float4 q0 = p[0], q1 = p[1], q2 = p[2];
+            v = 0.0f + q0.x;
+            v = v + q0.y; v = v + q0.z; v = v + q0.w;
+            v = v + q1.x; v = v + q1.y; v = v + q1.z; v = v + q1.w;
+            v = v + q2.x; v = v + q2.y; v = v + q2.z; v = v + q2.w;
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) s[k] = row_bcast_lane(v, k);
+    }
+
+    // The serial sums of chain12, the same in every lane of the row: a
+    // uniform event's through LDS (row_sums_lds), otherwise the chain's
+    // lane 11 broadcast over the row.
+    template <int N>
+    __device__ __forceinline__ void row_sums(const float (&t)[N], float (&s)[N], int g, int j) {
+        if constexpr (!WaveLds<NW, NS>::XO) {
+            if (uni) {
+                row_sums_lds(t, s, g, j);
+                return;
+            }
+        }
+        chain12(t, s);
+#pragma unroll
+        for (int k = 0; k < N; ++k) s[k] = row_lane11(s[k]);
     }
 
     // Adds the shader-clock cycles since the previous mark to counter k.
@@ -1141,6 +1209,16 @@ struct Track {
         const bool uvj = j < NL && is_uv(j);
         const float Tj = uvj ? T_uv : P->T_x;
         constexpr int LR = NL - 1;   // the row lane that holds the chained sums
+        // a uniform event: layer j's common z and stereo slope, read once (the
+        // sums then use their LDS rows as scratch)
+        float zj = 0.0f, dj = 1.0f;
+        if constexpr (!WaveLds<NW, NS>::XO) {
+            if (uni && j < NL) {
+                zj = L.wz[0][j][0];
+                if (uvj) dj = L.wd[0][uv_index(j)][0];
+            }
+        }
+        const bool zreg = !WaveLds<NW, NS>::XO && uni;
         while (fitm) {
             int r = -1;
             int rq[4];
@@ -1162,11 +1240,11 @@ struct Track {
             }
             float sv = 0.0f, h = 0.0f, rr = 0.0f, dxy = 1.0f;
             if (pres) {
-                const float zh = zat(sd, j, hit);
+                const float zh = zreg ? zj : zat(sd, j, hit);
                 const float u = zh - P->z_ref;
                 float xm;
                 if (uvj) {
-                    dxy = dat(sd, j, hit);
+                    dxy = zreg ? dj : dat(sd, j, hit);
                     const float yv = y_in + ty_in * (zh - P->z_in);
                     xm = L.wx[sd][j][hit] + dxy * yv;
                 } else {
@@ -1185,7 +1263,7 @@ struct Track {
             const float t1[10] = {sv, h, sv * sv, sv * h, h * h, rr, sv * rr, h * rr,
                                   pres_uv ? sv : 0.0f, pres_uv ? sv * sv : 0.0f};
             float s1[10];
-            chain12(t1, s1);
+            row_sums(t1, s1, g, j);
             const float S1 = s1[0], S2 = s1[1], S11 = s1[2], S12 = s1[3], S22 = s1[4];
             const float R0 = s1[5], R1 = s1[6], R2 = s1[7], YS1 = s1[8], YS11 = s1[9];
             const float m00 = S11 * S22 - S12 * S12;
@@ -1194,30 +1272,33 @@ struct Track {
             const float det = S0 * m00 - S1 * m01 + S2 * m02;
             const bool ok_x = fabsf(det) > 0.0f;
             const float det_s = ok_x ? det : 1.0f;
-            const float da = (R0 * m00 - S1 * (R1 * S22 - S12 * R2) + S2 * (R1 * S12 - S11 * R2)) / det_s;
-            const float db = (S0 * (R1 * S22 - S12 * R2) - R0 * m01 + S2 * (S1 * R2 - R1 * S2)) / det_s;
-            const float dc = (S0 * (S11 * R2 - R1 * S12) - S1 * (S1 * R2 - R1 * S2) + R0 * m02) / det_s;
-            const float da_r = row_lane11(da), db_r = row_lane11(db), dc_r = row_lane11(dc);
-            const float res = pres ? rr - (da_r + db_r * sv + dc_r * h) : 0.0f;
+            // the sums are the same in every lane of the row: lanes 0, 1 and 2
+            // divide the numerators of da, db and dc, and the row takes each
+            const float num_x = j == 0 ? R0 * m00 - S1 * (R1 * S22 - S12 * R2) + S2 * (R1 * S12 - S11 * R2)
+                              : j == 1 ? S0 * (R1 * S22 - S12 * R2) - R0 * m01 + S2 * (S1 * R2 - R1 * S2)
+                                       : S0 * (S11 * R2 - R1 * S12) - S1 * (S1 * R2 - R1 * S2) + R0 * m02;
+            const float q_x = num_x / det_s;
+            const float da = row_bcast_lane(q_x, 0), db = row_bcast_lane(q_x, 1), dc = row_bcast_lane(q_x, 2);
+            const float res = pres ? rr - (da + db * sv + dc * h) : 0.0f;
             const float eta = pres_uv ? -res / dxy : 0.0f;
             // Q_x, and the y line's residual sums
             const float t2[3] = {pres ? res * res / Tj : 0.0f, eta, pres_uv ? sv * eta : 0.0f};
             float s2[3];
-            chain12(t2, s2);
+            row_sums(t2, s2, g, j);
             const float Qx = s2[0], Y0 = s2[1], Y1 = s2[2];
             const float D = YS0 * YS11 - YS1 * YS1;
             const bool ok_y = fabsf(D) > 0.0f;
             const float D_s = ok_y ? D : 1.0f;
-            const float dy0 = (Y0 * YS11 - YS1 * Y1) / D_s;
-            const float dty = (YS0 * Y1 - YS1 * Y0) / D_s;
+            const float q_y = (j == 0 ? Y0 * YS11 - YS1 * Y1 : YS0 * Y1 - YS1 * Y0) / D_s;   // lanes 0, 1: dy0, dty
+            const float dy0 = row_bcast_lane(q_y, 0), dty = row_bcast_lane(q_y, 1);
             const float dslope = dty * INV1024;
-            const float dy0_r = row_lane11(dy0), dty_r = row_lane11(dty);
-            const float ry = pres_uv ? eta - (dy0_r + dty_r * sv) : 0.0f;
+            const float ry = pres_uv ? eta - (dy0 + dty * sv) : 0.0f;
             const float t3[1] = {pres_uv ? ry * ry / P->T_y : 0.0f};
             float s3[1];
-            chain12(t3, s3);
-            const float Qy = s3[0];
-            const float Q = (Qx / (float)(n - 3) + Qy / (float)(n_uv - 2)) * P->C_nhits[n - 9 < 0 ? 0 : (n - 9 > 3 ? 3 : n - 9)];
+            chain12(t3, s3);   // Q_y in lane 11
+            // lane 10 divides Q_x, lane 11 Q_y; lane 11 adds the two
+            const float q_q = j == LR - 1 ? Qx / (float)(n - 3) : s3[0] / (float)(n_uv - 2);
+            const float Q = (dpp<0x111, true>(q_q) + q_q) * P->C_nhits[n - 9 < 0 ? 0 : (n - 9 > 3 ? 3 : n - 9)];
             const bool acc = r >= 0 && ok_x && ok_y && fabsf(dslope) < P->T_ty && Q < P->T_Q;
             // candidates of this pass in rank order: the first strict minimum wins ties
             const uint64_t accm = __ballot(acc && j == LR);
