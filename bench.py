@@ -70,8 +70,8 @@ BYTES_PER_TRACK_OUT = 78
 # HBM traffic of the batched kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (per launch, scaled by the counters' reading of a known-size copy), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha256": "fda28abee919cd44b00ee5e2f314fbf33171db7cd7698f2c64bfa8d1cd896314",
-           "bytes_per_launch": 51938157}
+TRAFFIC = {"kernel_sha256": "a6c029a7a31eb87c9d93be862ce9d91ce3ac2795a96756fdd4c3f74b7d529f44",
+           "bytes_per_launch": 51959999}
 WORKLOADS = {
     "nominal": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",
     "uneven": "uneven: 20000 events, Poisson(7.6) x 50 particles, 0-13k hits and 0-600 tracks/event",
