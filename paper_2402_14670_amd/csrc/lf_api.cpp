@@ -3,12 +3,14 @@
 // result retrieval.  The numerical work is all in lf_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/lf.h"
@@ -24,9 +26,55 @@ struct Batch {
     lfk::DevBatch dev{};
     uint32_t n_events = 0, n_tracks = 0, n_hits = 0;
     std::vector<uint32_t> trk_off;  // host copy, for per-event launches
+    size_t out_off = 0, out_bytes = 0;   // the result arrays: one run of the allocation
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Host threads for validation and staging copies (the host share of one GPU).
+unsigned host_threads(size_t work) {
+    if (work < (size_t(1) << 20)) return 1;
+    const unsigned hw = std::thread::hardware_concurrency();
+    return std::max(1u, std::min(hw ? hw : 1u, 16u));
+}
+
+// Runs f(k) for k in [0, n) over contiguous slices on up to host_threads(work)
+// threads; f returns false at a failure.  Returns the least failing k (n if
+// none), the same index a serial scan would stop at.
+template <class F>
+size_t first_failure(size_t n, size_t work, F f) {
+    const unsigned nt = n < 2 ? 1u : std::min<unsigned>(host_threads(work), (unsigned)std::min<size_t>(n, 64));
+    std::vector<size_t> first(nt, n);
+    auto slice = [&](unsigned k) {
+        for (size_t i = n * k / nt, e = n * (k + 1) / nt; i < e; ++i)
+            if (!f(i)) { first[k] = i; return; }
+    };
+    std::vector<std::thread> th;
+    try {
+        for (unsigned k = 1; k < nt; ++k) th.emplace_back(slice, k);
+    } catch (...) {   // no threads to be had: the rest serially
+        for (unsigned k = (unsigned)th.size() + 1; k < nt; ++k) slice(k);
+    }
+    slice(0);
+    for (auto &t : th) t.join();
+    return *std::min_element(first.begin(), first.end());
+}
+
+// memcpy of several (dst, src, n) pieces, split over host threads.
+struct Piece { void *dst; const void *src; size_t n; };
+void copy_pieces(const std::vector<Piece> &pcs) {
+    size_t total = 0;
+    for (auto &p : pcs) total += p.n;
+    const size_t chunk = size_t(1) << 20;
+    std::vector<Piece> jobs;
+    for (auto &p : pcs)
+        for (size_t o = 0; o < p.n; o += chunk)
+            jobs.push_back({static_cast<char *>(p.dst) + o, static_cast<const char *>(p.src) + o, std::min(chunk, p.n - o)});
+    (void)first_failure(jobs.size(), total, [&](size_t k) {
+        std::memcpy(jobs[k].dst, jobs[k].src, jobs[k].n);
+        return true;
+    });
+}
 
 }  // namespace
 
@@ -43,6 +91,9 @@ struct lf_ctx {
     std::map<uint64_t, Batch> batches;
     uint64_t next_id = 1;
     std::string err;
+    // pinned host staging of uploads and downloads (grown on demand, kept)
+    char *pin = nullptr;
+    size_t pin_cap = 0;
 };
 
 namespace {
@@ -57,6 +108,21 @@ int hip_fail(lf_ctx *c, hipError_t e, const char *what) {
 }
 
 hipStream_t pick(lf_ctx *c, void *s) { return s ? reinterpret_cast<hipStream_t>(s) : c->stream; }
+
+// The context's pinned staging buffer, at least `bytes` long; nullptr when
+// it cannot be had (callers then copy from pageable memory directly).  Its
+// previous contents are not kept.  Only used between synchronisations.
+char *staging(lf_ctx *c, size_t bytes) {
+    if (bytes <= c->pin_cap) return c->pin;
+    if (c->pin) (void)hipHostFree(c->pin);
+    c->pin = nullptr;
+    c->pin_cap = 0;
+    void *p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    c->pin = static_cast<char *>(p);
+    c->pin_cap = bytes;
+    return c->pin;
+}
 
 bool finitef(float v) { return std::isfinite(v); }
 
@@ -129,21 +195,30 @@ int validate(const lf_batch *b, std::string &why) {
     if (H >= (1ull << 30) || T >= (1ull << 26)) { why = "batch: 2^30 or more hits, or 2^26 or more tracks"; return 0; }
     if (H && (!b->hit_x || !b->hit_z || !b->hit_dxdy)) { why = "batch: NULL hit array"; return 0; }
     if (T && (!b->trk_x || !b->trk_y || !b->trk_tx || !b->trk_ty || !b->trk_qop)) { why = "batch: NULL track array"; return 0; }
-    for (size_t i = 0; i < H; ++i)
-        if (!finitef(b->hit_x[i]) || !finitef(b->hit_z[i]) || !finitef(b->hit_dxdy[i])) {
-            why = "batch: non-finite hit " + std::to_string(i);
-            return 0;
-        }
-    for (size_t k = 0; k < nb; ++k)
+    // the scans below run over slices on several host threads; each reports
+    // the first failure a serial scan would
+    const size_t bad_hit = first_failure(H, 12 * H, [&](size_t i) {
+        return finitef(b->hit_x[i]) && finitef(b->hit_z[i]) && finitef(b->hit_dxdy[i]);
+    });
+    if (bad_hit < H) { why = "batch: non-finite hit " + std::to_string(bad_hit); return 0; }
+    const size_t bad_bucket = first_failure(nb, 4 * H, [&](size_t k) {
         for (uint32_t i = b->hit_off[k] + 1; i < b->hit_off[k + 1]; ++i)
-            if (b->hit_x[i] < b->hit_x[i - 1]) { why = "batch: bucket " + std::to_string(k) + " not sorted by x"; return 0; }
-    for (size_t t = 0; t < T; ++t) {
+            if (b->hit_x[i] < b->hit_x[i - 1]) return false;
+        return true;
+    });
+    if (bad_bucket < nb) { why = "batch: bucket " + std::to_string(bad_bucket) + " not sorted by x"; return 0; }
+    const size_t bad_track = first_failure(T, 20 * T, [&](size_t t) {
+        return finitef(b->trk_x[t]) && finitef(b->trk_y[t]) && finitef(b->trk_tx[t]) && finitef(b->trk_ty[t]) &&
+               finitef(b->trk_qop[t]) && b->trk_qop[t] != 0.0f;
+    });
+    if (bad_track < T) {
+        const size_t t = bad_track;
         if (!finitef(b->trk_x[t]) || !finitef(b->trk_y[t]) || !finitef(b->trk_tx[t]) || !finitef(b->trk_ty[t]) ||
-            !finitef(b->trk_qop[t])) {
+            !finitef(b->trk_qop[t]))
             why = "batch: non-finite track state " + std::to_string(t);
-            return 0;
-        }
-        if (b->trk_qop[t] == 0.0f) { why = "batch: q/p == 0 for track " + std::to_string(t); return 0; }
+        else
+            why = "batch: q/p == 0 for track " + std::to_string(t);
+        return 0;
     }
     return 1;
 }
@@ -332,6 +407,8 @@ int lf_upload_events(lf_ctx *c, const lf_batch *b, void *hip_stream, uint64_t *b
     Batch bt;
     bt.bytes = L.total;
     bt.n_events = E; bt.n_tracks = T; bt.n_hits = H;
+    bt.out_off = L.found;
+    bt.out_bytes = L.counter - L.found;
     try {
         bt.trk_off.assign(b->trk_off, b->trk_off + E + 1);
     } catch (...) {
@@ -374,10 +451,21 @@ int lf_upload_events(lf_ctx *c, const lf_batch *b, void *hip_stream, uint64_t *b
         {L.trk_off, b->trk_off, ((size_t)E + 1) * 4}, {L.tx, b->trk_x, (size_t)T * 4},
         {L.ty, b->trk_y, (size_t)T * 4}, {L.ttx, b->trk_tx, (size_t)T * 4},
         {L.tty, b->trk_ty, (size_t)T * 4}, {L.tqop, b->trk_qop, (size_t)T * 4}};
-    for (auto &x : cp) {
-        if (!x.n) continue;
-        e = hipMemcpyAsync(base + x.off, x.src, x.n, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) break;
+    // the inputs are one run [0, L.uni) of the allocation: staged in pinned
+    // memory by several host threads, then one copy over the host link
+    char *pin = staging(c, L.uni);
+    if (pin) {
+        std::vector<Piece> pcs;
+        for (auto &x : cp)
+            if (x.n) pcs.push_back({pin + x.off, x.src, x.n});
+        copy_pieces(pcs);
+        e = hipMemcpyAsync(base, pin, L.uni, hipMemcpyHostToDevice, s);
+    } else {
+        for (auto &x : cp) {
+            if (!x.n) continue;
+            e = hipMemcpyAsync(base + x.off, x.src, x.n, hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) break;
+        }
     }
     if (e == hipSuccess) e = hipMemsetAsync(d.counter, 0, 4 * (size_t)lfk::QUEUE_WORDS, s);
     if (e == hipSuccess) e = lfk::launch_track_event(d, s);
@@ -548,9 +636,23 @@ int copy_tracks(lf_ctx *c, uint64_t batch_id, lf_tracks_out *out, size_t cap_tra
             {out->found, d.found, T}, {out->n_hits, d.nhits, T}, {out->hit_idx, d.hit_idx, T * 48},
             {out->a, d.a, T * 4}, {out->b, d.b, T * 4}, {out->c, d.c, T * 4}, {out->y0, d.y0, T * 4},
             {out->ty, d.ty, T * 4}, {out->qop, d.qop, T * 4}, {out->Q, d.Q, T * 4}};
-        for (auto &x : cp) {
-            e = hipMemcpyAsync(x.dst, x.src, x.n, hipMemcpyDeviceToHost, s);
-            if (e != hipSuccess) break;
+        // the results are one run of the allocation: one copy over the host
+        // link into pinned memory, then spread by several host threads
+        const char *run = static_cast<const char *>(bt.dmem) + bt.out_off;
+        char *pin = staging(c, bt.out_bytes);
+        if (pin) {
+            e = hipMemcpyAsync(pin, run, bt.out_bytes, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e == hipSuccess) {
+                std::vector<Piece> pcs;
+                for (auto &x : cp) pcs.push_back({x.dst, pin + (static_cast<const char *>(x.src) - run), x.n});
+                copy_pieces(pcs);
+            }
+        } else {
+            for (auto &x : cp) {
+                e = hipMemcpyAsync(x.dst, x.src, x.n, hipMemcpyDeviceToHost, s);
+                if (e != hipSuccess) break;
+            }
         }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -614,6 +716,7 @@ void lf_destroy(lf_ctx *c) {
     (void)hipDeviceSynchronize();
     for (auto &kv : c->batches) (void)hipFree(kv.second.dmem);
     if (c->d_params) (void)hipFree(c->d_params);
+    if (c->pin) (void)hipHostFree(c->pin);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

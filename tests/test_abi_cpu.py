@@ -112,3 +112,30 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode != 0 and "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_check_batch_reports_the_first_failure_of_a_large_batch(lf):
+    """Validation of a large batch runs over slices on several host threads;
+    it must still name the failure a serial scan would meet first."""
+    ev = lfgen.generate("nominal", n_events=300)
+    assert 12 * ev.n_hits >= 1 << 20 and 20 * ev.n_tracks >= 1 << 20   # the threaded scans
+    H, T = ev.n_hits, ev.n_tracks
+    x = ev.hit_x.copy(); x[H - 10] = np.nan; x[H // 7] = np.inf
+    with pytest.raises(lf.LFError, match=f"non-finite hit {H // 7}$"):
+        lf.lf_check_batch(_mutated(ev, hit_x=x))
+    x = ev.hit_x.copy()
+    buckets = []
+    for k in (24 * 250 + 5, 24 * 40 + 2):
+        b0, b1 = int(ev.hit_off[k]), int(ev.hit_off[k + 1])
+        assert b1 - b0 >= 2
+        x[b0], x[b0 + 1] = x[b0 + 1] + 1.0, x[b0]
+        buckets.append(k)
+    with pytest.raises(lf.LFError, match=f"bucket {min(buckets)} not sorted by x$"):
+        lf.lf_check_batch(_mutated(ev, hit_x=x))
+    q = ev.trk_qop.copy(); q[T // 9] = 0.0
+    t = ev.trk_ty.copy(); t[T - 3] = np.inf
+    with pytest.raises(lf.LFError, match=f"q/p == 0 for track {T // 9}$"):
+        lf.lf_check_batch(_mutated(ev, trk_qop=q, trk_ty=t))
+    t = ev.trk_ty.copy(); t[T // 11] = np.nan
+    with pytest.raises(lf.LFError, match=f"non-finite track state {T // 11}$"):
+        lf.lf_check_batch(_mutated(ev, trk_qop=q, trk_ty=t))
