@@ -243,9 +243,11 @@ int lf_check_batch(const lf_batch *batch);
 /* The step's input (Algorithm logic: upstream track states and the SciFi
  * hits of each event).  Validates a host batch, copies it to device memory
  * (on hip_stream) and returns its id.  Input and output buffers of the batch stay resident until
- * lf_fetch_tracks or lf_release_batch.  Errors: LF_ERR_INVALID (malformed
- * batch; nothing is copied), LF_ERR_TOO_LARGE (over budget), LF_ERR_NOMEM,
- * LF_ERR_DEVICE. */
+ * lf_fetch_tracks or lf_release_batch.  The inputs pass through a pinned host
+ * buffer that the context keeps (grown to the largest batch or result set
+ * seen, held until lf_destroy); the call returns once they are on the
+ * device.  Errors: LF_ERR_INVALID (malformed batch; nothing is copied),
+ * LF_ERR_TOO_LARGE (over budget), LF_ERR_NOMEM, LF_ERR_DEVICE. */
 int lf_upload_events(lf_ctx *ctx, const lf_batch *batch, void *hip_stream, uint64_t *batch_id);
 
 /* The whole step of Algorithm logic: search windows (Defining the search
@@ -294,7 +296,8 @@ int lf_work_counts(lf_ctx *ctx, uint64_t batch_id, void *hip_stream, int64_t *co
  * candidate of the Quality Filter section, with its fitted x(z) and y(z)
  * parameters and the q/p of Calculation of momentum and track states.
  * Copies the results of a batch into caller buffers holding at least
- * cap_tracks >= number of input tracks slots, waits for completion and
+ * cap_tracks >= number of input tracks slots (through the context's pinned
+ * buffer, as in lf_upload_events), waits for completion and
  * frees the batch.  Errors: LF_ERR_STATE, LF_ERR_INVALID (NULL buffer or
  * cap_tracks too small; the batch stays resident), LF_ERR_DEVICE. */
 int lf_fetch_tracks(lf_ctx *ctx, uint64_t batch_id, lf_tracks_out *out, size_t cap_tracks,
