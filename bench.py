@@ -93,6 +93,9 @@ def parse():
     ap.add_argument("--workload", default="nominal", choices=sorted(WORKLOADS))
     ap.add_argument("--events", type=int, default=0, help="events of the workload (0: its full size)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--persistent-exec", default="",
+                    help="W,I,B: wavefronts per block, tracks per claim and blocks per CU of the persistent "
+                         "launch (instead of the autotuner's choice)")
     ap.add_argument("--modes", default="batched,persistent,plain",
                     help="comma-separated subset of batched,persistent,plain to time (batched is always timed)")
     ap.add_argument("--serve-requests", type=int, default=200000,
@@ -540,7 +543,11 @@ def main():
                               ("plain", args.plain_steps, 1)):
         if mode not in wanted:
             continue
-        if tuned and mode in tuned["per_mode"]:
+        if mode == "persistent" and args.persistent_exec:
+            w, i, b = (int(v) for v in args.persistent_exec.split(","))
+            lf.lf_set_exec(ctx, waves_per_block=w)
+            lf.lf_set_exec(ctx, items_per_grab=i, blocks_per_cu=b)
+        elif tuned and mode in tuned["per_mode"]:
             c = tuned["per_mode"][mode]
             lf.lf_set_exec(ctx, waves_per_block=c["waves_per_block"])
             lf.lf_set_exec(ctx, items_per_grab=c["items_per_grab"], blocks_per_cu=c["blocks_per_cu"])
