@@ -70,7 +70,7 @@ BYTES_PER_TRACK_OUT = 78
 # HBM traffic of the batched kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (per launch, scaled by the counters' reading of a known-size copy), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha256": "a6c029a7a31eb87c9d93be862ce9d91ce3ac2795a96756fdd4c3f74b7d529f44",
+TRAFFIC = {"kernel_sha256": "b5311544d8434c1ab77be366c776b0aecb51f6cadd33c311f259eceedef40b65",
            "bytes_per_launch": 51959999}
 WORKLOADS = {
     "nominal": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",

@@ -34,6 +34,7 @@
 // Nothing in this file allocates; the kernels' scratch is LDS, apart from
 // the fixed device array that the non-allocating entry point uses for its
 // queue words and per-event and per-track indexes.
+#include <cstddef>
 #include <mutex>
 
 #include "lf_internal.h"
@@ -388,7 +389,9 @@ struct Track {
         using W = WaveLds<NW, NS>;
         static_assert(!W::XO, "needs the per-hit z and slope rows");
         static_assert(N <= 10 && 4 * N * 12 <= NS * (NL + 6) * W::ZW, "4 N slots of 12 floats");
-        float *base = &L.wz[0][0][0];   // wz, then wd: one run of floats
+        static_assert(offsetof(W, wd) == offsetof(W, wz) + sizeof(L.wz), "wz and wd must be one run");
+        // wz, then wd: one run of floats of the wave's slice
+        float *base = reinterpret_cast<float *>(reinterpret_cast<char *>(&L) + offsetof(W, wz));
         wave_sync();   // the previous use of the scratch has been read
         if (j < NL) {
 #pragma unroll
