@@ -358,7 +358,9 @@ typedef struct {
     uint32_t results_on_device;  /* 0: every batch's results are copied to host memory [0]; 1: the
                                     results stay in the batch's device region (for later GPU stages)
                                     and only the per-event digests come back */
-    uint32_t reserved;           /* 0 */
+    uint32_t verify_results;     /* testing (0 or 1) [0]: with results_on_device = 0, each completed
+                                    batch's results in host memory are compared byte for byte with the
+                                    device copy (a synchronous copy inside the loop: not for timing) */
     size_t device_budget_bytes;  /* admission budget for resident events [8 GiB] */
 } lf_serve_config;
 
@@ -374,6 +376,7 @@ typedef struct {
                                     reads from the pinned pool (offsets, hits, states; none with
                                     pool_on_device) and the batch descriptors */
     uint64_t bytes_out;          /* bytes over the host link out: digests and track slots */
+    uint64_t result_mismatches;  /* verify_results: bytes of host results that differ from the device's */
 } lf_serve_stats;
 
 /* Runs a stream of requests through the serving loop and returns when all

@@ -163,7 +163,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
     if (cfg.n_slots == 0) cfg.n_slots = 4;
     if (cfg.device_budget_bytes == 0) cfg.device_budget_bytes = size_t(8) << 30;
     if (cfg.n_slots > 16 || cfg.n_pack_threads > 64 || cfg.max_batch_events > (1u << 20) || cfg.pool_on_device > 1 ||
-        cfg.results_on_device > 1)
+        cfg.results_on_device > 1 || cfg.verify_results > 1)
         return lfapi::ctx_fail(ctx, LF_ERR_INVALID, "lf_serve_run: configuration out of range");
     const uint32_t PE = pool_b->n_events;
     for (uint32_t i = 0; i < n_requests; ++i) {
@@ -268,6 +268,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
         }
         s.stage_cap = cfg.max_batch_events;
         s.out_cap = biggest.out_bytes;
+
     }
     // A host pool: the gather kernel reads the pinned blobs over the host
     // link.  A device pool: copied once (before the clock) as one resident
@@ -455,7 +456,8 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
     std::deque<uint32_t> queue;       // arrived, not yet in a batch
     std::deque<uint32_t> inflight;    // slot indices in submission order
     uint32_t next_arrival = 0, completed = 0;
-    uint64_t n_batches = 0, batched_events = 0, max_queue = 0, bytes_in = 0, bytes_out = 0;
+    uint64_t n_batches = 0, batched_events = 0, max_queue = 0, bytes_in = 0, bytes_out = 0, mismatches = 0;
+    std::vector<unsigned char> verify_buf;
     size_t max_dev = 0;
     int rc = LF_OK;
     const Clock::time_point t0 = Clock::now();
@@ -473,6 +475,21 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
             if (q != hipSuccess) { rc = lfapi::ctx_fail(ctx, LF_ERR_DEVICE, std::string("lf_serve_run: ") + hipGetErrorString(q)); break; }
             const double t = now_s();
             const unsigned long long *dig = reinterpret_cast<const unsigned long long *>(s.out);
+            if (cfg.verify_results && !cfg.results_on_device) {
+                // (testing) the results downloaded to host memory against the device copy
+                const size_t nb = s.lay.out_bytes;
+                verify_buf.resize(nb);
+                const hipError_t ve = hipMemcpy(verify_buf.data(), static_cast<char *>(ring_mem) + s.ring_at + s.lay.dig,
+                                                nb, hipMemcpyDeviceToHost);
+                if (ve != hipSuccess) { rc = lfapi::ctx_fail(ctx, LF_ERR_DEVICE, std::string("lf_serve_run: ") + hipGetErrorString(ve)); break; }
+                // the arrays only (the alignment gaps between them are never written)
+                const BatchLayout &y = s.lay;
+                const size_t ranges[5][2] = {{0, (size_t)y.E * 8}, {y.found - y.dig, y.T}, {y.nhits - y.dig, y.T},
+                                             {y.hit_idx - y.dig, (size_t)y.T * 48}, {y.fl - y.dig, (size_t)y.T * 28}};
+                for (const auto &r : ranges)
+                    for (size_t k = r[0]; k < r[0] + r[1]; ++k)
+                        mismatches += verify_buf[k] != static_cast<unsigned char>(s.out[k]);
+            }
             for (size_t k = 0; k < s.reqs.size(); ++k) {
                 const uint32_t r = s.reqs[k];
                 lat[r] = t - arrival_s[r];
@@ -575,6 +592,7 @@ extern "C" int lf_serve_run(lf_ctx *ctx, const lf_batch *pool_b, uint32_t n_requ
         stats->max_queue = max_queue;
         stats->bytes_in = bytes_in;
         stats->bytes_out = bytes_out;
+        stats->result_mismatches = mismatches;
     }
     return LF_OK;
 }

@@ -79,7 +79,7 @@ class lf_serve_config(ctypes.Structure):
     _fields_ = [("max_batch_events", ctypes.c_uint32), ("min_batch_events", ctypes.c_uint32),
                 ("max_wait_us", ctypes.c_uint32), ("n_slots", ctypes.c_uint32),
                 ("n_pack_threads", ctypes.c_uint32), ("pool_on_device", ctypes.c_uint32),
-                ("results_on_device", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("results_on_device", ctypes.c_uint32), ("verify_results", ctypes.c_uint32),
                 ("device_budget_bytes", ctypes.c_size_t)]
 
 
@@ -89,7 +89,7 @@ class lf_serve_stats(ctypes.Structure):
                 ("events_per_s", ctypes.c_double), ("lat_p50_s", ctypes.c_double), ("lat_p99_s", ctypes.c_double),
                 ("lat_p999_s", ctypes.c_double), ("lat_max_s", ctypes.c_double),
                 ("mean_batch_events", ctypes.c_double), ("bytes_in", ctypes.c_uint64),
-                ("bytes_out", ctypes.c_uint64)]
+                ("bytes_out", ctypes.c_uint64), ("result_mismatches", ctypes.c_uint64)]
 
 
 class lf_exec(ctypes.Structure):

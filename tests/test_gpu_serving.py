@@ -46,9 +46,11 @@ def _stream(n_pool, n, rate, seed=40):
     ({"results_on_device": 1}, 20000.0),
     ({"pool_on_device": 1, "results_on_device": 1, "n_slots": 4, "min_batch_events": 384, "max_wait_us": 150},
      2.0e6),
+    ({"verify_results": 1}, 20000.0),
+    ({"pool_on_device": 1, "verify_results": 1, "max_batch_events": 64, "n_slots": 3}, None),
 ], ids=["poisson", "saturated", "one-by-one", "small-batches", "wait-to-fill", "device-pool-poisson",
         "device-pool-saturated", "device-pool-one-by-one", "device-pool-results-on-device", "results-on-device",
-        "device-pool-wait-to-fill-results-on-device"])
+        "device-pool-wait-to-fill-results-on-device", "host-results-checked", "device-pool-host-results-checked"])
 def test_results_same_alone_and_in_the_mix(pool, cfg, rate):
     from paper_2402_14670_amd import lf
     ev, ref = pool
@@ -63,6 +65,8 @@ def test_results_same_alone_and_in_the_mix(pool, cfg, rate):
     bad = np.nonzero(dig != ref[req])[0]
     assert len(bad) == 0, f"{len(bad)} requests differ from the oracle, first {bad[:5]}"
     assert np.all(lat > 0) and st["n_requests"] == len(req)
+    # results the digest kernel wrote into host memory, compared with the device copy
+    assert st["result_mismatches"] == 0
     if cfg.get("max_batch_events") == 1:
         assert st["n_batches"] == len(req)
     # host-link bytes: descriptors always, event blobs only from a host pool
