@@ -329,10 +329,12 @@ int lf_batch_info(lf_ctx *ctx, uint64_t batch_id, uint32_t *n_events, uint32_t *
 size_t lf_device_bytes_in_use(const lf_ctx *ctx);
 
 /* Captured launch sequences (HIP graphs).  A graph records the hot path
- * of n resident batches in the given mode, in order, and replays it with
- * one launch call.  The batches must stay resident (not fetched or
- * released) while the graph is used.  No memset node is recorded: the
- * persistent mode's queue words reset themselves. */
+ * of n resident batches in the given mode and replays it with one launch
+ * call.  Distinct batches are recorded as parallel branches (their launches
+ * may overlap); a list that names a batch twice is recorded in order.  The
+ * batches must stay resident (not fetched or released) while the graph is
+ * used.  No memset node is recorded: the persistent mode's queue words
+ * reset themselves. */
 typedef struct lf_graph lf_graph;
 
 /* Errors: LF_ERR_STATE (unknown batch), LF_ERR_INVALID, LF_ERR_DEVICE. */

@@ -559,23 +559,48 @@ int lf_graph_create(lf_ctx *c, const uint64_t *ids, uint32_t n, int mode, lf_gra
         if (it == c->batches.end()) return fail(c, LF_ERR_STATE, "lf_graph_create: unknown batch id");
         bs.push_back(&it->second);
     }
+    // Distinct batches are independent (each writes only its own results
+    // and, in persistent mode, its own queue words): captured as parallel
+    // branches (a fork from the capture stream and a join back), so the
+    // graph's launches may overlap and fill each other's ragged ends.  A
+    // batch listed twice keeps the whole sequence in order on one stream.
+    bool distinct = true;
+    {
+        std::vector<uint64_t> sorted(ids, ids + n);
+        std::sort(sorted.begin(), sorted.end());
+        distinct = std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end();
+    }
+    const uint32_t n_side = distinct ? n - 1 : 0;
     hipStream_t cs = nullptr;
+    std::vector<hipStream_t> side(n_side, nullptr);
+    std::vector<hipEvent_t> evs(n, nullptr);   // evs[0]: the fork; evs[i]: branch i's join
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    for (uint32_t i = 0; i < n && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&evs[i], hipEventDisableTiming);
+    for (uint32_t i = 0; i < n_side && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
+    auto release = [&]() {
+        for (auto &x : side) if (x) (void)hipStreamDestroy(x);
+        for (auto &x : evs) if (x) (void)hipEventDestroy(x);
+        if (cs) (void)hipStreamDestroy(cs);
+    };
     lf_graph *g = new (std::nothrow) lf_graph();
-    if (!g) { if (cs) (void)hipStreamDestroy(cs); return fail(c, LF_ERR_NOMEM, "lf_graph_create: out of memory"); }
+    if (!g) { release(); return fail(c, LF_ERR_NOMEM, "lf_graph_create: out of memory"); }
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = hipSuccess;
-        for (Batch *b : bs) {
-            le = lfk::launch_find(b->dev, c->d_params, c->params.n_hits_window, lfapi::ctx_sides(c), mode,
-                                  c->exec, b->trk_off.data(), cs);
-            if (le != hipSuccess) break;
+        hipError_t le = n_side ? hipEventRecord(evs[0], cs) : hipSuccess;
+        for (uint32_t i = 0; i < n_side && le == hipSuccess; ++i) le = hipStreamWaitEvent(side[i], evs[0], 0);
+        for (uint32_t i = 0; i < n && le == hipSuccess; ++i) {
+            const bool branch = n_side && i > 0;
+            hipStream_t st = branch ? side[i - 1] : cs;
+            le = lfk::launch_find(bs[i]->dev, c->d_params, c->params.n_hits_window, lfapi::ctx_sides(c), mode,
+                                  c->exec, bs[i]->trk_off.data(), st);
+            if (le == hipSuccess && branch) le = hipEventRecord(evs[i], st);
+            if (le == hipSuccess && branch) le = hipStreamWaitEvent(cs, evs[i], 0);
         }
         e = hipStreamEndCapture(cs, &g->graph);
         if (le != hipSuccess) e = le;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
-    if (cs) (void)hipStreamDestroy(cs);
+    release();
     if (e != hipSuccess) {
         lf_graph_destroy(g);
         return hip_fail(c, e, "lf_graph_create");

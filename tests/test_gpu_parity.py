@@ -412,6 +412,36 @@ def test_graph_replays(mode):
         lf.lf_destroy(ctx)
 
 
+@pytest.mark.parametrize("mode", ["batched", "persistent"])
+def test_graph_with_a_batch_named_twice(mode):
+    """A capture list that names a batch twice is recorded in order (the two
+    launches of that batch must not overlap: in persistent mode they share
+    its queue words); every replay matches the oracle."""
+    from paper_2402_14670_amd import lf
+    parts = [lfgen.generate("uneven", n_events=20, first_event=20 * i) for i in range(2)]
+    refs = [oracle.run(p, W) for p in parts]
+    ctx = lf.lf_create(W)
+    try:
+        ids = [lf.lf_upload_events(ctx, p) for p in parts]
+        say(f"[gpu] graph capture mode={mode} of batches {ids[0]}, {ids[1]}, {ids[0]}")
+        g = lf.lf_graph_create(ctx, [ids[0], ids[1], ids[0]], mode)
+        try:
+            for rep in range(3):
+                for i in ids:
+                    lf.lf_poison_tracks(ctx, i)
+                lf.lf_graph_launch(ctx, g)
+                for i, p, r in zip(ids, parts, refs):
+                    compare(r, lf.lf_copy_tracks(ctx, i, p.n_tracks), label=f"graph-twice/{mode}/replay{rep}")
+        finally:
+            lf.lf_graph_destroy(g)
+        # the queue words were left clean: an eager persistent launch still matches
+        lf.lf_poison_tracks(ctx, ids[0])
+        lf.lf_find_tracks(ctx, ids[0], "persistent")
+        compare(refs[0], lf.lf_copy_tracks(ctx, ids[0], parts[0].n_tracks), label=f"graph-twice/{mode}/after")
+    finally:
+        lf.lf_destroy(ctx)
+
+
 def test_autotuner_keeps_results():
     import torch
     from paper_2402_14670_amd import autotune, lf
