@@ -56,7 +56,10 @@ def autotune(ctx, batch_id, stream, modes=("batched", "persistent"), steps=5) ->
     batched one."""
     table = []
     for cfg in candidates(modes):
-        ms = time_config(ctx, batch_id, cfg, stream, steps=steps)
+        # the batched mode has three candidates only, whose times lie within a
+        # few percent: they get more timed launches, so noise does not decide
+        n = steps if cfg["mode"] == "persistent" else max(steps, 12)
+        ms = time_config(ctx, batch_id, cfg, stream, steps=n)
         table.append(dict(cfg, ms=round(ms, 4)))
     per_mode = {}
     for row in table:
