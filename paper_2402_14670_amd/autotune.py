@@ -55,11 +55,24 @@ def autotune(ctx, batch_id, stream, modes=("batched", "persistent"), steps=5) ->
     launch parameters when the best mode is persistent, else with the best
     batched one."""
     table = []
-    for cfg in candidates(modes):
-        # the batched mode has three candidates only, whose times lie within a
-        # few percent: they get more timed launches, so noise does not decide
-        n = steps if cfg["mode"] == "persistent" else max(steps, 12)
-        ms = time_config(ctx, batch_id, cfg, stream, steps=n)
+    cands = candidates(modes)
+    # the batched mode's three candidates lie within a few percent of each
+    # other: each gets more launches, timed in three interleaved rounds after
+    # a warm-up of the device (the first candidate timed on a cold device
+    # would lose to its order alone), and keeps its best round
+    batched = [c for c in cands if c["mode"] == "batched"]
+    if batched:
+        time_config(ctx, batch_id, batched[0], stream, steps=max(steps, 12))
+        best_ms = {}
+        for _ in range(3):
+            for k, cfg in enumerate(batched):
+                ms = time_config(ctx, batch_id, cfg, stream, steps=max(steps, 12))
+                best_ms[k] = min(best_ms.get(k, ms), ms)
+        table += [dict(cfg, ms=round(best_ms[k], 4)) for k, cfg in enumerate(batched)]
+    for cfg in cands:
+        if cfg["mode"] == "batched":
+            continue
+        ms = time_config(ctx, batch_id, cfg, stream, steps=steps)
         table.append(dict(cfg, ms=round(ms, 4)))
     per_mode = {}
     for row in table:
