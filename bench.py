@@ -429,8 +429,8 @@ def paper_field_mode(lf, workload, n_events, stream, steps, warmup, tune=True):
 def general_path(lf, world, ev, stream, steps, warmup, tune=True, z_mm=1.5, slope_rel=0.02, seed=11):
     """The same events with every hit's z and stereo slope jittered (tilted
     or bowed layers: no bucket shares one z or one slope), so the kernel
-    stages z and slope per hit, tests every pair of a seed set whose
-    windows lack a common z, and scans stereo windows; batched mode."""
+    stages z and slope per hit, brackets each doublet's third window over
+    the z range of its hits, and scans stereo windows; batched mode."""
     import numpy as np
     import lfgen
     rng = np.random.default_rng(seed)

@@ -860,20 +860,44 @@ struct Track {
         }
         int qn = 0;
         // One item per (side, set, h0).  Each item gets the range of h2 in its third
-        // window that can pass the magnet filter: with a common z per window,
-        // a passing slope t satisfies |x0 - x_mag + (z_mag - z0) t| < tol(t)
-        // <= tolb, so t lies within tolb/|z_mag - z0| of t_c = (x_mag - x0) /
-        // (z_mag - z0), and x2 = x0 + t (z2 - z0).  The x2 interval is widened
+        // window that can pass the magnet filter: a passing slope t satisfies
+        // |x0 - x_mag + (z_mag - z0) t| < tol(t) <= tolb, so t lies within
+        // tolb/|z_mag - z0| of t_c = (x_mag - x0) / (z_mag - z0), and
+        // x2 = x0 + t (z2 - z0), with z2 the window's one z or, where its hits
+        // differ in z, anywhere in their range (the extremes of x2 are then at
+        // the corners of the t and z2 intervals).  The x2 interval is widened
         // by 0.5 mm + 1e-5 relative, orders of magnitude above the rounding
         // of the filter itself and of the approximate reciprocal used for the
         // bracket, and every pair in it is tested with the exact filter
-        // below; pairs outside cannot pass.  Sets without a common z
-        // per window (or a degenerate lever arm) test every pair.
+        // below; pairs outside cannot pass.  A degenerate lever arm, or (in
+        // builds that stage x only) a window whose hits differ in z, tests
+        // every pair.
         // items in (side, set) order: group g = 2 side + set starts at c[g]
         const int c1 = L.wlen[0][0], c2 = c1 + L.wlen[0][3];
         const int c3 = NS > 1 ? c2 + L.wlen[NS - 1][0] : c2;
         const int items_total = NS > 1 ? c3 + L.wlen[NS - 1][3] : c2;
         if constexpr (CNT) cnt[C_ITEMS] = (uint32_t)items_total;
+        // builds that stage z per hit: the z range of each third window whose
+        // hits do not share one z (min and max over its hits, wave-wide)
+        float z2lo[2] = {0.0f, 0.0f}, z2hi[2] = {0.0f, 0.0f};
+        if constexpr (!WaveLds<NW, NS>::XO) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int l2 = s ? 11 : 8;
+                if ((zvar >> l2) & 1u) {
+                    const int n2 = L.wlen[0][l2];
+                    const float z = lane < n2 ? L.wz[0][l2][lane < NW ? lane : 0] : 0.0f;
+                    float lo = lane < n2 ? z : INFINITY, hi = lane < n2 ? z : -INFINITY;
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) {
+                        lo = fminf(lo, __shfl_xor(lo, off));
+                        hi = fmaxf(hi, __shfl_xor(hi, off));
+                    }
+                    z2lo[s] = bcast_f(lo, 0);
+                    z2hi[s] = bcast_f(hi, 0);
+                }
+            }
+        }
         for (int base = 0; base < items_total; base += WAVE) {
             const int item = base + lane;
             const int grp = item < c1 ? 0 : (item < c2 ? 1 : (item < c3 ? 2 : 3));
@@ -887,10 +911,15 @@ struct Track {
                 x0 = L.wx[sd][l0][i0];
                 z0 = zat(sd, l0, i0);
                 jhi = n2;
-                if (n2 > 0 && !(((zvar >> (NL * sd + l0)) | (zvar >> (NL * sd + l2))) & 1u)) {
+                // the third window's z range: one value, or (builds that stage
+                // z per hit) the range of its hits' z
+                const bool mix2 = (zvar >> (NL * sd + l2)) & 1u, mix0 = (zvar >> (NL * sd + l0)) & 1u;
+                const bool ranged = !WaveLds<NW, NS>::XO && mix2;
+                if (n2 > 0 && (!WaveLds<NW, NS>::XO || !(mix0 || mix2))) {
                     const float lev = P->z_mag - z0;
-                    const float dz = L.wz[sd][l2][0] - z0;
-                    if (fabsf(lev) > 1.0f && fabsf(dz) > 1.0f) {
+                    const float dzl = (ranged ? sel(z2lo, s) : L.wz[sd][l2][0]) - z0;
+                    const float dzh = (ranged ? sel(z2hi, s) : L.wz[sd][l2][0]) - z0;
+                    if (fabsf(lev) > 1.0f && (dzl > 1.0f || dzh < -1.0f)) {
                         const float rl = __builtin_amdgcn_rcpf(lev);   // within 1 ulp: the bracket is padded
                         const float arl = fabsf(rl);
                         const float tc = (x_mag - x0) * rl;
@@ -900,10 +929,22 @@ struct Track {
                         if (tolb < P->magtol_min) tolb = P->magtol_min;
                         if (tolb > P->magtol_max) tolb = P->magtol_max;
                         const float dt = tolb * arl;
-                        const float e1 = x0 + (tc - dt) * dz, e2 = x0 + (tc + dt) * dz;
+                        // x2 = x0 + t dz over t in [tc - dt, tc + dt] and dz in
+                        // [dzl, dzh] (one value when the window shares one z)
+                        float e1, e2;
+                        if (ranged) {
+                            const float c1 = (tc - dt) * dzl, c2 = (tc - dt) * dzh;
+                            const float c3 = (tc + dt) * dzl, c4 = (tc + dt) * dzh;
+                            e1 = x0 + fminf(fminf(c1, c2), fminf(c3, c4));
+                            e2 = x0 + fmaxf(fmaxf(c1, c2), fmaxf(c3, c4));
+                        } else {   // dzl = dzh
+                            const float a1 = x0 + (tc - dt) * dzl, a2 = x0 + (tc + dt) * dzl;
+                            e1 = a1 < a2 ? a1 : a2;
+                            e2 = a1 < a2 ? a2 : a1;
+                        }
                         const float margin = 0.5f + 1e-5f * (fabsf(e1) + fabsf(e2));
-                        const float xlo = (e1 < e2 ? e1 : e2) - margin;
-                        const float xhi = (e1 < e2 ? e2 : e1) + margin;
+                        const float xlo = e1 - margin;
+                        const float xhi = e2 + margin;
                         if (fabsf(xlo) < 1e30f && fabsf(xhi) < 1e30f) {
                             bounds_sorted<NW>(L.wx[sd][l2], n2, xlo, xhi, jlo, jhi);
                         }
