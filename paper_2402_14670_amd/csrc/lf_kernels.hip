@@ -877,13 +877,17 @@ struct Track {
         const int c3 = NS > 1 ? c2 + L.wlen[NS - 1][0] : c2;
         const int items_total = NS > 1 ? c3 + L.wlen[NS - 1][3] : c2;
         if constexpr (CNT) cnt[C_ITEMS] = (uint32_t)items_total;
-        // builds that stage z per hit: the z range of each third window whose
-        // hits do not share one z (min and max over its hits, wave-wide)
+        // builds that stage z per hit (one side): the z range of each third
+        // window, its one z or, where its hits differ in z, the min and max
+        // over them (wave-wide); ranged: some third window of the track is
+        // of the second kind (a wave-uniform choice of bracket form)
         float z2lo[2] = {0.0f, 0.0f}, z2hi[2] = {0.0f, 0.0f};
+        const bool ranged = !WaveLds<NW, NS>::XO && ((zvar >> 8) & 1u || (zvar >> 11) & 1u);
         if constexpr (!WaveLds<NW, NS>::XO) {
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const int l2 = s ? 11 : 8;
+                z2lo[s] = z2hi[s] = L.wz[0][l2][0];
                 if ((zvar >> l2) & 1u) {
                     const int n2 = L.wlen[0][l2];
                     const float z = lane < n2 ? L.wz[0][l2][lane < NW ? lane : 0] : 0.0f;
@@ -914,11 +918,10 @@ struct Track {
                 // the third window's z range: one value, or (builds that stage
                 // z per hit) the range of its hits' z
                 const bool mix2 = (zvar >> (NL * sd + l2)) & 1u, mix0 = (zvar >> (NL * sd + l0)) & 1u;
-                const bool ranged = !WaveLds<NW, NS>::XO && mix2;
                 if (n2 > 0 && (!WaveLds<NW, NS>::XO || !(mix0 || mix2))) {
                     const float lev = P->z_mag - z0;
-                    const float dzl = (ranged ? sel(z2lo, s) : L.wz[sd][l2][0]) - z0;
-                    const float dzh = (ranged ? sel(z2hi, s) : L.wz[sd][l2][0]) - z0;
+                    const float dzl = (WaveLds<NW, NS>::XO ? L.wz[sd][l2][0] : sel(z2lo, s)) - z0;
+                    const float dzh = (WaveLds<NW, NS>::XO ? L.wz[sd][l2][0] : sel(z2hi, s)) - z0;
                     if (fabsf(lev) > 1.0f && (dzl > 1.0f || dzh < -1.0f)) {
                         const float rl = __builtin_amdgcn_rcpf(lev);   // within 1 ulp: the bracket is padded
                         const float arl = fabsf(rl);
@@ -932,7 +935,7 @@ struct Track {
                         // x2 = x0 + t dz over t in [tc - dt, tc + dt] and dz in
                         // [dzl, dzh] (one value when the window shares one z)
                         float e1, e2;
-                        if (ranged) {
+                        if (ranged) {   // corners; exact also where dzl = dzh
                             const float c1 = (tc - dt) * dzl, c2 = (tc - dt) * dzh;
                             const float c3 = (tc + dt) * dzl, c4 = (tc + dt) * dzh;
                             e1 = x0 + fminf(fminf(c1, c2), fminf(c3, c4));
