@@ -70,8 +70,8 @@ BYTES_PER_TRACK_OUT = 78
 # HBM traffic of the batched kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (per launch, scaled by the counters' reading of a known-size copy), valid
 # only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha256": "b5311544d8434c1ab77be366c776b0aecb51f6cadd33c311f259eceedef40b65",
-           "bytes_per_launch": 51959999}
+TRAFFIC = {"kernel_sha256": "23551861fd187e3fcb61e3e77c9759c10aafb0874e4e1533755d4b22d1692791",
+           "bytes_per_launch": 51958319}
 WORKLOADS = {
     "nominal": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",
     "uneven": "uneven: 20000 events, Poisson(7.6) x 50 particles, 0-13k hits and 0-600 tracks/event",
