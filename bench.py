@@ -69,9 +69,9 @@ BYTES_PER_TRACK_IN = 20
 BYTES_PER_TRACK_OUT = 78
 # HBM traffic of the batched kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (per launch, scaled by the counters' reading of a known-size copy), valid
-# only for the kernel source it was measured on.
+# only for the kernel source and the workload it was measured on.
 TRAFFIC = {"kernel_sha256": "23551861fd187e3fcb61e3e77c9759c10aafb0874e4e1533755d4b22d1692791",
-           "bytes_per_launch": 51958319}
+           "workload": "nominal", "events": 0, "bytes_per_launch": 51958319}
 WORKLOADS = {
     "nominal": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",
     "uneven": "uneven: 20000 events, Poisson(7.6) x 50 particles, 0-13k hits and 0-600 tracks/event",
@@ -620,7 +620,8 @@ def main():
     achieved_ex = ops_ex / (ms * 1e-3) / 1e12
     import hashlib
     sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    traffic = TRAFFIC["bytes_per_launch"] if TRAFFIC["kernel_sha256"] == sha else None
+    traffic = (TRAFFIC["bytes_per_launch"] if (TRAFFIC["kernel_sha256"], TRAFFIC["workload"], TRAFFIC["events"]) ==
+               (sha, args.workload, args.events) else None)
     nbytes = algorithmic_bytes(ev)
     line = {
         "metric": "events/s on 1 MI355X (plain vs batched vs serving); p50/p99 event latency",

@@ -94,7 +94,8 @@ def test_geometry_variants():
 def _jitter(ev, z_mm, slope_rel, seed):
     """Per-hit z (tilted or bowed layers) and per-hit stereo slope: the hits
     of one window no longer share a z (or a slope), so the GPU takes its
-    general paths (every pair tested, stereo windows scanned)."""
+    general paths (doublets bracketed over the third window's z range,
+    stereo windows scanned)."""
     rng = np.random.default_rng(seed)
     hz = ev.hit_z + rng.uniform(-z_mm, z_mm, ev.n_hits).astype(np.float32)
     hd = ev.hit_dxdy * (1.0 + rng.uniform(-slope_rel, slope_rel, ev.n_hits)).astype(np.float32)
@@ -177,6 +178,18 @@ def test_events_of_every_kind_in_one_batch():
     ev = lfgen.concat([nom, stress, one, jit, empty, lfgen.select_events(nom, [2])])
     for params in (None, {"n_hits_window": 64}):
         _check_all_modes(ev, "events of every kind", params)
+
+
+@pytest.mark.parametrize("layers", [(8,), (11,), (0, 3, 8, 11)], ids=["layer8", "layer11", "layers0_3_8_11"])
+def test_doublet_bracket_over_a_wide_z_range(layers):
+    """Third-layer windows (layers 8 and 11) whose hits spread over +-60 mm in
+    z: a hit's x on the track's line moves by the slope times its z offset,
+    many millimetres, far beyond the doublet bracket's 0.5 mm padding, so the
+    bracket must span the window's z range (corners of the slope and z
+    intervals); one seed set's third window mixed and the other's common,
+    and both mixed with mixed first layers."""
+    ev = _jitter_layers(lfgen.generate("nominal", n_events=5, seed=41), layers, 60.0, 0.0, seed=42)
+    _check_all_modes(ev, f"nominal[5] layers {layers} z+-60")
 
 
 @pytest.mark.parametrize("n_hits_window", [64, 48, 32])
