@@ -227,8 +227,9 @@ void lf_default_params_no_ut(lf_params *p);
  * section; tolerances of the Table of parameters and tolerances and the
  * C(n_hits) table of the Quality Filter section).  Geometry and parameters are
  * copied.  device_budget_bytes bounds the device memory of all resident
- * batches (0 = no bound).  Errors: LF_ERR_INVALID (NULL pointers, parameters
- * out of range), LF_ERR_DEVICE, LF_ERR_NOMEM. */
+ * batches together with the one freed block the context keeps for reuse
+ * (0 = no bound).  Errors: LF_ERR_INVALID (NULL pointers, parameters out of
+ * range), LF_ERR_DEVICE, LF_ERR_NOMEM. */
 int lf_create(const lf_geometry *geom, const lf_params *params, size_t device_budget_bytes,
               lf_ctx **out);
 
@@ -246,7 +247,9 @@ int lf_check_batch(const lf_batch *batch);
  * lf_fetch_tracks or lf_release_batch.  The inputs pass through a pinned host
  * buffer that the context keeps (grown to the largest batch or result set
  * seen, held until lf_destroy); the call returns once they are on the
- * device.  Errors: LF_ERR_INVALID (malformed batch; nothing is copied),
+ * device.  The batch's device block is the one the context kept from the
+ * last batch it freed when that fits (at least the size needed and at most
+ * twice it), else a new allocation.  Errors: LF_ERR_INVALID (malformed batch; nothing is copied),
  * LF_ERR_TOO_LARGE (over budget), LF_ERR_NOMEM, LF_ERR_DEVICE. */
 int lf_upload_events(lf_ctx *ctx, const lf_batch *batch, void *hip_stream, uint64_t *batch_id);
 
@@ -298,7 +301,8 @@ int lf_work_counts(lf_ctx *ctx, uint64_t batch_id, void *hip_stream, int64_t *co
  * Copies the results of a batch into caller buffers holding at least
  * cap_tracks >= number of input tracks slots (through the context's pinned
  * buffer, as in lf_upload_events), waits for completion and
- * frees the batch.  Errors: LF_ERR_STATE, LF_ERR_INVALID (NULL buffer or
+ * frees the batch (its device block is kept for reuse, as lf_release_batch
+ * describes).  Errors: LF_ERR_STATE, LF_ERR_INVALID (NULL buffer or
  * cap_tracks too small; the batch stays resident), LF_ERR_DEVICE. */
 int lf_fetch_tracks(lf_ctx *ctx, uint64_t batch_id, lf_tracks_out *out, size_t cap_tracks,
                     void *hip_stream);
@@ -313,7 +317,10 @@ int lf_copy_tracks(lf_ctx *ctx, uint64_t batch_id, lf_tracks_out *out, size_t ca
  * Errors: LF_ERR_STATE, LF_ERR_DEVICE. */
 int lf_poison_tracks(lf_ctx *ctx, uint64_t batch_id, void *hip_stream);
 
-/* Frees a resident batch without fetching it.  Errors: LF_ERR_STATE. */
+/* Frees a resident batch without fetching it, after the device has
+ * finished all queued work.  As in lf_fetch_tracks, the context keeps the
+ * batch's device block for a later upload (the block kept before is freed;
+ * lf_destroy frees it).  Errors: LF_ERR_STATE. */
 int lf_release_batch(lf_ctx *ctx, uint64_t batch_id);
 
 /* Sets the launch configuration used by later lf_find_tracks calls.
@@ -325,7 +332,8 @@ int lf_set_exec(lf_ctx *ctx, const lf_exec *exec);
 int lf_batch_info(lf_ctx *ctx, uint64_t batch_id, uint32_t *n_events, uint32_t *n_tracks,
                   uint32_t *n_hits, size_t *device_bytes);
 
-/* Device bytes held by resident batches. */
+/* Device bytes held by resident batches (the kept freed block is not
+ * counted). */
 size_t lf_device_bytes_in_use(const lf_ctx *ctx);
 
 /* Captured launch sequences (HIP graphs).  A graph records the hot path

@@ -4,10 +4,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -38,6 +42,79 @@ unsigned host_threads(size_t work) {
     return std::max(1u, std::min(hw ? hw : 1u, 16u));
 }
 
+// Host worker threads shared by every context, started on first use and kept
+// until the process ends (the object is never destroyed, so no thread is
+// joined at exit).  One parallel section runs at a time; a caller that finds
+// the workers busy runs its section alone.  The caller takes part in its own
+// section, so a section completes even with no worker at all.
+class Workers {
+public:
+    static Workers &get() {
+        static Workers *w = new Workers();
+        return *w;
+    }
+    // Runs f(k) for every k in [0, n), on the caller and the workers.
+    void run(unsigned n, const std::function<void(unsigned)> &f) {
+        std::unique_lock<std::mutex> use(use_, std::try_to_lock);
+        if (!use.owns_lock() || n < 2) {
+            for (unsigned k = 0; k < n; ++k) f(k);
+            return;
+        }
+        start(n - 1);
+        {
+            std::lock_guard<std::mutex> g(m_);
+            job_ = &f;
+            n_ = n;
+            next_.store(0);
+            ++gen_;
+        }
+        cv_.notify_all();
+        for (unsigned k; (k = next_.fetch_add(1)) < n;) f(k);
+        // every index is claimed; wait for the workers still inside the
+        // section, then close it (a worker that wakes later finds no job)
+        std::unique_lock<std::mutex> g(m_);
+        done_.wait(g, [&] { return busy_ == 0; });
+        job_ = nullptr;
+    }
+
+private:
+    void start(unsigned want) {
+        const unsigned hw = std::thread::hardware_concurrency();
+        want = std::min(want, std::min(hw > 1 ? hw - 1 : 0u, 15u));
+        while (started_ < want) {
+            try {
+                std::thread(&Workers::loop, this).detach();
+            } catch (...) {
+                return;   // no more threads to be had: the sections use fewer
+            }
+            ++started_;
+        }
+    }
+    void loop() {
+        uint64_t seen = 0;
+        std::unique_lock<std::mutex> g(m_);
+        for (;;) {
+            cv_.wait(g, [&] { return gen_ != seen; });
+            seen = gen_;
+            if (!job_) continue;   // that section has closed
+            const std::function<void(unsigned)> *job = job_;
+            const unsigned n = n_;
+            ++busy_;
+            g.unlock();
+            for (unsigned k; (k = next_.fetch_add(1)) < n;) (*job)(k);
+            g.lock();
+            if (--busy_ == 0) done_.notify_all();
+        }
+    }
+    std::mutex use_;   // held by the caller of the running section
+    std::mutex m_;
+    std::condition_variable cv_, done_;
+    const std::function<void(unsigned)> *job_ = nullptr;
+    unsigned n_ = 0, busy_ = 0, started_ = 0;
+    uint64_t gen_ = 0;
+    std::atomic<unsigned> next_{0};
+};
+
 // Runs f(k) for k in [0, n) over contiguous slices on up to host_threads(work)
 // threads; f returns false at a failure.  Returns the least failing k (n if
 // none), the same index a serial scan would stop at.
@@ -45,18 +122,10 @@ template <class F>
 size_t first_failure(size_t n, size_t work, F f) {
     const unsigned nt = n < 2 ? 1u : std::min<unsigned>(host_threads(work), (unsigned)std::min<size_t>(n, 64));
     std::vector<size_t> first(nt, n);
-    auto slice = [&](unsigned k) {
+    Workers::get().run(nt, [&](unsigned k) {
         for (size_t i = n * k / nt, e = n * (k + 1) / nt; i < e; ++i)
             if (!f(i)) { first[k] = i; return; }
-    };
-    std::vector<std::thread> th;
-    try {
-        for (unsigned k = 1; k < nt; ++k) th.emplace_back(slice, k);
-    } catch (...) {   // no threads to be had: the rest serially
-        for (unsigned k = (unsigned)th.size() + 1; k < nt; ++k) slice(k);
-    }
-    slice(0);
-    for (auto &t : th) t.join();
+    });
     return *std::min_element(first.begin(), first.end());
 }
 
@@ -94,6 +163,10 @@ struct lf_ctx {
     // pinned host staging of uploads and downloads (grown on demand, kept)
     char *pin = nullptr;
     size_t pin_cap = 0;
+    // the device block of the last batch freed, kept for the next upload
+    // that fits it (not counted in `used`)
+    void *spare = nullptr;
+    size_t spare_bytes = 0;
 };
 
 namespace {
@@ -122,6 +195,38 @@ char *staging(lf_ctx *c, size_t bytes) {
     c->pin = static_cast<char *>(p);
     c->pin_cap = bytes;
     return c->pin;
+}
+
+// A batch's device block, at least `need` bytes: the spare block when it fits
+// (and is not more than twice the need), else a new allocation, the spare
+// being freed first when it does not fit or when holding it would take the
+// context past its budget.  *got: the block's size.
+hipError_t take_block(lf_ctx *c, size_t need, void **p, size_t *got) {
+    if (c->spare && c->spare_bytes >= need && c->spare_bytes / 2 <= need &&
+        (!c->budget || c->used + c->spare_bytes <= c->budget)) {
+        *p = c->spare;
+        *got = c->spare_bytes;
+        c->spare = nullptr;
+        c->spare_bytes = 0;
+        return hipSuccess;
+    }
+    if (c->spare) {
+        (void)hipFree(c->spare);
+        c->spare = nullptr;
+        c->spare_bytes = 0;
+    }
+    *got = need;
+    return hipMalloc(p, need);
+}
+
+// Frees a batch's block: kept as the spare (the previous spare is freed).
+// The device is synchronised first, as a free would be, so that no queued
+// work on any stream still uses the block when an upload reuses it.
+void drop_block(lf_ctx *c, void *p, size_t bytes) {
+    (void)hipDeviceSynchronize();
+    if (c->spare) (void)hipFree(c->spare);
+    c->spare = p;
+    c->spare_bytes = bytes;
 }
 
 bool finitef(float v) { return std::isfinite(v); }
@@ -196,16 +301,46 @@ int validate(const lf_batch *b, std::string &why) {
     if (H && (!b->hit_x || !b->hit_z || !b->hit_dxdy)) { why = "batch: NULL hit array"; return 0; }
     if (T && (!b->trk_x || !b->trk_y || !b->trk_tx || !b->trk_ty || !b->trk_qop)) { why = "batch: NULL track array"; return 0; }
     // the scans below run over slices on several host threads; each reports
-    // the first failure a serial scan would
-    const size_t bad_hit = first_failure(H, 12 * H, [&](size_t i) {
-        return finitef(b->hit_x[i]) && finitef(b->hit_z[i]) && finitef(b->hit_dxdy[i]);
+    // the first failure a serial scan would.  Hits and buckets in one pass
+    // over slices of buckets holding about equal numbers of hits: the first
+    // non-finite hit of each slice (where the slice stops: that report wins),
+    // and the first bucket before it not sorted by x.
+    const unsigned ns = H < 2 ? 1u : std::min<unsigned>(host_threads(12 * H), 64u);
+    std::vector<size_t> bad_h(ns, H), bad_b(ns, nb);
+    auto bucket_at = [&](unsigned k) -> size_t {
+        if (k == 0) return 0;
+        if (k == ns) return nb;
+        const uint64_t target = H * (uint64_t)k / ns;
+        return (size_t)(std::lower_bound(b->hit_off, b->hit_off + nb + 1, (uint32_t)target) - b->hit_off);
+    };
+    // a bucket is first tested whole, branch-free (the loops vectorise); only
+    // a failing bucket is scanned hit by hit for where it fails
+    auto bits = [](const float *v, uint32_t i) { uint32_t u; std::memcpy(&u, v + i, 4); return u; };
+    auto bucket_ok = [&](uint32_t i0, uint32_t i1) {
+        uint32_t bad = 0;
+        for (uint32_t i = i0; i < i1; ++i)
+            bad |= (uint32_t)((bits(b->hit_x, i) & 0x7f800000u) == 0x7f800000u) |
+                   (uint32_t)((bits(b->hit_z, i) & 0x7f800000u) == 0x7f800000u) |
+                   (uint32_t)((bits(b->hit_dxdy, i) & 0x7f800000u) == 0x7f800000u);
+        for (uint32_t i = i0 + 1; i < i1; ++i) bad |= (uint32_t)(b->hit_x[i] < b->hit_x[i - 1]);
+        return bad == 0;
+    };
+    Workers::get().run(ns, [&](unsigned k) {
+        for (size_t q = bucket_at(k), qe = bucket_at(k + 1); q < qe; ++q) {
+            const uint32_t i0 = b->hit_off[q], i1 = b->hit_off[q + 1];
+            if (bucket_ok(i0, i1)) continue;
+            for (uint32_t i = i0; i < i1; ++i) {
+                if (!(finitef(b->hit_x[i]) && finitef(b->hit_z[i]) && finitef(b->hit_dxdy[i]))) {
+                    bad_h[k] = i;
+                    return;
+                }
+                if (i > i0 && b->hit_x[i] < b->hit_x[i - 1] && bad_b[k] == nb) bad_b[k] = q;
+            }
+        }
     });
+    const size_t bad_hit = *std::min_element(bad_h.begin(), bad_h.end());
     if (bad_hit < H) { why = "batch: non-finite hit " + std::to_string(bad_hit); return 0; }
-    const size_t bad_bucket = first_failure(nb, 4 * H, [&](size_t k) {
-        for (uint32_t i = b->hit_off[k] + 1; i < b->hit_off[k + 1]; ++i)
-            if (b->hit_x[i] < b->hit_x[i - 1]) return false;
-        return true;
-    });
+    const size_t bad_bucket = *std::min_element(bad_b.begin(), bad_b.end());
     if (bad_bucket < nb) { why = "batch: bucket " + std::to_string(bad_bucket) + " not sorted by x"; return 0; }
     const size_t bad_track = first_failure(T, 20 * T, [&](size_t t) {
         return finitef(b->trk_x[t]) && finitef(b->trk_y[t]) && finitef(b->trk_tx[t]) && finitef(b->trk_ty[t]) &&
@@ -405,7 +540,6 @@ int lf_upload_events(lf_ctx *c, const lf_batch *b, void *hip_stream, uint64_t *b
         return fail(c, LF_ERR_TOO_LARGE, "lf_upload_events: batch needs " + std::to_string(L.total) +
                                              " device bytes, " + std::to_string(c->budget - c->used) + " left");
     Batch bt;
-    bt.bytes = L.total;
     bt.n_events = E; bt.n_tracks = T; bt.n_hits = H;
     bt.out_off = L.found;
     bt.out_bytes = L.counter - L.found;
@@ -414,7 +548,7 @@ int lf_upload_events(lf_ctx *c, const lf_batch *b, void *hip_stream, uint64_t *b
     } catch (...) {
         return fail(c, LF_ERR_NOMEM, "lf_upload_events: out of host memory");
     }
-    hipError_t e = hipMalloc(&bt.dmem, L.total);
+    hipError_t e = take_block(c, L.total, &bt.dmem, &bt.bytes);
     if (e != hipSuccess) return fail(c, LF_ERR_NOMEM, std::string("lf_upload_events: hipMalloc: ") + hipGetErrorString(e));
     char *base = static_cast<char *>(bt.dmem);
     lfk::DevBatch &d = bt.dev;
@@ -451,15 +585,21 @@ int lf_upload_events(lf_ctx *c, const lf_batch *b, void *hip_stream, uint64_t *b
         {L.trk_off, b->trk_off, ((size_t)E + 1) * 4}, {L.tx, b->trk_x, (size_t)T * 4},
         {L.ty, b->trk_y, (size_t)T * 4}, {L.ttx, b->trk_tx, (size_t)T * 4},
         {L.tty, b->trk_ty, (size_t)T * 4}, {L.tqop, b->trk_qop, (size_t)T * 4}};
-    // the inputs are one run [0, L.uni) of the allocation: staged in pinned
-    // memory by several host threads, then one copy over the host link
+    // the inputs are one run [0, L.uni) of the allocation, staged in pinned
+    // memory by several host threads in four parts (offsets and x, z, dxdy,
+    // the tracks), each sent over the host link while the next is staged
     char *pin = staging(c, L.uni);
     if (pin) {
-        std::vector<Piece> pcs;
-        for (auto &x : cp)
-            if (x.n) pcs.push_back({pin + x.off, x.src, x.n});
-        copy_pieces(pcs);
-        e = hipMemcpyAsync(base, pin, L.uni, hipMemcpyHostToDevice, s);
+        const size_t part_end[4] = {L.hz, L.hd, L.trk_off, L.uni};
+        size_t from = 0;
+        for (size_t p = 0; p < 4 && e == hipSuccess; ++p) {
+            std::vector<Piece> pcs;
+            for (auto &x : cp)
+                if (x.n && x.off >= from && x.off < part_end[p]) pcs.push_back({pin + x.off, x.src, x.n});
+            copy_pieces(pcs);
+            e = hipMemcpyAsync(base + from, pin + from, part_end[p] - from, hipMemcpyHostToDevice, s);
+            from = part_end[p];
+        }
     } else {
         for (auto &x : cp) {
             if (!x.n) continue;
@@ -683,7 +823,7 @@ int copy_tracks(lf_ctx *c, uint64_t batch_id, lf_tracks_out *out, size_t cap_tra
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "lf_fetch_tracks");
     if (release) {
-        (void)hipFree(bt.dmem);
+        drop_block(c, bt.dmem, bt.bytes);
         c->used -= bt.bytes;
         c->batches.erase(it);
     }
@@ -714,7 +854,7 @@ int lf_release_batch(lf_ctx *c, uint64_t batch_id) {
     if (it == c->batches.end()) return fail(c, LF_ERR_STATE, "lf_release_batch: unknown batch id");
     // work on the batch may still be queued on any stream: wait for the device
     const hipError_t e = hipDeviceSynchronize();
-    (void)hipFree(it->second.dmem);
+    drop_block(c, it->second.dmem, it->second.bytes);
     c->used -= it->second.bytes;
     c->batches.erase(it);
     if (e != hipSuccess) return hip_fail(c, e, "lf_release_batch");
@@ -740,6 +880,7 @@ void lf_destroy(lf_ctx *c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     (void)hipDeviceSynchronize();
     for (auto &kv : c->batches) (void)hipFree(kv.second.dmem);
+    if (c->spare) (void)hipFree(c->spare);
     if (c->d_params) (void)hipFree(c->d_params);
     if (c->pin) (void)hipHostFree(c->pin);
     if (c->stream) (void)hipStreamDestroy(c->stream);

@@ -323,12 +323,18 @@ def lf_work_counts(ctx, batch_id: int, stream=None) -> dict:
 
 def lf_fetch_tracks(ctx, batch_id: int, n_tracks: int | None = None, stream=None, release: bool = True) -> dict:
     """Results of a batch; the batch is freed unless release is False (lf_copy_tracks)."""
-    if n_tracks is None:
-        n_tracks = lf_batch_info(ctx, batch_id)["n_tracks"]
-    T = int(n_tracks)
-    out = dict(found=np.zeros(T, np.uint8), n_hits=np.zeros(T, np.uint8), hit_idx=np.full((T, NL), -1, np.int32))
-    for k in ("a", "b", "c", "y0", "ty", "qop", "Q"):
-        out[k] = np.zeros(T, np.float32)
+    nb = lf_batch_info(ctx, batch_id)["n_tracks"]
+    T = nb if n_tracks is None else int(n_tracks)
+    # the call fills every slot of the batch's tracks (or fails, and the
+    # arrays are dropped); slots past the batch's count keep defaults
+    if T == nb:
+        out = dict(found=np.empty(T, np.uint8), n_hits=np.empty(T, np.uint8), hit_idx=np.empty((T, NL), np.int32))
+        for k in ("a", "b", "c", "y0", "ty", "qop", "Q"):
+            out[k] = np.empty(T, np.float32)
+    else:
+        out = dict(found=np.zeros(T, np.uint8), n_hits=np.zeros(T, np.uint8), hit_idx=np.full((T, NL), -1, np.int32))
+        for k in ("a", "b", "c", "y0", "ty", "qop", "Q"):
+            out[k] = np.zeros(T, np.float32)
     o = lf_tracks_out(*[out[k].ctypes.data for k in ("found", "n_hits", "hit_idx", "a", "b", "c", "y0", "ty",
                                                       "qop", "Q")])
     fn = lib().lf_fetch_tracks if release else lib().lf_copy_tracks

@@ -132,6 +132,14 @@ def test_check_batch_reports_the_first_failure_of_a_large_batch(lf):
         buckets.append(k)
     with pytest.raises(lf.LFError, match=f"bucket {min(buckets)} not sorted by x$"):
         lf.lf_check_batch(_mutated(ev, hit_x=x))
+    # a bucket out of order ahead of non-finite z and dxdy further on: every
+    # hit is checked for finite values before any bucket's order
+    z = ev.hit_z.copy(); z[H - 5] = np.inf
+    with pytest.raises(lf.LFError, match=f"non-finite hit {H - 5}$"):
+        lf.lf_check_batch(_mutated(ev, hit_x=x, hit_z=z))
+    d = ev.hit_dxdy.copy(); d[H // 3] = -np.inf
+    with pytest.raises(lf.LFError, match=f"non-finite hit {H // 3}$"):
+        lf.lf_check_batch(_mutated(ev, hit_x=x, hit_z=z, hit_dxdy=d))
     q = ev.trk_qop.copy(); q[T // 9] = 0.0
     t = ev.trk_ty.copy(); t[T - 3] = np.inf
     with pytest.raises(lf.LFError, match=f"q/p == 0 for track {T // 9}$"):

@@ -343,6 +343,37 @@ def test_determinism_and_event_order():
             assert np.array_equal(a[k][r0:r1], c[k][s0:s0 + r1 - r0]), k
 
 
+def test_a_freed_batch_block_is_reused():
+    """The device block of a fetched or released batch serves the next upload
+    that fits it (at least its size, at most twice it): the results are those
+    of a fresh block, every old content overwritten or unused.  An upload
+    that does not fit gets a new block."""
+    from paper_2402_14670_amd import lf
+    big = lfgen.generate("nominal", n_events=20, seed=51)
+    mid = lfgen.generate("nominal", n_events=14, seed=52)
+    small = lfgen.generate("nominal", n_events=2, seed=53)
+    ctx = lf.lf_create(W)
+    try:
+        say("[gpu] block reuse: nominal[20], then nominal[14] in its block, then nominal[2] in a new one")
+        bid = lf.lf_upload_events(ctx, big)
+        size_big = lf.lf_batch_info(ctx, bid)["device_bytes"]
+        lf.lf_find_tracks(ctx, bid, "batched")
+        compare(oracle.run(big, W), lf.lf_fetch_tracks(ctx, bid), label="first block")
+        sizes = []
+        for ev, mode in ((mid, "batched"), (small, "persistent"), (small, "plain")):
+            bid = lf.lf_upload_events(ctx, ev)
+            sizes.append(lf.lf_batch_info(ctx, bid)["device_bytes"])
+            lf.lf_find_tracks(ctx, bid, mode)
+            compare(oracle.run(ev, W), lf.lf_copy_tracks(ctx, bid), label=f"{ev.n_events} events, {mode}")
+            lf.lf_release_batch(ctx, bid)
+            assert lf.lf_device_bytes_in_use(ctx) == 0
+        # nominal[14] in the block of nominal[20]; nominal[2] (under half of
+        # it) in a new block, which the second nominal[2] reuses
+        assert sizes[0] == size_big and sizes[1] < size_big // 2 and sizes[2] == sizes[1]
+    finally:
+        lf.lf_destroy(ctx)
+
+
 def test_torch_stream():
     import torch
     ev = lfgen.generate("nominal", n_events=4)
