@@ -79,6 +79,40 @@ def _mutated(ev, **kw):
     return lfgen.Events(**d)
 
 
+def test_check_batch_from_several_threads_at_once(lf):
+    """The host worker threads are shared by every caller: batches validated
+    from several threads at once (one caller's section on the workers, the
+    others on their own thread) each get their own first failure."""
+    import threading
+    ev = lfgen.generate("nominal", n_events=120)
+    H = ev.n_hits
+    cases = []
+    for k in range(8):
+        x = ev.hit_x.copy()
+        at = H // 3 + 9973 * k
+        x[at] = np.nan
+        cases.append((_mutated(ev, hit_x=x), f"non-finite hit {at}$"))
+    cases.append((ev, None))
+    errors = []
+
+    def work(batch, expect):
+        for _ in range(5):
+            try:
+                lf.lf_check_batch(batch)
+                if expect is not None:
+                    errors.append(f"accepted a batch that should fail with {expect!r}")
+            except lf.LFError as e:
+                if expect is None or not re.search(expect, str(e)):
+                    errors.append(f"{e} (expected {expect!r})")
+
+    threads = [threading.Thread(target=work, args=c) for c in cases]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors[:4]
+
+
 @pytest.mark.parametrize("case", ["nan_hit", "inf_track", "qop_zero", "unsorted", "offset_decrease",
                                   "offset_start"])
 def test_check_batch_rejects_malformed(lf, case):
