@@ -70,8 +70,8 @@ BYTES_PER_TRACK_OUT = 78
 # HBM traffic of the batched kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (per launch, scaled by the counters' reading of a known-size copy), valid
 # only for the kernel source and the workload it was measured on.
-TRAFFIC = {"kernel_sha256": "23551861fd187e3fcb61e3e77c9759c10aafb0874e4e1533755d4b22d1692791",
-           "workload": "nominal", "events": 0, "bytes_per_launch": 51958319}
+TRAFFIC = {"kernel_sha256": "985bb2886f02f49228c45613d199e605f3c3a98cd426572fa0fcbc2bdcc8e45b",
+           "workload": "nominal", "events": 0, "bytes_per_launch": 51952280}
 WORKLOADS = {
     "nominal": "nominal: 1000 events x 200 input tracks, ~5.4k SciFi hits/event, toy kick field",
     "uneven": "uneven: 20000 events, Poisson(7.6) x 50 particles, 0-13k hits and 0-600 tracks/event",

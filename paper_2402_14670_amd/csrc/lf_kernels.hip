@@ -902,6 +902,8 @@ struct Track {
                 }
             }
         }
+        const float mag_z = P->z_mag, mag_txs = P->magtol_txscale, mag_min = P->magtol_min,
+                    mag_max = P->magtol_max;
         for (int base = 0; base < items_total; base += WAVE) {
             const int item = base + lane;
             const int grp = item < c1 ? 0 : (item < c2 ? 1 : (item < c3 ? 2 : 3));
@@ -998,14 +1000,15 @@ struct Track {
             }
             auto more = [&](int k) { return NS == 2 ? k < span : __ballot(k < span) != 0; };
             // the binary32 filter of pair (i0, i2)
+            const float dzm = mag_z - z0;
             auto test32 = [&](int i2) {
                 const float x2 = L.wx[sd][l2][i2], z2 = zat(sd, l2, i2);
                 const float txd = (x2 - x0) / (z2 - z0);
                 bool pass = !(low_p && !((txd - tx_in) * qop > 0.0f));
-                const float xm = x0 + txd * (P->z_mag - z0);
-                float tol = tolc + P->magtol_txscale * fabsf(txd);
-                if (tol < P->magtol_min) tol = P->magtol_min;
-                if (tol > P->magtol_max) tol = P->magtol_max;
+                const float xm = x0 + txd * dzm;
+                float tol = tolc + mag_txs * fabsf(txd);
+                if (tol < mag_min) tol = mag_min;
+                if (tol > mag_max) tol = mag_max;
                 if (!(fabsf(xm - x_mag) < tol)) pass = false;
                 return pass;
             };
@@ -1037,7 +1040,12 @@ struct Track {
                 for (int k = 0; more(k); ++k) {
                     const int i2 = jlo + k;
                     const bool tested = i2 < jhi;
-                    push(tested && test32(i2), tested, i2);
+                    // every lane evaluates the filter, without a branch (a
+                    // divergent one issues the same instructions and adds the
+                    // exec-mask bookkeeping); a lane without a pair reads its
+                    // window's slot 0 and drops the result
+                    const bool pass = test32(tested ? i2 : 0);
+                    push(tested && pass, tested, i2);
                 }
             } else {
                 // two pairs (i2, i2 + 1) per step: one packed binary16
