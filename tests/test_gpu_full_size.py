@@ -1,5 +1,6 @@
 """Every output slot of the full uneven (20,000 events) and stress (5,000
-events) workloads, in the launch configurations the benchmark times, against
+events) workloads, and of the nominal batch on the general path (per-hit z
+and slopes), in the launch configurations the benchmark times, against
 the oracle run over the whole batch on the host's threads.  The stress batch
 is the one that drives the exact top-n selection hardest (hundreds of
 triplets per input track); the uneven batch is also run as four resident
@@ -52,6 +53,24 @@ def test_full_stress_batch_every_slot():
     ref = oracle_parallel(ev)
     say(f"[gpu] stress[{ev.n_events}] mode=batched")
     st = compare(ref, run_gpu(ev, "batched"), label=f"stress[{ev.n_events}]/batched")
+    say(f"    found={st['found']} bit-exact params {st['bit_exact_params']}/{st['params']}")
+
+
+def test_full_nominal_general_path_every_slot():
+    """The general path at the size it is timed at: the whole nominal batch
+    with every hit's z jittered by +-1.5 mm and every stereo slope by +-2%
+    (uniform, seed 11, the benchmark's recipe), so that no window shares one
+    z or one slope; every slot against the oracle, with one wavefront per
+    block as the benchmark's autotuner picks."""
+    ev = lfgen.generate("nominal")
+    rng = np.random.default_rng(11)
+    hz = (ev.hit_z + rng.uniform(-1.5, 1.5, ev.n_hits)).astype(np.float32)
+    hd = (ev.hit_dxdy * (1.0 + rng.uniform(-0.02, 0.02, ev.n_hits))).astype(np.float32)
+    gev = lfgen.Events(**{**ev.__dict__, "hit_z": hz, "hit_dxdy": hd})
+    say(f"[gpu] nominal[{gev.n_events}] per-hit z and slopes: oracle on the host")
+    ref = oracle_parallel(gev)
+    say(f"[gpu] nominal[{gev.n_events}] per-hit z and slopes, mode=batched, one wavefront per block")
+    st = compare(ref, run_gpu(gev, "batched", exec_cfg={"waves_per_block": 1}), label="general path, full nominal")
     say(f"    found={st['found']} bit-exact params {st['bit_exact_params']}/{st['params']}")
 
 
