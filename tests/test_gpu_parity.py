@@ -374,6 +374,48 @@ def test_a_freed_batch_block_is_reused():
         lf.lf_destroy(ctx)
 
 
+def test_kept_block_within_the_device_budget():
+    """Under a device budget: a kept block that does not fit the next upload
+    is freed before the new allocation, two batches that fit the budget
+    together stay resident, the kept block of one of them is reused, and an
+    upload over the budget fails with LF_ERR_TOO_LARGE, leaving the resident
+    batches as they were."""
+    from paper_2402_14670_amd import lf
+    big = lfgen.generate("nominal", n_events=20, seed=61)
+    small = lfgen.generate("nominal", n_events=2, seed=63)
+    probe = lf.lf_create(W)
+    try:
+        size_big = lf.lf_batch_info(probe, lf.lf_upload_events(probe, big))["device_bytes"]
+        size_small = lf.lf_batch_info(probe, lf.lf_upload_events(probe, small))["device_bytes"]
+    finally:
+        lf.lf_destroy(probe)
+    assert size_small < size_big // 2
+    ref_big, ref_small = oracle.run(big, W), oracle.run(small, W)
+    ctx = lf.lf_create(W, None, size_big + size_small + size_big // 20)
+    try:
+        say("[gpu] kept block under a budget of both batches plus 5%")
+        bid = lf.lf_upload_events(ctx, big)
+        lf.lf_find_tracks(ctx, bid, "batched")
+        compare(ref_big, lf.lf_fetch_tracks(ctx, bid), label="budget: big")
+        bs = lf.lf_upload_events(ctx, small)                  # the kept block is too large: freed
+        assert lf.lf_batch_info(ctx, bs)["device_bytes"] == size_small
+        bb = lf.lf_upload_events(ctx, big)                    # fits beside the small batch
+        assert lf.lf_device_bytes_in_use(ctx) == size_small + size_big
+        lf.lf_release_batch(ctx, bb)                          # kept
+        bb = lf.lf_upload_events(ctx, big)                    # the kept block, reused
+        assert lf.lf_batch_info(ctx, bb)["device_bytes"] == size_big
+        with pytest.raises(lf.LFError) as e:
+            lf.lf_upload_events(ctx, small)                   # over the budget
+        assert e.value.code == lf.LF_ERR_TOO_LARGE
+        assert lf.lf_device_bytes_in_use(ctx) == size_small + size_big
+        for b_, ref, mode in ((bs, ref_small, "persistent"), (bb, ref_big, "batched")):
+            lf.lf_find_tracks(ctx, b_, mode)
+            compare(ref, lf.lf_fetch_tracks(ctx, b_), label=f"budget: {mode}")
+        assert lf.lf_device_bytes_in_use(ctx) == 0
+    finally:
+        lf.lf_destroy(ctx)
+
+
 def test_torch_stream():
     import torch
     ev = lfgen.generate("nominal", n_events=4)
